@@ -1,0 +1,528 @@
+/*
+ * FP64 CPU oracle for multi-scale demons deformable image registration
+ * (Gu et al., "Implementation and evaluation of various demons deformable
+ * image registration algorithms on GPU").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * statement of what the registration computes.  It is called by the tests,
+ * by the package smoke check and by the benchmark's CPU-baseline leg, never
+ * by the product path, and it shares no code, header or table with the HIP
+ * library.  Every step follows the paper in the paper's order; where the
+ * paper is silent or garbled the reading taken is stated at the function.
+ *
+ * Conventions (the same ones the HIP library documents independently):
+ *   - volumes are [nz][ny][nx] doubles, x fastest: index x + nx*(y + ny*z);
+ *   - a displacement field is three such planes (x, y, z components) in
+ *     voxel units, one after the other;
+ *   - the field v registers M onto S when M(x - v(x)) = S(x); the paper's
+ *     increment dr is added to v (Sec 2.1, Eq 1);
+ *   - index and coordinate clamping at the volume border.
+ *
+ * Reductions are plain serial loops in voxel order so results do not depend
+ * on the thread count; element-wise loops may run under OpenMP.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PASSIVE 0
+#define ORC_EVOLVED 1
+#define ORC_ACTIVE 2
+#define ORC_DOUBLE 3
+#define ORC_INVERSE_CONSISTENT 4
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_ENUMERIC (-4)
+
+#define ORC_MAX_LEVELS 8
+#define ORC_MAX_RADIUS 16
+#define ORC_DENOM_FLOOR 1e-9
+
+static int64_t clampi(int64_t i, int64_t n) { return i < 0 ? 0 : (i > n - 1 ? n - 1 : i); }
+
+static int64_t at(int64_t x, int64_t y, int64_t z, int64_t nx, int64_t ny) { return x + nx * (y + ny * z); }
+
+int orc_version(void) { return 1; }
+
+/* ------------------------------------------------------------------------
+ * Trilinear interpolation (Sec 2.5, interpolation kernel).  The paper uses
+ * its own full-precision trilinear code rather than hardware filtering.  The
+ * paper is silent on samples outside the grid: each coordinate is clamped to
+ * [0, n-1] (edge replication).  The cell is i0 = min(floor(p), n-2) with
+ * t = p - i0, so the last grid point is reached with t = 1; an axis of
+ * length 1 contributes its single value.
+ * ------------------------------------------------------------------------ */
+static void axis_cell(double p, int64_t n, int64_t *i0, int64_t *i1, double *t)
+{
+    if (n == 1) { *i0 = 0; *i1 = 0; *t = 0.0; return; }
+    if (!(p > 0.0)) p = 0.0;                 /* also maps NaN to 0 */
+    if (p > (double)(n - 1)) p = (double)(n - 1);
+    int64_t i = (int64_t)floor(p);
+    if (i > n - 2) i = n - 2;
+    *i0 = i;
+    *i1 = i + 1;
+    *t = p - (double)i;
+}
+
+double orc_trilerp(const double *I, int64_t nx, int64_t ny, int64_t nz, double px, double py, double pz)
+{
+    int64_t x0, x1, y0, y1, z0, z1;
+    double tx, ty, tz;
+    axis_cell(px, nx, &x0, &x1, &tx);
+    axis_cell(py, ny, &y0, &y1, &ty);
+    axis_cell(pz, nz, &z0, &z1, &tz);
+    double s = 0.0;
+    s += (1 - tx) * (1 - ty) * (1 - tz) * I[at(x0, y0, z0, nx, ny)];
+    s += tx * (1 - ty) * (1 - tz) * I[at(x1, y0, z0, nx, ny)];
+    s += (1 - tx) * ty * (1 - tz) * I[at(x0, y1, z0, nx, ny)];
+    s += tx * ty * (1 - tz) * I[at(x1, y1, z0, nx, ny)];
+    s += (1 - tx) * (1 - ty) * tz * I[at(x0, y0, z1, nx, ny)];
+    s += tx * (1 - ty) * tz * I[at(x1, y0, z1, nx, ny)];
+    s += (1 - tx) * ty * tz * I[at(x0, y1, z1, nx, ny)];
+    s += tx * ty * tz * I[at(x1, y1, z1, nx, ny)];
+    return s;
+}
+
+/* Deformed image (Sec 2.1 and Sec 2.5): out(x) = I(x - sign * v(x)).
+ * sign = +1 deforms the moving image by the field; sign = -1 applies the
+ * first-order inverse x + v, used for the static image of the
+ * inverse-consistent variant (Sec 2.2, text after Eq 6). */
+void orc_warp(const double *I, const double *v, int64_t nx, int64_t ny, int64_t nz, double sign, double *out)
+{
+    const int64_t N = nx * ny * nz;
+    const double *vx = v, *vy = v + N, *vz = v + 2 * N;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t i = at(x, y, z, nx, ny);
+                out[i] = orc_trilerp(I, nx, ny, nz, (double)x - sign * vx[i], (double)y - sign * vy[i],
+                                     (double)z - sign * vz[i]);
+            }
+}
+
+/* Image gradient (Sec 2.5, gradient kernel): the separable gradient mask is
+ * read as the central difference (I[i+1] - I[i-1]) / 2 per axis in voxel
+ * units, neighbour indices clamped.  Output: three planes (d/dx, d/dy, d/dz). */
+void orc_gradient(const double *I, int64_t nx, int64_t ny, int64_t nz, double *g)
+{
+    const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t i = at(x, y, z, nx, ny);
+                g[i] = 0.5 * (I[at(clampi(x + 1, nx), y, z, nx, ny)] - I[at(clampi(x - 1, nx), y, z, nx, ny)]);
+                g[N + i] = 0.5 * (I[at(x, clampi(y + 1, ny), z, nx, ny)] - I[at(x, clampi(y - 1, ny), z, nx, ny)]);
+                g[2 * N + i] = 0.5 * (I[at(x, y, clampi(z + 1, nz), nx, ny)] - I[at(x, y, clampi(z - 1, nz), nx, ny)]);
+            }
+}
+
+/* Gaussian low-pass filter weights (Sec 2.5, low-pass filter kernel): the
+ * sampled Gaussian exp(-j^2 / (2 sigma^2)) for j in [-R, R], normalised to
+ * unit sum.  w has 2R+1 entries, w[j + R] for offset j. */
+void orc_gauss_weights(double sigma, int radius, double *w)
+{
+    double sum = 0.0;
+    for (int j = -radius; j <= radius; ++j) {
+        w[j + radius] = exp(-(double)(j * j) / (2.0 * sigma * sigma));
+        sum += w[j + radius];
+    }
+    for (int j = 0; j <= 2 * radius; ++j) w[j] /= sum;
+}
+
+/* One 1D correlation pass along `axis` (0 = x, 1 = y, 2 = z) with clamped
+ * indices. */
+static void smooth_pass(const double *in, int64_t nx, int64_t ny, int64_t nz, int axis, const double *w, int radius,
+                        double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                double s = 0.0;
+                for (int j = -radius; j <= radius; ++j) {
+                    int64_t k;
+                    if (axis == 0) k = at(clampi(x + j, nx), y, z, nx, ny);
+                    else if (axis == 1) k = at(x, clampi(y + j, ny), z, nx, ny);
+                    else k = at(x, y, clampi(z + j, nz), nx, ny);
+                    s += w[j + radius] * in[k];
+                }
+                out[at(x, y, z, nx, ny)] = s;
+            }
+}
+
+/* Gaussian smoothing of `ncomp` planes (Sec 2.1 regularisation, Sec 2.5
+ * separable convolution): x pass, then y, then z, clamped borders.
+ * Returns ORC_EINVAL on bad sigma/radius, ORC_ENOMEM on allocation failure. */
+int orc_smooth(const double *in, int ncomp, int64_t nx, int64_t ny, int64_t nz, double sigma, int radius, double *out)
+{
+    if (!(sigma > 0.0) || radius < 0 || radius > ORC_MAX_RADIUS) return ORC_EINVAL;
+    double w[2 * ORC_MAX_RADIUS + 1];
+    orc_gauss_weights(sigma, radius, w);
+    const int64_t N = nx * ny * nz;
+    double *t1 = (double *)malloc(sizeof(double) * N);
+    double *t2 = (double *)malloc(sizeof(double) * N);
+    if (!t1 || !t2) { free(t1); free(t2); return ORC_ENOMEM; }
+    for (int c = 0; c < ncomp; ++c) {
+        smooth_pass(in + c * N, nx, ny, nz, 0, w, radius, t1);
+        smooth_pass(t1, nx, ny, nz, 1, w, radius, t2);
+        smooth_pass(t2, nx, ny, nz, 2, w, radius, out + c * N);
+    }
+    free(t1);
+    free(t2);
+    return ORC_OK;
+}
+
+/* Coarse grid size for one down-sampling by 2 (Sec 2.3). */
+static int64_t coarse_len(int64_t n) { return (n + 1) / 2; }
+
+/* Down-sampling by a factor of 2 per dimension (Sec 2.3).  The paper gives
+ * only the factor; the filter read here is the 2x2x2 box mean, children
+ * clamped to the grid, coarse size ceil(n/2). */
+void orc_restrict(const double *in, int64_t nx, int64_t ny, int64_t nz, double *out)
+{
+    const int64_t cx = coarse_len(nx), cy = coarse_len(ny), cz = coarse_len(nz);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < cz; ++k)
+        for (int64_t j = 0; j < cy; ++j)
+            for (int64_t i = 0; i < cx; ++i) {
+                double s = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a)
+                            s += in[at(clampi(2 * i + a, nx), clampi(2 * j + b, ny), clampi(2 * k + c, nz), nx, ny)];
+                out[at(i, j, k, cx, cy)] = s / 8.0;
+            }
+}
+
+/* Up-sampling of the displacement field to the next finer level (Sec 2.3):
+ * cell-centred trilinear interpolation (fine index f sits at coarse
+ * coordinate (f - 0.5) / 2), then values multiplied by 2 because one coarse
+ * voxel of motion is two fine voxels. */
+void orc_prolong(const double *vc, int64_t cx, int64_t cy, int64_t cz, double *vf, int64_t fx, int64_t fy, int64_t fz)
+{
+    const int64_t Nc = cx * cy * cz, Nf = fx * fy * fz;
+    for (int c = 0; c < 3; ++c) {
+#pragma omp parallel for schedule(static)
+        for (int64_t z = 0; z < fz; ++z)
+            for (int64_t y = 0; y < fy; ++y)
+                for (int64_t x = 0; x < fx; ++x)
+                    vf[c * Nf + at(x, y, z, fx, fy)] =
+                        2.0 * orc_trilerp(vc + c * Nc, cx, cy, cz, (x - 0.5) / 2.0, (y - 0.5) / 2.0, (z - 0.5) / 2.0);
+    }
+}
+
+/* Demons force term of Eq 1 / Eq 3, with Pennec's normalisation factor alpha
+ * on the squared intensity difference (Sec 2.2, Eq 5):
+ *   f = D g / (alpha^2 D^2 + |g|^2).
+ * The paper is silent on a vanishing denominator; the force is 0 there
+ * (denominator <= 1e-9, in intensity^2 units). */
+static void force_term(double D, double gx, double gy, double gz, double alpha, double *fx, double *fy, double *fz)
+{
+    double den = alpha * alpha * D * D + (gx * gx + gy * gy + gz * gz);
+    if (den <= ORC_DENOM_FLOOR) { *fx = *fy = *fz = 0.0; return; }
+    *fx = D * gx / den;
+    *fy = D * gy / den;
+    *fz = D * gz / den;
+}
+
+/* Evolved passive force, Eq 2, read with both gradient magnitudes squared in
+ * the second denominator factor (the printed one mixes |grad Is|^2 with
+ * |grad Im0|, which is not invariant to intensity scaling) and with a = the
+ * gradient magnitude of the level's undeformed moving image at x:
+ *   e = 4 D G |G| a / ((2 D^2 + |G|^2 + a^2) (|G|^2 + a^2)),  G = grad Is0. */
+static void evolved_term(double D, double gx, double gy, double gz, double a, double *fx, double *fy, double *fz)
+{
+    double G2 = gx * gx + gy * gy + gz * gz;
+    double den = (2.0 * D * D + G2 + a * a) * (G2 + a * a);
+    if (den <= ORC_DENOM_FLOOR) { *fx = *fy = *fz = 0.0; return; }
+    double s = 4.0 * D * sqrt(G2) * a / den;
+    *fx = s * gx;
+    *fy = s * gy;
+    *fz = s * gz;
+}
+
+/* Per-level constants of Sec 2.1: grad Is0 is computed once per level
+ * (passive, evolved and double force); |grad Im0| once per level (evolved). */
+typedef struct {
+    double *gs;  /* 3N or NULL */
+    double *am;  /* N or NULL */
+} level_consts;
+
+static int uses_static_gradient(int variant)
+{
+    return variant == ORC_PASSIVE || variant == ORC_EVOLVED || variant == ORC_DOUBLE;
+}
+
+/* One force evaluation of Eqs 1-6 over the whole level.
+ * Inputs: S, M (level images), v (current field, or the half field h of the
+ * inverse-consistent variant), per-level constants.
+ * Outputs: u = v + dr; sums[0] = sum_x |dr(x)|, sums[1] = sum_x |v(x)|
+ * (per-voxel Euclidean norms, for the relative norm of Sec 2.4) and
+ * sums[2] = sum_x D(x)^2 (intensity difference before the update). */
+static int force_step(int variant, double alpha, const double *S, const double *M, const double *v, int64_t nx,
+                      int64_t ny, int64_t nz, const level_consts *lc, double *u, double *sums)
+{
+    const int64_t N = nx * ny * nz;
+    const int need_gm = (variant == ORC_ACTIVE || variant == ORC_DOUBLE || variant == ORC_INVERSE_CONSISTENT);
+    const int is_ic = (variant == ORC_INVERSE_CONSISTENT);
+    double *Im = (double *)malloc(sizeof(double) * N);
+    double *D = (double *)malloc(sizeof(double) * N);
+    double *dr = (double *)malloc(sizeof(double) * 3 * N);
+    double *gm = need_gm ? (double *)malloc(sizeof(double) * 3 * N) : NULL;
+    double *Is = is_ic ? (double *)malloc(sizeof(double) * N) : NULL;
+    double *gsn = is_ic ? (double *)malloc(sizeof(double) * 3 * N) : NULL;
+    int rc = ORC_OK;
+    if (!Im || !D || !dr || (need_gm && !gm) || (is_ic && (!Is || !gsn))) { rc = ORC_ENOMEM; goto done; }
+
+    /* deformed moving image Im(n); for Eq 6 also the deformed static image Is(n) */
+    orc_warp(M, v, nx, ny, nz, +1.0, Im);
+    if (need_gm) orc_gradient(Im, nx, ny, nz, gm);
+    if (is_ic) {
+        orc_warp(S, v, nx, ny, nz, -1.0, Is);
+        orc_gradient(Is, nx, ny, nz, gsn);
+    }
+
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double fx = 0, fy = 0, fz = 0, ax = 0, ay = 0, az = 0;
+        if (is_ic) {
+            /* Eq 6: D = Im(n) - Is(n), g = grad Im(n) + grad Is(n) */
+            D[i] = Im[i] - Is[i];
+            force_term(D[i], gm[i] + gsn[i], gm[N + i] + gsn[N + i], gm[2 * N + i] + gsn[2 * N + i], alpha, &fx,
+                       &fy, &fz);
+        } else {
+            D[i] = Im[i] - S[i];
+            if (variant == ORC_PASSIVE || variant == ORC_DOUBLE) /* Eq 1; first term of Eq 4 / Eq 5 */
+                force_term(D[i], lc->gs[i], lc->gs[N + i], lc->gs[2 * N + i], alpha, &fx, &fy, &fz);
+            if (variant == ORC_ACTIVE || variant == ORC_DOUBLE) /* Eq 3; second term of Eq 4 / Eq 5 */
+                force_term(D[i], gm[i], gm[N + i], gm[2 * N + i], alpha, &ax, &ay, &az);
+            if (variant == ORC_EVOLVED) /* Eq 2 */
+                evolved_term(D[i], lc->gs[i], lc->gs[N + i], lc->gs[2 * N + i], lc->am[i], &fx, &fy, &fz);
+        }
+        dr[i] = fx + ax;
+        dr[N + i] = fy + ay;
+        dr[2 * N + i] = fz + az;
+        u[i] = v[i] + dr[i];
+        u[N + i] = v[N + i] + dr[N + i];
+        u[2 * N + i] = v[2 * N + i] + dr[2 * N + i];
+    }
+
+    /* serial sums in voxel order */
+    {
+        double s1 = 0.0, s2 = 0.0, sse = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            s1 += sqrt(dr[i] * dr[i] + dr[N + i] * dr[N + i] + dr[2 * N + i] * dr[2 * N + i]);
+            s2 += sqrt(v[i] * v[i] + v[N + i] * v[N + i] + v[2 * N + i] * v[2 * N + i]);
+            sse += D[i] * D[i];
+        }
+        sums[0] = s1;
+        sums[1] = s2;
+        sums[2] = sse;
+    }
+done:
+    free(Im);
+    free(D);
+    free(dr);
+    free(gm);
+    free(Is);
+    free(gsn);
+    return rc;
+}
+
+static int make_level_consts(int variant, const double *S, const double *M, int64_t nx, int64_t ny, int64_t nz,
+                             level_consts *lc)
+{
+    const int64_t N = nx * ny * nz;
+    lc->gs = NULL;
+    lc->am = NULL;
+    if (uses_static_gradient(variant)) {
+        if (!(lc->gs = (double *)malloc(sizeof(double) * 3 * N))) return ORC_ENOMEM;
+        orc_gradient(S, nx, ny, nz, lc->gs);
+    }
+    if (variant == ORC_EVOLVED) {
+        double *gm0 = (double *)malloc(sizeof(double) * 3 * N);
+        lc->am = (double *)malloc(sizeof(double) * N);
+        if (!gm0 || !lc->am) { free(gm0); return ORC_ENOMEM; }
+        orc_gradient(M, nx, ny, nz, gm0);
+        for (int64_t i = 0; i < N; ++i)
+            lc->am[i] = sqrt(gm0[i] * gm0[i] + gm0[N + i] * gm0[N + i] + gm0[2 * N + i] * gm0[2 * N + i]);
+        free(gm0);
+    }
+    return ORC_OK;
+}
+
+static void free_level_consts(level_consts *lc)
+{
+    free(lc->gs);
+    free(lc->am);
+    lc->gs = NULL;
+    lc->am = NULL;
+}
+
+static int valid_variant(int variant) { return variant >= ORC_PASSIVE && variant <= ORC_INVERSE_CONSISTENT; }
+
+/* Public single force evaluation: u = v + dr (Eqs 1-6) with the per-level
+ * constants computed from S and M as given.  sums as in force_step. */
+int orc_force(int variant, double alpha, const double *S, const double *M, const double *v, int64_t nx, int64_t ny,
+              int64_t nz, double *u, double *sums)
+{
+    if (!valid_variant(variant) || !(alpha > 0.0)) return ORC_EINVAL;
+    level_consts lc;
+    int rc = make_level_consts(variant, S, M, nx, ny, nz, &lc);
+    if (rc == ORC_OK) rc = force_step(variant, alpha, S, M, v, nx, ny, nz, &lc, u, sums);
+    free_level_consts(&lc);
+    return rc;
+}
+
+/* Iterations at one resolution level (Sec 2.1, Fig 1a): deform, force,
+ * add, Gaussian-smooth the total field, record the relative norm of Sec 2.4.
+ *
+ * history receives 4 doubles per iteration run: sum|dr|, sum|v| (field before
+ * the update), mean squared intensity difference D^2 / N, and the relative
+ * norm l = sum|dr| / sum|v| (NaN while sum|v| = 0).
+ *
+ * Stopping (Sec 2.4; the printed inequality is garbled): with eps > 0 the
+ * level stops after iteration n >= 10 when l(n-10) - l(n) <= eps, i.e. when
+ * the relative norm has stopped falling over ten iterations; eps = 0 runs the
+ * fixed count.  Returns the number of iterations run, or a negative code. */
+int orc_iterate(int variant, double alpha, double sigma, int radius, const double *S, const double *M, int64_t nx,
+                int64_t ny, int64_t nz, double *v, int iters, double eps, double *history)
+{
+    if (!valid_variant(variant) || !(alpha > 0.0) || !(sigma > 0.0) || radius < 0 || radius > ORC_MAX_RADIUS ||
+        iters < 0 || !(eps >= 0.0))
+        return ORC_EINVAL;
+    const int64_t N = nx * ny * nz;
+    level_consts lc;
+    double *u = (double *)malloc(sizeof(double) * 3 * N);
+    int rc = make_level_consts(variant, S, M, nx, ny, nz, &lc);
+    if (!u) rc = ORC_ENOMEM;
+    int n = 0;
+    for (; rc == ORC_OK && n < iters; ++n) {
+        double sums[3];
+        rc = force_step(variant, alpha, S, M, v, nx, ny, nz, &lc, u, sums);
+        if (rc != ORC_OK) break;
+        rc = orc_smooth(u, 3, nx, ny, nz, sigma, radius, v);
+        if (rc != ORC_OK) break;
+        double l = sums[1] > 0.0 ? sums[0] / sums[1] : NAN;
+        history[4 * n + 0] = sums[0];
+        history[4 * n + 1] = sums[1];
+        history[4 * n + 2] = sums[2] / (double)N;
+        history[4 * n + 3] = l;
+        if (eps > 0.0 && n >= 10) {
+            double l10 = history[4 * (n - 10) + 3];
+            if (!isnan(l) && !isnan(l10) && l10 - l <= eps) { ++n; break; }
+        }
+    }
+    free(u);
+    free_level_consts(&lc);
+    return rc == ORC_OK ? n : rc;
+}
+
+/* Output field of the inverse-consistent variant.  The iteration returns the
+ * symmetric half field h with M(p - h(p)) = S(p + h(p)) at a match.  Writing
+ * z = p + h(p) gives M(z - 2 h(p)) = S(z), so the field in the convention of
+ * the other variants is w(z) = 2 h(p) with p = z - h(p), solved by K
+ * fixed-point updates starting at p = z (reading of Sec 2.2, text after
+ * Eq 6). */
+void orc_compose(const double *h, int64_t nx, int64_t ny, int64_t nz, int K, double *w)
+{
+    const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                double px = (double)x, py = (double)y, pz = (double)z;
+                for (int k = 0; k < K; ++k) {
+                    double hx = orc_trilerp(h, nx, ny, nz, px, py, pz);
+                    double hy = orc_trilerp(h + N, nx, ny, nz, px, py, pz);
+                    double hz = orc_trilerp(h + 2 * N, nx, ny, nz, px, py, pz);
+                    px = (double)x - hx;
+                    py = (double)y - hy;
+                    pz = (double)z - hz;
+                }
+                int64_t i = at(x, y, z, nx, ny);
+                w[i] = 2.0 * orc_trilerp(h, nx, ny, nz, px, py, pz);
+                w[N + i] = 2.0 * orc_trilerp(h + N, nx, ny, nz, px, py, pz);
+                w[2 * N + i] = 2.0 * orc_trilerp(h + 2 * N, nx, ny, nz, px, py, pz);
+            }
+}
+
+/* Multi-scale registration (Sec 2.3, Fig 1a).
+ *
+ * levels >= 1 resolution levels, level 0 the input grid and level k of size
+ * ceil(n / 2^k) per dimension; iters[] lists the iteration counts from the
+ * coarsest level to the finest.  The field starts at 0 on the coarsest level
+ * and is prolonged (values times 2) to each finer level.  compose_iters is K
+ * of orc_compose for the inverse-consistent variant (ignored otherwise).
+ *
+ * field receives 3 * nx*ny*nz doubles (voxel units, M(x - v(x)) = S(x));
+ * history must hold 4 doubles per iteration of sum(iters); iters_run[] gets
+ * the iterations run per level (coarse to fine); the history of the levels is
+ * packed in that order.  Returns ORC_OK, ORC_EINVAL, ORC_ENOMEM or
+ * ORC_ENUMERIC (a non-finite sum in the history). */
+int orc_register(const double *S, const double *M, int64_t nx, int64_t ny, int64_t nz, int variant, double alpha,
+                 double sigma, int radius, int levels, const int *iters, double eps, int compose_iters,
+                 double *field, double *history, int *iters_run)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || levels < 1 || levels > ORC_MAX_LEVELS || !valid_variant(variant) ||
+        compose_iters < 0)
+        return ORC_EINVAL;
+    for (int l = 0; l < levels; ++l)
+        if (iters[l] < 0) return ORC_EINVAL;
+
+    int64_t dims[ORC_MAX_LEVELS][3];
+    double *Sk[ORC_MAX_LEVELS] = {0}, *Mk[ORC_MAX_LEVELS] = {0};
+    dims[0][0] = nx;
+    dims[0][1] = ny;
+    dims[0][2] = nz;
+    for (int k = 1; k < levels; ++k)
+        for (int d = 0; d < 3; ++d) dims[k][d] = coarse_len(dims[k - 1][d]);
+
+    int rc = ORC_OK;
+    const int64_t N0 = nx * ny * nz;
+    double *v = (double *)calloc(3 * N0, sizeof(double));
+    double *vt = (double *)calloc(3 * N0, sizeof(double));
+    if (!v || !vt) rc = ORC_ENOMEM;
+    Sk[0] = (double *)S;
+    Mk[0] = (double *)M;
+    for (int k = 1; k < levels && rc == ORC_OK; ++k) {
+        int64_t Nk = dims[k][0] * dims[k][1] * dims[k][2];
+        Sk[k] = (double *)malloc(sizeof(double) * Nk);
+        Mk[k] = (double *)malloc(sizeof(double) * Nk);
+        if (!Sk[k] || !Mk[k]) { rc = ORC_ENOMEM; break; }
+        orc_restrict(Sk[k - 1], dims[k - 1][0], dims[k - 1][1], dims[k - 1][2], Sk[k]);
+        orc_restrict(Mk[k - 1], dims[k - 1][0], dims[k - 1][1], dims[k - 1][2], Mk[k]);
+    }
+
+    int64_t hist_off = 0;
+    for (int k = levels - 1; k >= 0 && rc == ORC_OK; --k) {
+        const int li = levels - 1 - k; /* coarse-to-fine position */
+        const int64_t *d = dims[k];
+        if (k < levels - 1) {
+            const int64_t *dc = dims[k + 1];
+            orc_prolong(v, dc[0], dc[1], dc[2], vt, d[0], d[1], d[2]);
+            memcpy(v, vt, sizeof(double) * 3 * d[0] * d[1] * d[2]);
+        }
+        int n = orc_iterate(variant, alpha, sigma, radius, Sk[k], Mk[k], d[0], d[1], d[2], v, iters[li], eps,
+                            history + 4 * hist_off);
+        if (n < 0) { rc = n; break; }
+        iters_run[li] = n;
+        hist_off += n;
+    }
+
+    if (rc == ORC_OK) {
+        if (variant == ORC_INVERSE_CONSISTENT) orc_compose(v, nx, ny, nz, compose_iters, field);
+        else memcpy(field, v, sizeof(double) * 3 * N0);
+        for (int64_t i = 0; i < 4 * hist_off; ++i)
+            if ((i % 4) != 3 && !isfinite(history[i])) { rc = ORC_ENUMERIC; break; }
+    }
+    for (int k = 1; k < levels; ++k) { free(Sk[k]); free(Mk[k]); }
+    free(v);
+    free(vt);
+    return rc;
+}
