@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the demons registration hot path on one MI355X.
+
+Workload: a seeded synthetic 4DCT-shaped pair of 256x256x100 voxels
+(1.1 x 1.1 x 2.5 mm, max displacement 15 voxels), 3-level pyramid with
+100/50/25 iterations coarse to fine, Gaussian sigma 1.5 voxels (R = 5), and
+the six force settings: passive, active, double force, alpha-normalised
+passive (alpha = 0.4), inverse-consistent, and double force with alpha = 0.4.
+One step registers the pair once with each of the six.
+
+Prints one JSON line: voxel-iterations per second over the timed steps,
+per-registration latency percentiles, the roofline position of the kernel
+that takes the most device time (timed with HIP events on the library's
+stream during the timed steps), and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+SHAPE = (256, 256, 100)          # nx, ny, nz
+ITERS = [100, 50, 25]            # coarsest first
+SIGMA = 1.5
+RADIUS = 5
+SEED = 2
+MAX_U = 15.0
+SPACING = (1.1, 1.1, 2.5)
+SETTINGS = [("passive", "passive", 1.0), ("active", "active", 1.0), ("double", "double", 1.0),
+            ("passive_alpha0.4", "passive", 0.4), ("inverse_consistent", "inverse_consistent", 1.0),
+            ("double_alpha0.4", "double", 0.4)]
+METRIC = "voxel-iters/s + HBM GB/s fraction; p50/p99 per-registration latency"
+
+# Algorithmic HBM bytes per voxel of one launch (each operand read or written
+# once; stencil neighbours and gather re-reads are not counted).
+ALGO_BYTES_PER_VOXEL = {
+    "force": 32.0,       # S or Im/Is 4-8 + M or S 4 (or Im) + v 12 in + u 12 out
+    "warp": 20.0,        # image 4 + field 12 + out 4
+    "warp_pair": 28.0,   # M 4 + S 4 + h 12 + Im 4 + Is 4
+    "smooth_x": 24.0, "smooth_y": 24.0, "smooth_z": 24.0,   # field 12 in + 12 out
+}
+
+
+def level_dims(shape, levels):
+    dims = [tuple(shape)]
+    for _ in range(levels - 1):
+        dims.append(tuple((n + 1) // 2 for n in dims[-1]))
+    return dims   # finest first
+
+
+def voxel_iters(shape, iters):
+    dims = level_dims(shape, len(iters))
+    total = 0
+    for k, it in enumerate(iters):            # iters coarsest first
+        nx, ny, nz = dims[len(iters) - 1 - k]
+        total += nx * ny * nz * it
+    return total
+
+
+def launch_units(kernel, shape, iters, n_ic, n_active_like, n_settings):
+    """Voxels processed by all launches of `kernel` in one step (for bytes)."""
+    dims = level_dims(shape, len(iters))
+    per_reg = 0
+    for k, it in enumerate(iters):
+        nx, ny, nz = dims[len(iters) - 1 - k]
+        per_reg += nx * ny * nz * it
+    if kernel in ("force", "smooth_x", "smooth_y", "smooth_z"):
+        return per_reg * n_settings
+    if kernel == "warp":
+        return per_reg * n_active_like
+    if kernel == "warp_pair":
+        return per_reg * n_ic
+    return None
+
+
+def cpu_baseline(S, M):
+    """The FP64 oracle on one passive registration of the same pair."""
+    import oracle as O
+    t0 = time.perf_counter()
+    O.register(S, M, O.PASSIVE, ITERS, sigma=SIGMA, radius=RADIUS)
+    dt = time.perf_counter() - t0
+    vi = voxel_iters(SHAPE, ITERS)
+    return {"value": vi / dt, "unit": "voxel-iter/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"one passive registration of the 256x256x100 pair, {ITERS} iterations coarse to fine "
+                      f"({vi} voxel-iterations, {dt:.1f} s, FP64)", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-kernel", default=None, help="kernel to time for the roofline (default: largest)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run plain device copies of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: independent registrations shard by pair, "
+                                   "and a single volume is not split across GPUs; use --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    if args.copy_probe:
+        n = 256 * 1024 * 1024 // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
+        return
+
+    from paper_0909_0928_amd import binding as B
+    from paper_0909_0928_amd import phantom as P
+
+    print(f"[bench] building phantom {SHAPE}", file=sys.stderr, flush=True)
+    ph = P.make_phantom(SHAPE, seed=SEED, max_u=MAX_U, spacing_mm=SPACING)
+    S64 = ph.static.astype(np.float32).astype(np.float64)
+    M64 = ph.moving.astype(np.float32).astype(np.float64)
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(ph.static.astype(np.float32)).to(dev)
+    M = torch.from_numpy(ph.moving.astype(np.float32)).to(dev)
+    out = torch.empty((3,) + tuple(S.shape), dtype=torch.float32, device=dev)
+    params = {name: B.make_params(var, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha) for name, var, alpha in SETTINGS}
+    h = B.dir_create(0)
+    vi_reg = voxel_iters(SHAPE, ITERS)
+
+    def step(lat=None):
+        for name, _, _ in SETTINGS:
+            t0 = time.perf_counter()
+            B.dir_register(h, S, M, params[name], field_out=out, history=False)
+            if lat is not None:
+                lat.append((name, (time.perf_counter() - t0) * 1e3))
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # which kernel takes the most device time (one untimed step, all kernels timed)
+    names = B.dir_timing_names()
+    B.dir_timing_enable(h, names)
+    step()
+    per_kernel = {k: B.dir_timing_read(h, k) for k in names}
+    B.dir_timing_enable(h, ())
+    dominant = args.roofline_kernel or max(per_kernel, key=lambda k: per_kernel[k][0])
+    print(f"[bench] per-kernel ms in one step: "
+          + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in per_kernel.items() if v[1]), file=sys.stderr, flush=True)
+
+    # timed region: events bracket only the dominant kernel
+    B.dir_timing_enable(h, [dominant])
+    lat = []
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(lat)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms, kern_launches = B.dir_timing_read(h, dominant)
+    B.dir_timing_enable(h, ())
+
+    total_vi = vi_reg * len(SETTINGS) * args.steps
+    value = total_vi / elapsed
+    lats = np.array([l for _, l in lat])
+    per_var = {name: float(np.median([l for n, l in lat if n == name])) for name, _, _ in SETTINGS}
+
+    # roofline of the dominant kernel: algorithmic bytes over its measured time
+    n_ic = sum(1 for _, v, _ in SETTINGS if v == "inverse_consistent")
+    n_act = sum(1 for _, v, _ in SETTINGS if v in ("active", "double"))
+    units = launch_units(dominant, SHAPE, ITERS, n_ic, n_act, len(SETTINGS))
+    roof = None
+    if units is not None and dominant in ALGO_BYTES_PER_VOXEL and kern_launches:
+        bytes_total = units * ALGO_BYTES_PER_VOXEL[dominant] * args.steps
+        achieved = bytes_total / (kern_ms * 1e-3) / 1e9
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "avg_launch_us": kern_ms * 1e3 / kern_launches, "launches": kern_launches,
+                "algo_bytes_per_voxel": ALGO_BYTES_PER_VOXEL[dominant],
+                "bytes_per_launch": bytes_total / kern_launches}
+
+    # ground-truth error of each setting on a body sample
+    rng = np.random.default_rng(0)
+    body = np.flatnonzero(ph.body.ravel())
+    sample = rng.choice(body, size=min(100000, body.size), replace=False)
+    z, y, x = np.unravel_index(sample, ph.static.shape)
+    vt, _ = ph.ground_truth(x.astype(float), y.astype(float), z.astype(float))
+    gt = {}
+    for name, _, _ in SETTINGS:
+        B.dir_register(h, S, M, params[name], field_out=out, history=False)
+        f = out.view(3, -1)[:, torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
+        d = f - vt
+        mm = np.sqrt((d[0] * SPACING[0]) ** 2 + (d[1] * SPACING[1]) ** 2 + (d[2] * SPACING[2]) ** 2)
+        gt[name] = {"mean_vox": float(np.sqrt((d ** 2).sum(axis=0)).mean()), "mean_mm": float(mm.mean())}
+    B.dir_destroy(h)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(S64, M64)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "voxel-iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256x256x100 synthetic 4DCT phantom pair, 3-level pyramid, 100/50/25 iterations "
+                               "coarse to fine, sigma 1.5 (R 5), six force settings per step",
+                   "shape_xyz": list(SHAPE), "iters_coarse_to_fine": ITERS, "sigma": SIGMA, "radius": RADIUS,
+                   "settings": [s[0] for s in SETTINGS], "voxel_iters_per_step": vi_reg * len(SETTINGS)},
+        "latency_ms": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99)),
+                       "per_setting_p50": per_var},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "gt_error": gt,
+        "per_kernel_ms_one_step": {k: v[0] for k, v in per_kernel.items() if v[1]},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * demons.h - C ABI of the gfx950 (MI355X) demons deformable-registration
+ * library, libdemons.so.
+ *
+ * What it computes: multi-scale demons registration as described by Gu et al.,
+ * "Implementation and evaluation of various demons deformable image
+ * registration algorithms on GPU": each iteration deforms the moving image
+ * with the current displacement field by trilinear interpolation (Sec 2.5,
+ * interpolation kernel), evaluates one of the demons forces of Eqs 1-6 from
+ * the intensity difference and central-difference gradients (Sec 2.1, 2.2,
+ * Sec 2.5 gradient and displacement kernels), adds it to the field and
+ * smooths the field with a separable Gaussian (Sec 2.1, Sec 2.5 low-pass
+ * filter kernel).  Levels run coarse to fine with 2x down-sampling and 2x
+ * field up-sampling (Sec 2.3); the relative norm of Sec 2.4 is reduced every
+ * iteration and optionally stops a level.
+ *
+ * Conventions shared by every entry point:
+ *   - Volumes are float32 [nz][ny][nx], x fastest (index x + nx*(y + ny*z)).
+ *   - A displacement field is three such planes back to back (x, y, z
+ *     components), float32, in voxel units.
+ *   - A field v registers M onto S when M(x - v(x)) ~= S(x).
+ *   - Out-of-grid samples clamp the coordinate; stencils clamp the index.
+ *   - Pointers named d_* are DEVICE pointers on the handle's device, owned by
+ *     the caller; host pointers are named without the prefix.
+ *   - 3 * nx*ny*nz must be below 2^31.
+ *   - All device work is enqueued on the handle's stream.  dir_register and
+ *     dir_force block until their work is complete; the other entry points
+ *     only enqueue (call dir_synchronize before reading their outputs on the
+ *     host).
+ *   - Return value: DIR_OK or a negative dir_status; no exception crosses the
+ *     ABI.  After an error the contents of output buffers are unspecified.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef DEMONS_H
+#define DEMONS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIR_ABI_VERSION 1
+#define DIR_MAX_LEVELS 8
+#define DIR_MAX_RADIUS 16
+#define DIR_DEFAULT_COMPOSE_ITERS 10
+
+typedef enum {
+    DIR_OK = 0,
+    DIR_EINVAL = -1,   /* bad argument (null pointer, size, parameter range) */
+    DIR_ENOMEM = -2,   /* device or host allocation failed */
+    DIR_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed */
+    DIR_ENUMERIC = -4  /* a non-finite value appeared in the per-iteration sums */
+} dir_status;
+
+/* Demons force variants (Sec 2.1-2.2).  The Pennec/Wang normalisation factor
+ * alpha multiplies D^2 in every denominator of Eqs 1, 3, 4 (giving Eq 5 for
+ * DIR_DOUBLE) and 6; alpha = 1 is the paper's unnormalised form.  It is not
+ * used by DIR_EVOLVED_PASSIVE (Eq 2). */
+typedef enum {
+    DIR_PASSIVE = 0,             /* Eq 1: grad of the static image, computed once per level */
+    DIR_EVOLVED_PASSIVE = 1,     /* Eq 2: adds |grad| of the undeformed moving image */
+    DIR_ACTIVE = 2,              /* Eq 3: grad of the deformed moving image, every iteration */
+    DIR_DOUBLE = 3,              /* Eq 4 (Eq 5 with alpha != 1): Eq 1 + Eq 3 */
+    DIR_INVERSE_CONSISTENT = 4   /* Eq 6: both images deformed toward each other */
+} dir_variant;
+
+/* Registration parameters.  Set struct_size = sizeof(dir_params). */
+typedef struct {
+    int32_t struct_size;
+    int32_t variant;                 /* dir_variant */
+    double alpha;                    /* > 0; 1.0 = paper form */
+    double sigma;                    /* Gaussian standard deviation in voxels, > 0 (Sec 2.5: 1 voxel) */
+    int32_t radius;                  /* taps 2R+1 per axis; <= 0 selects ceil(3 sigma); at most DIR_MAX_RADIUS */
+    int32_t levels;                  /* 1..DIR_MAX_LEVELS; level k has ceil(n / 2^k) voxels per axis */
+    int32_t iters[DIR_MAX_LEVELS];   /* iterations per level, COARSEST FIRST; each >= 0 */
+    double eps;                      /* 0: fixed counts; > 0: stop a level once l(n-10) - l(n) <= eps (Sec 2.4) */
+    int32_t compose_iters;           /* fixed-point steps of the IC output composition; < 0 selects 10 */
+    int32_t reserved;                /* must be 0 */
+} dir_params;
+
+/* Optional registration statistics.  Set struct_size = sizeof(dir_stats).
+ * history, if not NULL, is a caller-owned host buffer of 4 * history_capacity
+ * doubles; per iteration run (levels coarse to fine, packed) it receives
+ * sum|dr|, sum|v| (field before the update), mean D^2 and the relative norm
+ * l = sum|dr| / sum|v| (NaN while sum|v| = 0). */
+typedef struct {
+    int32_t struct_size;
+    int32_t levels;                     /* written */
+    int32_t iters_run[DIR_MAX_LEVELS];  /* written, coarsest first */
+    double mse_final;                   /* written: mean D^2 of the last iteration run */
+    double relnorm_final;               /* written: l of the last iteration run */
+    double *history;                    /* in: host buffer or NULL */
+    int32_t history_capacity;           /* in: iterations the buffer holds */
+    int32_t history_len;                /* written: iterations stored */
+} dir_stats;
+
+typedef struct dir_handle dir_handle;
+
+/* ABI version of the loaded library (DIR_ABI_VERSION it was built with). */
+int32_t dir_abi_version(void);
+
+/* Static, never-NULL description of a status code. */
+const char *dir_strerror(int32_t code);
+
+/* Text of the last HIP error seen by any handle of this thread ("" if none). */
+const char *dir_last_error_message(void);
+
+/* Create a handle on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL selects the null stream).  The handle owns its workspace
+ * (image pyramid, ping-pong fields, per-block sums, history), which grows to
+ * the largest request and is freed by dir_destroy. */
+int32_t dir_create(dir_handle **out, int32_t device, void *stream);
+
+/* Replace the stream work is enqueued on. */
+int32_t dir_set_stream(dir_handle *h, void *stream);
+
+/* Free the handle and its workspace.  NULL is accepted. */
+int32_t dir_destroy(dir_handle *h);
+
+/* Wait for all work enqueued by this handle. */
+int32_t dir_synchronize(dir_handle *h);
+
+/* Multi-scale demons registration of d_moving onto d_static (Sec 2.1-2.4).
+ * d_static, d_moving: nx*ny*nz floats each.  spacing_mm: host array of three
+ * voxel sizes (> 0) or NULL; the algorithm works in voxel units as the paper
+ * does, so spacing is only validated.  d_field_out: 3*nx*ny*nz floats,
+ * receives v with M(x - v(x)) ~= S(x) for every variant (for
+ * DIR_INVERSE_CONSISTENT the composed full field, see dir_compose).
+ * Blocks until complete. */
+int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                     int32_t nz, const double *spacing_mm, const dir_params *params, float *d_field_out,
+                     dir_stats *stats);
+
+/* Deformed image (Sec 2.5 interpolation kernel): d_out(x) = vol(x - v(x)),
+ * trilinear, coordinates clamped.  d_field: 3 planes. */
+int32_t dir_warp(dir_handle *h, const float *d_vol, const float *d_field, int32_t nx, int32_t ny, int32_t nz,
+                 float *d_out);
+
+/* Central-difference gradient (Sec 2.5 gradient kernel): 3 planes
+ * (I[i+1] - I[i-1]) / 2 per axis, indices clamped, voxel units. */
+int32_t dir_gradient(dir_handle *h, const float *d_img, int32_t nx, int32_t ny, int32_t nz, float *d_grad);
+
+/* Separable Gaussian smoothing (Sec 2.1, Sec 2.5 low-pass filter kernel) of
+ * ncomp planes (1..3): weights exp(-j^2/(2 sigma^2)) normalised to unit sum,
+ * j in [-R, R], clamped borders.  radius <= 0 selects ceil(3 sigma).
+ * d_in and d_out must not overlap. */
+int32_t dir_smooth(dir_handle *h, const float *d_in, int32_t ncomp, int32_t nx, int32_t ny, int32_t nz,
+                   double sigma, int32_t radius, float *d_out);
+
+/* 2x down-sampling (Sec 2.3): 2x2x2 box mean with children clamped to the
+ * grid; d_out has ceil(nx/2) x ceil(ny/2) x ceil(nz/2) voxels. */
+int32_t dir_restrict(dir_handle *h, const float *d_in, int32_t nx, int32_t ny, int32_t nz, float *d_out);
+
+/* Field up-sampling to the next finer level (Sec 2.3): cell-centred trilinear
+ * interpolation (fine index f at coarse coordinate (f - 0.5) / 2, clamped),
+ * values multiplied by 2.  d_coarse: 3 planes of cnx*cny*cnz; d_fine: 3 planes
+ * of fnx*fny*fnz. */
+int32_t dir_prolong(dir_handle *h, const float *d_coarse, int32_t cnx, int32_t cny, int32_t cnz, float *d_fine,
+                    int32_t fnx, int32_t fny, int32_t fnz);
+
+/* One force evaluation (Eqs 1-6) at one level, as inside dir_register:
+ * d_updated = v + dr.  For DIR_INVERSE_CONSISTENT d_field is the symmetric
+ * half field h (M deformed by x - h, S by x + h).  sums, if not NULL, is a
+ * host array receiving sum|dr|, sum|v| and sum D^2 (FP64).  Blocks. */
+int32_t dir_force(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
+                  const float *d_field, int32_t nx, int32_t ny, int32_t nz, float *d_updated, double *sums);
+
+/* Output field of the inverse-consistent variant from its half field h:
+ * w(z) = 2 h(p) with p = z - h(p), p found by K fixed-point updates from
+ * p = z (K < 0 selects 10).  d_half, d_out: 3 planes, must not overlap. */
+int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, int32_t nz, int32_t K,
+                    float *d_out);
+
+/* Per-kernel device timing with HIP events on the handle's stream.
+ * Kernels are numbered 0 .. dir_timing_count()-1; dir_timing_name(k) gives
+ * the kernel's name (NULL if k is out of range).
+ * dir_timing_enable(h, mask) zeroes the totals and, for every kernel k whose
+ * bit (1 << k) is set, brackets each later launch with a pair of events on
+ * the handle's stream; mask 0 stops recording.  dir_timing_read returns the
+ * accumulated device milliseconds and launch count of kernel k over the
+ * launches of blocking calls (dir_register, dir_force) and of calls followed
+ * by dir_synchronize. */
+int32_t dir_timing_count(void);
+const char *dir_timing_name(int32_t kernel);
+int32_t dir_timing_enable(dir_handle *h, uint64_t kernel_mask);
+int32_t dir_timing_read(dir_handle *h, int32_t kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEMONS_H */

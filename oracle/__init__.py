@@ -52,6 +52,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         i64 = ctypes.c_int64
+        L.orc_max_threads.restype = ctypes.c_int
         L.orc_trilerp.restype = ctypes.c_double
         L.orc_trilerp.argtypes = [dp, i64, i64, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_warp.argtypes = [dp, dp, i64, i64, i64, ctypes.c_double, dp]
@@ -68,6 +69,11 @@ def lib():
                                    ctypes.c_int, ctypes.c_int, ip, ctypes.c_double, ctypes.c_int, dp, dp, ip]
         _lib = L
     return _lib
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's element-wise loops use."""
+    return int(lib().orc_max_threads())
 
 
 def _p(a):

@@ -47,6 +47,19 @@ static int64_t at(int64_t x, int64_t y, int64_t z, int64_t nx, int64_t ny) { ret
 
 int orc_version(void) { return 1; }
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Threads the element-wise loops run on (1 without OpenMP). */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Trilinear interpolation (Sec 2.5, interpolation kernel).  The paper uses
  * its own full-precision trilinear code rather than hardware filtering.  The

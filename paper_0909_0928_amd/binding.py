@@ -1,0 +1,328 @@
+"""ctypes binding of libdemons.so (include/demons.h), same names as the C ABI.
+
+Argument marshalling only: every step of the registration runs in the HIP
+kernels of libdemons.so.  Tensors are torch CUDA (HIP) float32 tensors,
+contiguous, on the handle's device: volumes [nz, ny, nx], fields
+[3, nz, ny, nx] in voxel units.  If the shared library is missing this module
+raises; there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdemons.so")
+
+DIR_OK, DIR_EINVAL, DIR_ENOMEM, DIR_EDEVICE, DIR_ENUMERIC = 0, -1, -2, -3, -4
+DIR_PASSIVE, DIR_EVOLVED_PASSIVE, DIR_ACTIVE, DIR_DOUBLE, DIR_INVERSE_CONSISTENT = 0, 1, 2, 3, 4
+DIR_MAX_LEVELS = 8
+DIR_MAX_RADIUS = 16
+VARIANTS = {"passive": DIR_PASSIVE, "evolved": DIR_EVOLVED_PASSIVE, "active": DIR_ACTIVE, "double": DIR_DOUBLE,
+            "inverse_consistent": DIR_INVERSE_CONSISTENT}
+
+
+class DemonsError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = int(code)
+        msg = f"{where}: {_strerror(self.code)} ({self.code})"
+        detail = _last_error()
+        if detail:
+            msg += f" [{detail}]"
+        super().__init__(msg)
+
+
+class dir_params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("variant", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("radius", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("iters", ctypes.c_int32 * DIR_MAX_LEVELS), ("eps", ctypes.c_double),
+                ("compose_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class dir_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("iters_run", ctypes.c_int32 * DIR_MAX_LEVELS), ("mse_final", ctypes.c_double),
+                ("relnorm_final", ctypes.c_double), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("history_capacity", ctypes.c_int32), ("history_len", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdemons.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DemonsError(DIR_EDEVICE, f"{LIB_PATH} missing; build it with python -m paper_0909_0928_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.dir_abi_version.restype = i32
+        L.dir_strerror.restype = ctypes.c_char_p
+        L.dir_strerror.argtypes = [i32]
+        L.dir_last_error_message.restype = ctypes.c_char_p
+        L.dir_create.argtypes = [ctypes.POINTER(vp), i32, vp]
+        L.dir_set_stream.argtypes = [vp, vp]
+        L.dir_destroy.argtypes = [vp]
+        L.dir_synchronize.argtypes = [vp]
+        L.dir_register.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(dir_params), vp,
+                                   ctypes.POINTER(dir_stats)]
+        L.dir_warp.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+        L.dir_gradient.argtypes = [vp, vp, i32, i32, i32, vp]
+        L.dir_smooth.argtypes = [vp, vp, i32, i32, i32, i32, f64, i32, vp]
+        L.dir_restrict.argtypes = [vp, vp, i32, i32, i32, vp]
+        L.dir_prolong.argtypes = [vp, vp, i32, i32, i32, vp, i32, i32, i32]
+        L.dir_force.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(f64)]
+        L.dir_compose.argtypes = [vp, vp, i32, i32, i32, i32, vp]
+        L.dir_timing_count.restype = i32
+        L.dir_timing_name.restype = ctypes.c_char_p
+        L.dir_timing_name.argtypes = [i32]
+        L.dir_timing_enable.argtypes = [vp, ctypes.c_uint64]
+        L.dir_timing_read.argtypes = [vp, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
+        for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
+                     "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_compose",
+                     "dir_timing_enable", "dir_timing_read"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _strerror(code):
+    try:
+        return lib().dir_strerror(int(code)).decode()
+    except Exception:
+        return "error"
+
+
+def _last_error():
+    try:
+        return lib().dir_last_error_message().decode()
+    except Exception:
+        return ""
+
+
+def _check(rc, where):
+    if rc != DIR_OK:
+        raise DemonsError(rc, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, name, ndim):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on the GPU")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions, got {tuple(t.shape)}")
+    return t
+
+
+def _dims(vol):
+    nz, ny, nx = vol.shape[-3:]
+    return int(nx), int(ny), int(nz)
+
+
+def _stream_ptr(stream, device):
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Handle:
+    """Owns one dir_handle; use as a context manager or call dir_destroy."""
+
+    def __init__(self, ptr, device):
+        self.ptr = ptr
+        self.device = device
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        dir_destroy(self)
+
+    @property
+    def _as_param_(self):
+        return self.ptr
+
+
+def dir_abi_version():
+    return lib().dir_abi_version()
+
+
+def dir_strerror(code):
+    return _strerror(code)
+
+
+def dir_create(device=0, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib().dir_create(ctypes.byref(h), int(device), _stream_ptr(stream, device)), "dir_create")
+    return Handle(h, device)
+
+
+def dir_set_stream(h, stream):
+    _check(lib().dir_set_stream(h.ptr, _stream_ptr(stream, h.device)), "dir_set_stream")
+
+
+def dir_destroy(h):
+    if h is not None and h.ptr:
+        rc = lib().dir_destroy(h.ptr)
+        h.ptr = ctypes.c_void_p()
+        _check(rc, "dir_destroy")
+
+
+def dir_synchronize(h):
+    _check(lib().dir_synchronize(h.ptr), "dir_synchronize")
+
+
+def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_iters=-1):
+    """dir_params; `iters` lists the levels coarsest first."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    iters = [int(i) for i in iters]
+    if not 1 <= len(iters) <= DIR_MAX_LEVELS:
+        raise ValueError("1..8 levels")
+    p = dir_params()
+    p.struct_size = ctypes.sizeof(dir_params)
+    p.variant = int(variant)
+    p.alpha = float(alpha)
+    p.sigma = float(sigma)
+    p.radius = int(radius)
+    p.levels = len(iters)
+    for k, n in enumerate(iters):
+        p.iters[k] = n
+    p.eps = float(eps)
+    p.compose_iters = int(compose_iters)
+    p.reserved = 0
+    return p
+
+
+def dir_register(h, static, moving, params, field_out=None, spacing_mm=None, history=True):
+    """Register `moving` onto `static`; returns (field [3,nz,ny,nx], stats dict)."""
+    _dev_f32(static, "static", 3)
+    _dev_f32(moving, "moving", 3)
+    if static.shape != moving.shape:
+        raise ValueError("static and moving differ in shape")
+    nx, ny, nz = _dims(static)
+    if field_out is None:
+        field_out = torch.empty((3,) + tuple(static.shape), dtype=torch.float32, device=static.device)
+    _dev_f32(field_out, "field_out", 4)
+    st = dir_stats()
+    st.struct_size = ctypes.sizeof(dir_stats)
+    total = sum(params.iters[k] for k in range(params.levels))
+    buf = (ctypes.c_double * max(4 * total, 4))() if history else None
+    if history:
+        st.history = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+        st.history_capacity = total
+    sp = (ctypes.c_double * 3)(*spacing_mm) if spacing_mm is not None else None
+    rc = lib().dir_register(h.ptr, _ptr(static), _ptr(moving), nx, ny, nz, sp, ctypes.byref(params),
+                            _ptr(field_out), ctypes.byref(st))
+    stats = {"rc": rc, "levels": st.levels, "iters_run": list(st.iters_run)[:st.levels],
+             "mse_final": st.mse_final, "relnorm_final": st.relnorm_final, "history": None}
+    if history:
+        stats["history"] = [tuple(buf[4 * i:4 * i + 4]) for i in range(st.history_len)]
+    if rc != DIR_OK:
+        raise DemonsError(rc, "dir_register")
+    return field_out, stats
+
+
+def dir_warp(h, vol, field, out=None):
+    _dev_f32(vol, "vol", 3)
+    _dev_f32(field, "field", 4)
+    if field.shape[1:] != vol.shape or field.shape[0] != 3:
+        raise ValueError("field must be [3] + vol.shape")
+    out = torch.empty_like(vol) if out is None else _dev_f32(out, "out", 3)
+    _check(lib().dir_warp(h.ptr, _ptr(vol), _ptr(field), *_dims(vol), _ptr(out)), "dir_warp")
+    return out
+
+
+def dir_gradient(h, img, out=None):
+    _dev_f32(img, "img", 3)
+    out = torch.empty((3,) + tuple(img.shape), dtype=torch.float32, device=img.device) if out is None else out
+    _dev_f32(out, "out", 4)
+    _check(lib().dir_gradient(h.ptr, _ptr(img), *_dims(img), _ptr(out)), "dir_gradient")
+    return out
+
+
+def dir_smooth(h, x, sigma, radius=0, out=None):
+    """Smooth a volume [nz,ny,nx] or a stack [c,nz,ny,nx] (c <= 3)."""
+    if x.dim() == 3:
+        ncomp = 1
+        _dev_f32(x, "x", 3)
+    else:
+        _dev_f32(x, "x", 4)
+        ncomp = x.shape[0]
+    out = torch.empty_like(x) if out is None else out
+    _dev_f32(out, "out", x.dim())
+    _check(lib().dir_smooth(h.ptr, _ptr(x), ncomp, *_dims(x), float(sigma), int(radius), _ptr(out)), "dir_smooth")
+    return out
+
+
+def coarse_shape(shape3):
+    return tuple((int(n) + 1) // 2 for n in shape3)
+
+
+def dir_restrict(h, x, out=None):
+    _dev_f32(x, "x", 3)
+    out = torch.empty(coarse_shape(x.shape), dtype=torch.float32, device=x.device) if out is None else out
+    _dev_f32(out, "out", 3)
+    _check(lib().dir_restrict(h.ptr, _ptr(x), *_dims(x), _ptr(out)), "dir_restrict")
+    return out
+
+
+def dir_prolong(h, coarse, fine_shape3, out=None):
+    _dev_f32(coarse, "coarse", 4)
+    fz, fy, fx = (int(n) for n in fine_shape3)
+    out = torch.empty((3, fz, fy, fx), dtype=torch.float32, device=coarse.device) if out is None else out
+    _dev_f32(out, "out", 4)
+    _check(lib().dir_prolong(h.ptr, _ptr(coarse), *_dims(coarse), _ptr(out), fx, fy, fz), "dir_prolong")
+    return out
+
+
+def dir_force(h, variant, alpha, static, moving, field, out=None):
+    """u = v + dr (Eqs 1-6) and the FP64 sums (sum|dr|, sum|v|, sum D^2)."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    _dev_f32(static, "static", 3)
+    _dev_f32(moving, "moving", 3)
+    _dev_f32(field, "field", 4)
+    out = torch.empty_like(field) if out is None else _dev_f32(out, "out", 4)
+    sums = (ctypes.c_double * 3)()
+    _check(lib().dir_force(h.ptr, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
+                           *_dims(static), _ptr(out), sums), "dir_force")
+    return out, tuple(sums)
+
+
+def dir_compose(h, half, K=-1, out=None):
+    _dev_f32(half, "half", 4)
+    out = torch.empty_like(half) if out is None else _dev_f32(out, "out", 4)
+    _check(lib().dir_compose(h.ptr, _ptr(half), *_dims(half), int(K), _ptr(out)), "dir_compose")
+    return out
+
+
+def dir_timing_names():
+    L = lib()
+    return [L.dir_timing_name(k).decode() for k in range(L.dir_timing_count())]
+
+
+def dir_timing_enable(h, kernels=()):
+    """Time the named kernels (or indices) from now on; () stops timing."""
+    names = dir_timing_names()
+    mask = 0
+    for k in kernels:
+        mask |= 1 << (names.index(k) if isinstance(k, str) else int(k))
+    _check(lib().dir_timing_enable(h.ptr, ctypes.c_uint64(mask)), "dir_timing_enable")
+
+
+def dir_timing_read(h, kernel):
+    names = dir_timing_names()
+    k = names.index(kernel) if isinstance(kernel, str) else int(kernel)
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().dir_timing_read(h.ptr, k, ctypes.byref(ms), ctypes.byref(n)), "dir_timing_read")
+    return ms.value, n.value

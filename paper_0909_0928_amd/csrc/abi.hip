@@ -1,0 +1,586 @@
+// C ABI of libdemons (include/demons.h): handle, workspace, argument
+// validation, the multi-scale registration loop and per-kernel timing.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "demons.h"
+#include "dir_internal.h"
+
+using namespace dir;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+const char *const kKernelNames[K_COUNT] = {
+    "force", "warp", "warp_pair", "smooth_x", "smooth_y", "smooth_z", "finalize",
+    "level_reset", "restrict", "prolong", "gradient", "compose", "fill",
+};
+
+// Device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need)
+    {
+        if (need <= bytes) return hipSuccess;
+        if (p) {
+            hipFree(p);
+            p = nullptr;
+            bytes = 0;
+        }
+        hipError_t e = hipMalloc(&p, need);
+        if (e == hipSuccess) bytes = need;
+        return e;
+    }
+    void release()
+    {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return static_cast<T *>(p);
+    }
+};
+
+}  // namespace
+
+struct dir_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Timer timer;
+    DevBuf pyr_s, pyr_m;           // levels 1.. of the image pyramids, packed
+    DevBuf field[3];               // ping-pong fields, 3 planes each
+    DevBuf img_a, img_b;           // deformed images (active, double, inverse-consistent)
+    DevBuf partials;               // 3 doubles per force workgroup
+    DevBuf history;                // 4 doubles per iteration, per-level fixed offsets
+    DevBuf state;                  // one LevelState per level
+};
+
+namespace {
+
+int fail_hip(hipError_t e, const char *what)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_last_error = buf;
+    return e == hipErrorOutOfMemory ? DIR_ENOMEM : DIR_EDEVICE;
+}
+
+#define DIR_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return fail_hip(_e, #expr); \
+    } while (0)
+
+bool dims_ok(int32_t nx, int32_t ny, int32_t nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return false;
+    const int64_t n = (int64_t)nx * ny * nz;
+    return 3 * n < (int64_t(1) << 31);
+}
+
+int resolve_radius(double sigma, int32_t radius)
+{
+    if (radius > 0) return radius;
+    return (int)ceil(3.0 * sigma);
+}
+
+// Normalised sampled Gaussian (Sec 2.5 low-pass filter), computed in FP64 and
+// rounded to FP32 taps.
+GaussTaps make_taps(double sigma, int radius)
+{
+    GaussTaps t;
+    memset(&t, 0, sizeof t);
+    t.radius = radius;
+    double w[2 * kMaxRadius + 1], sum = 0.0;
+    for (int j = -radius; j <= radius; ++j) {
+        w[j + radius] = exp(-(double)(j * j) / (2.0 * sigma * sigma));
+        sum += w[j + radius];
+    }
+    for (int j = 0; j <= 2 * radius; ++j) t.w[j] = (float)(w[j] / sum);
+    return t;
+}
+
+Dims coarser(Dims d) { return Dims{(d.nx + 1) / 2, (d.ny + 1) / 2, (d.nz + 1) / 2}; }
+
+int enter(dir_handle *h)
+{
+    if (!h) return DIR_EINVAL;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    return DIR_OK;
+}
+
+// Wait for the stream, then fold completed timing events into the totals.
+int finish(dir_handle *h)
+{
+    DIR_TRY(hipStreamSynchronize(h->stream));
+    DIR_TRY(h->timer.harvest());
+    return DIR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Timer
+// ---------------------------------------------------------------------------
+namespace dir {
+
+hipError_t Timer::take(hipEvent_t *ev)
+{
+    if (!pool_.empty()) {
+        *ev = pool_.back();
+        pool_.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+hipError_t Timer::begin(int, hipStream_t s, hipEvent_t *ev)
+{
+    hipError_t e = take(ev);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(*ev, s);
+}
+
+hipError_t Timer::end(int k, hipStream_t s, hipEvent_t start)
+{
+    hipEvent_t b;
+    hipError_t e = take(&b);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    pending_.push_back(Rec{k, start, b});
+    return hipSuccess;
+}
+
+hipError_t Timer::harvest()
+{
+    hipError_t err = hipSuccess;
+    for (const Rec &r : pending_) {
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e == hipSuccess) {
+            total_ms[r.k] += ms;
+            launches[r.k] += 1;
+        } else if (err == hipSuccess) {
+            err = e;
+        }
+        pool_.push_back(r.a);
+        pool_.push_back(r.b);
+    }
+    pending_.clear();
+    return err;
+}
+
+void Timer::reset()
+{
+    for (int k = 0; k < K_COUNT; ++k) {
+        total_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+}
+
+void Timer::release()
+{
+    for (const Rec &r : pending_) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    pending_.clear();
+    for (hipEvent_t e : pool_) hipEventDestroy(e);
+    pool_.clear();
+}
+
+}  // namespace dir
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t dir_abi_version(void) { return DIR_ABI_VERSION; }
+
+const char *dir_strerror(int32_t code)
+{
+    switch (code) {
+    case DIR_OK: return "success";
+    case DIR_EINVAL: return "invalid argument";
+    case DIR_ENOMEM: return "out of memory";
+    case DIR_EDEVICE: return "HIP device error";
+    case DIR_ENUMERIC: return "non-finite value in the registration sums";
+    default: return "unknown status code";
+    }
+}
+
+const char *dir_last_error_message(void) { return g_last_error.c_str(); }
+
+int32_t dir_create(dir_handle **out, int32_t device, void *stream)
+{
+    if (!out) return DIR_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return DIR_EINVAL;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    dir_handle *h = new (std::nothrow) dir_handle();
+    if (!h) return DIR_ENOMEM;
+    h->device = device;
+    h->stream = static_cast<hipStream_t>(stream);
+    *out = h;
+    return DIR_OK;
+}
+
+int32_t dir_set_stream(dir_handle *h, void *stream)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    rc = finish(h);  // work already enqueued on the old stream completes first
+    h->stream = static_cast<hipStream_t>(stream);
+    return rc;
+}
+
+int32_t dir_destroy(dir_handle *h)
+{
+    if (!h) return DIR_OK;
+    int rc = enter(h);
+    if (rc == DIR_OK) hipStreamSynchronize(h->stream);
+    h->timer.release();
+    h->pyr_s.release();
+    h->pyr_m.release();
+    for (auto &f : h->field) f.release();
+    h->img_a.release();
+    h->img_b.release();
+    h->partials.release();
+    h->history.release();
+    h->state.release();
+    delete h;
+    return rc;
+}
+
+int32_t dir_synchronize(dir_handle *h)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    return finish(h);
+}
+
+int32_t dir_timing_count(void) { return K_COUNT; }
+
+const char *dir_timing_name(int32_t kernel)
+{
+    if (kernel < 0 || kernel >= K_COUNT) return nullptr;
+    return kKernelNames[kernel];
+}
+
+int32_t dir_timing_enable(dir_handle *h, uint64_t kernel_mask)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    rc = finish(h);
+    h->timer.reset();
+    h->timer.mask = kernel_mask;
+    return rc;
+}
+
+int32_t dir_timing_read(dir_handle *h, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!h || kernel < 0 || kernel >= K_COUNT) return DIR_EINVAL;
+    if (total_ms) *total_ms = h->timer.total_ms[kernel];
+    if (launches) *launches = h->timer.launches[kernel];
+    return DIR_OK;
+}
+
+int32_t dir_warp(dir_handle *h, const float *d_vol, const float *d_field, int32_t nx, int32_t ny, int32_t nz,
+                 float *d_out)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_vol || !d_field || !d_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    Ctx c{h->stream, &h->timer};
+    DIR_TRY(launch_warp(c, d_vol, d_field, Dims{nx, ny, nz}, d_out, nullptr));
+    return DIR_OK;
+}
+
+int32_t dir_gradient(dir_handle *h, const float *d_img, int32_t nx, int32_t ny, int32_t nz, float *d_grad)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_img || !d_grad || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    Ctx c{h->stream, &h->timer};
+    DIR_TRY(launch_gradient(c, d_img, Dims{nx, ny, nz}, d_grad));
+    return DIR_OK;
+}
+
+int32_t dir_smooth(dir_handle *h, const float *d_in, int32_t ncomp, int32_t nx, int32_t ny, int32_t nz,
+                   double sigma, int32_t radius, float *d_out)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_in || !d_out || ncomp < 1 || ncomp > 3 || !dims_ok(nx, ny, nz) || !(sigma > 0.0) || !isfinite(sigma))
+        return DIR_EINVAL;
+    const int R = resolve_radius(sigma, radius);
+    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+    const Dims d{nx, ny, nz};
+    const size_t bytes = sizeof(float) * (size_t)ncomp * (size_t)d.n();
+    const char *in = reinterpret_cast<const char *>(d_in);
+    const char *out = reinterpret_cast<const char *>(d_out);
+    if (in < out + bytes && out < in + bytes) return DIR_EINVAL;  // overlap
+    DIR_TRY(h->field[2].ensure(sizeof(float) * 3 * (size_t)d.n()));
+    Ctx c{h->stream, &h->timer};
+    DIR_TRY(launch_smooth(c, d_in, ncomp, d, make_taps(sigma, R), d_out, h->field[2].as<float>(), nullptr));
+    return DIR_OK;
+}
+
+int32_t dir_restrict(dir_handle *h, const float *d_in, int32_t nx, int32_t ny, int32_t nz, float *d_out)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_in || !d_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    const Dims f{nx, ny, nz};
+    Ctx c{h->stream, &h->timer};
+    DIR_TRY(launch_restrict(c, d_in, f, d_out, coarser(f)));
+    return DIR_OK;
+}
+
+int32_t dir_prolong(dir_handle *h, const float *d_coarse, int32_t cnx, int32_t cny, int32_t cnz, float *d_fine,
+                    int32_t fnx, int32_t fny, int32_t fnz)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_coarse || !d_fine || !dims_ok(cnx, cny, cnz) || !dims_ok(fnx, fny, fnz)) return DIR_EINVAL;
+    Ctx c{h->stream, &h->timer};
+    DIR_TRY(launch_prolong(c, d_coarse, Dims{cnx, cny, cnz}, d_fine, Dims{fnx, fny, fnz}));
+    return DIR_OK;
+}
+
+int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, int32_t nz, int32_t K,
+                    float *d_out)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_half || !d_out || !dims_ok(nx, ny, nz) || d_half == d_out) return DIR_EINVAL;
+    if (K < 0) K = DIR_DEFAULT_COMPOSE_ITERS;
+    Ctx c{h->stream, &h->timer};
+    DIR_TRY(launch_compose(c, d_half, Dims{nx, ny, nz}, K, d_out));
+    return DIR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device buffers one force evaluation needs at level size d.
+int ensure_force_workspace(dir_handle *h, Dims d, int variant)
+{
+    const size_t n = (size_t)d.n();
+    if (variant == kActive || variant == kDouble || variant == kInverseConsistent)
+        DIR_TRY(h->img_a.ensure(sizeof(float) * n));
+    if (variant == kInverseConsistent) DIR_TRY(h->img_b.ensure(sizeof(float) * n));
+    DIR_TRY(h->partials.ensure(sizeof(double) * 3 * (size_t)force_blocks(d)));
+    return DIR_OK;
+}
+
+// One force evaluation: pre-warp where the variant needs deformed-image
+// gradients, then the force kernel (u = v + dr and workgroup sums).
+hipError_t force_step(dir_handle *h, Ctx &c, int variant, float alpha2, const float *S, const float *M,
+                      const float *v, Dims d, float *u, const int *stop)
+{
+    float *Im = h->img_a.as<float>(), *Is = h->img_b.as<float>();
+    hipError_t e = hipSuccess;
+    if (variant == kActive || variant == kDouble) e = launch_warp(c, M, v, d, Im, stop);
+    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, Im, Is, stop);
+    if (e != hipSuccess) return e;
+    return launch_force(c, variant, alpha2, S, M, v, Im, Is, d, u, h->partials.as<double>(), stop);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dir_force(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
+                  const float *d_field, int32_t nx, int32_t ny, int32_t nz, float *d_updated, double *sums)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_static || !d_moving || !d_field || !d_updated || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    if (variant < kPassive || variant > kInverseConsistent || !(alpha > 0.0) || !isfinite(alpha)) return DIR_EINVAL;
+    if (d_updated == d_field) return DIR_EINVAL;
+    const Dims d{nx, ny, nz};
+    rc = ensure_force_workspace(h, d, variant);
+    if (rc != DIR_OK) return rc;
+    DIR_TRY(h->history.ensure(sizeof(double) * 4));
+    DIR_TRY(h->state.ensure(sizeof(LevelState)));
+    Ctx c{h->stream, &h->timer};
+    LevelState *st = h->state.as<LevelState>();
+    DIR_TRY(launch_level_reset(c, st));
+    DIR_TRY(force_step(h, c, variant, (float)(alpha * alpha), d_static, d_moving, d_field, d, d_updated, nullptr));
+    DIR_TRY(launch_finalize(c, h->partials.as<double>(), force_blocks(d), 1.0, h->history.as<double>(), 0, st, 0.0));
+    rc = finish(h);
+    if (rc != DIR_OK) return rc;
+    if (sums) {
+        double e[4];
+        DIR_TRY(hipMemcpy(e, h->history.p, sizeof e, hipMemcpyDeviceToHost));
+        sums[0] = e[0];
+        sums[1] = e[1];
+        sums[2] = e[2];  // inv_n = 1: the raw sum of D^2
+    }
+    return DIR_OK;
+}
+
+int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                     int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out,
+                     dir_stats *stats)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    // ---- validation ----
+    if (!d_static || !d_moving || !p || !d_field_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    if (p->struct_size != (int32_t)sizeof(dir_params) || p->reserved != 0) return DIR_EINVAL;
+    if (stats && stats->struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
+    if (spacing_mm)
+        for (int k = 0; k < 3; ++k)
+            if (!(spacing_mm[k] > 0.0) || !isfinite(spacing_mm[k])) return DIR_EINVAL;
+    const int variant = p->variant;
+    if (variant < kPassive || variant > kInverseConsistent) return DIR_EINVAL;
+    if (!(p->alpha > 0.0) || !isfinite(p->alpha) || !(p->sigma > 0.0) || !isfinite(p->sigma)) return DIR_EINVAL;
+    if (!(p->eps >= 0.0) || !isfinite(p->eps)) return DIR_EINVAL;
+    const int L = p->levels;
+    if (L < 1 || L > DIR_MAX_LEVELS) return DIR_EINVAL;
+    int64_t total_iters = 0;
+    for (int l = 0; l < L; ++l) {
+        if (p->iters[l] < 0) return DIR_EINVAL;
+        total_iters += p->iters[l];
+    }
+    const int R = resolve_radius(p->sigma, p->radius);
+    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+    const int K = p->compose_iters < 0 ? DIR_DEFAULT_COMPOSE_ITERS : p->compose_iters;
+    const GaussTaps taps = make_taps(p->sigma, R);
+    const float alpha2 = (float)(p->alpha * p->alpha);
+    const char *out_b = reinterpret_cast<const char *>(d_field_out);
+    const size_t out_bytes = sizeof(float) * 3 * (size_t)((int64_t)nx * ny * nz);
+    for (const float *in : {d_static, d_moving}) {
+        const char *b = reinterpret_cast<const char *>(in);
+        if (b < out_b + out_bytes && out_b < b + sizeof(float) * (size_t)((int64_t)nx * ny * nz)) return DIR_EINVAL;
+    }
+
+    // ---- workspace ----
+    Dims dims[DIR_MAX_LEVELS];
+    dims[0] = Dims{nx, ny, nz};
+    size_t pyr = 0;
+    for (int k = 1; k < L; ++k) {
+        dims[k] = coarser(dims[k - 1]);
+        pyr += (size_t)dims[k].n();
+    }
+    const size_t n0 = (size_t)dims[0].n();
+    if (L > 1) {
+        DIR_TRY(h->pyr_s.ensure(sizeof(float) * pyr));
+        DIR_TRY(h->pyr_m.ensure(sizeof(float) * pyr));
+    }
+    for (auto &f : h->field) DIR_TRY(f.ensure(sizeof(float) * 3 * n0));
+    rc = ensure_force_workspace(h, dims[0], variant);
+    if (rc != DIR_OK) return rc;
+    DIR_TRY(h->history.ensure(sizeof(double) * 4 * (size_t)(total_iters > 0 ? total_iters : 1)));
+    DIR_TRY(h->state.ensure(sizeof(LevelState) * DIR_MAX_LEVELS));
+
+    Ctx c{h->stream, &h->timer};
+    const float *Sk[DIR_MAX_LEVELS], *Mk[DIR_MAX_LEVELS];
+    Sk[0] = d_static;
+    Mk[0] = d_moving;
+    {
+        size_t off = 0;
+        for (int k = 1; k < L; ++k) {
+            float *s = h->pyr_s.as<float>() + off, *m = h->pyr_m.as<float>() + off;
+            DIR_TRY(launch_restrict(c, Sk[k - 1], dims[k - 1], s, dims[k]));
+            DIR_TRY(launch_restrict(c, Mk[k - 1], dims[k - 1], m, dims[k]));
+            Sk[k] = s;
+            Mk[k] = m;
+            off += (size_t)dims[k].n();
+        }
+    }
+
+    // ---- levels, coarse to fine (Sec 2.3) ----
+    float *v = h->field[0].as<float>(), *u = h->field[1].as<float>(), *tmp = h->field[2].as<float>();
+    LevelState *states = h->state.as<LevelState>();
+    double *hist = h->history.as<double>();
+    int64_t hist_off[DIR_MAX_LEVELS];
+    DIR_TRY(launch_zero(c, v, 3 * dims[L - 1].n()));
+    int64_t off = 0;
+    for (int k = L - 1; k >= 0; --k) {
+        const int li = L - 1 - k;
+        const Dims d = dims[k];
+        if (k < L - 1) {
+            DIR_TRY(launch_prolong(c, v, dims[k + 1], u, d));
+            float *t = v;
+            v = u;
+            u = t;
+        }
+        LevelState *st = states + li;
+        DIR_TRY(launch_level_reset(c, st));
+        hist_off[li] = off;
+        const int iters = p->iters[li];
+        const double inv_n = 1.0 / (double)d.n();
+        const int64_t nb = force_blocks(d);
+        for (int n = 0; n < iters; ++n) {
+            DIR_TRY(force_step(h, c, variant, alpha2, Sk[k], Mk[k], v, d, u, &st->stop));
+            DIR_TRY(launch_smooth(c, u, 3, d, taps, v, tmp, &st->stop));
+            DIR_TRY(launch_finalize(c, h->partials.as<double>(), nb, inv_n, hist + 4 * off, n, st, p->eps));
+            if (p->eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
+                int stop = 0;
+                DIR_TRY(hipMemcpyAsync(&stop, &st->stop, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+                DIR_TRY(hipStreamSynchronize(h->stream));
+                if (stop) break;
+            }
+        }
+        off += iters;
+    }
+
+    // ---- output ----
+    if (variant == kInverseConsistent) DIR_TRY(launch_compose(c, v, dims[0], K, d_field_out));
+    else DIR_TRY(hipMemcpyAsync(d_field_out, v, sizeof(float) * 3 * n0, hipMemcpyDeviceToDevice, h->stream));
+    rc = finish(h);
+    if (rc != DIR_OK) return rc;
+
+    // ---- statistics and the numeric check ----
+    LevelState hs[DIR_MAX_LEVELS];
+    DIR_TRY(hipMemcpy(hs, states, sizeof(LevelState) * L, hipMemcpyDeviceToHost));
+    std::vector<double> hh((size_t)4 * (size_t)(total_iters > 0 ? total_iters : 1));
+    if (total_iters > 0) DIR_TRY(hipMemcpy(hh.data(), hist, sizeof(double) * 4 * total_iters, hipMemcpyDeviceToHost));
+    bool finite = true;
+    int64_t packed = 0;
+    double last_mse = 0.0, last_l = __builtin_nan("");
+    for (int li = 0; li < L; ++li) {
+        for (int n = 0; n < hs[li].iters_run; ++n) {
+            const double *e = &hh[(size_t)4 * (hist_off[li] + n)];
+            if (!isfinite(e[0]) || !isfinite(e[1]) || !isfinite(e[2])) finite = false;
+            if (stats && stats->history && packed < stats->history_capacity)
+                memcpy(stats->history + 4 * packed, e, sizeof(double) * 4);
+            last_mse = e[2];
+            last_l = e[3];
+            ++packed;
+        }
+    }
+    if (stats) {
+        stats->levels = L;
+        for (int li = 0; li < DIR_MAX_LEVELS; ++li) stats->iters_run[li] = li < L ? hs[li].iters_run : 0;
+        stats->mse_final = last_mse;
+        stats->relnorm_final = last_l;
+        stats->history_len = (int32_t)(stats->history ? (packed < stats->history_capacity ? packed
+                                                                                         : stats->history_capacity)
+                                                      : 0);
+    }
+    return finite ? DIR_OK : DIR_ENUMERIC;
+}
+
+}  // extern "C"

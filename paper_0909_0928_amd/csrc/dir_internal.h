@@ -1,0 +1,107 @@
+// Internal declarations of libdemons: kernel launchers, launch context and
+// per-kernel event timing.  Not part of the public ABI (see include/demons.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace dir {
+
+constexpr int kMaxRadius = 16;
+constexpr int kBlockX = 64;   // one wavefront along x
+constexpr int kBlockY = 4;    // four wavefronts per workgroup
+constexpr int kFinalizeThreads = 256;
+
+// Variant codes, numerically equal to dir_variant.
+enum Variant { kPassive = 0, kEvolved = 1, kActive = 2, kDouble = 3, kInverseConsistent = 4 };
+
+// Kernel ids for event timing; names in kKernelNames (abi.hip).
+enum KernelId {
+    K_FORCE = 0,
+    K_WARP,
+    K_WARP_PAIR,
+    K_SMOOTH_X,
+    K_SMOOTH_Y,
+    K_SMOOTH_Z,
+    K_FINALIZE,
+    K_LEVEL_RESET,
+    K_RESTRICT,
+    K_PROLONG,
+    K_GRADIENT,
+    K_COMPOSE,
+    K_FILL,
+    K_COUNT
+};
+
+struct Dims {
+    int nx, ny, nz;
+    int64_t n() const { return (int64_t)nx * ny * nz; }
+};
+
+// Normalised Gaussian taps w[j + radius], j in [-radius, radius], in FP32.
+struct GaussTaps {
+    float w[2 * kMaxRadius + 1];
+    int radius;
+};
+
+// Device-side state of one resolution level (stopping rule of Sec 2.4).
+struct LevelState {
+    int stop;        // set by the finalize kernel once the rule fires
+    int iters_run;   // iterations completed at this level
+};
+
+// Per-kernel HIP-event timing.  Events are recycled from a pool; pairs are
+// read back by harvest() after the stream has completed.
+class Timer {
+  public:
+    uint64_t mask = 0;
+    double total_ms[K_COUNT] = {};
+    int64_t launches[K_COUNT] = {};
+
+    bool on(int k) const { return (mask >> k) & 1ull; }
+    hipError_t begin(int k, hipStream_t s, hipEvent_t *ev);
+    hipError_t end(int k, hipStream_t s, hipEvent_t start);
+    hipError_t harvest();   // stream must be complete
+    void reset();
+    void release();         // destroy all events
+
+  private:
+    struct Rec {
+        int k;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool_;
+    std::vector<Rec> pending_;
+    hipError_t take(hipEvent_t *ev);
+};
+
+// What every launcher needs: the stream, and the timer to bracket launches.
+struct Ctx {
+    hipStream_t stream;
+    Timer *timer;
+};
+
+// Number of workgroups the force kernel launches for a level (one partial
+// sum triple per workgroup).
+int64_t force_blocks(Dims d);
+
+// ---- launchers (kernels.hip); each returns the launch status -------------
+hipError_t launch_restrict(Ctx &c, const float *in, Dims fine, float *out, Dims coarse);
+hipError_t launch_prolong(Ctx &c, const float *vc, Dims coarse, float *vf, Dims fine);
+hipError_t launch_gradient(Ctx &c, const float *img, Dims d, float *grad);
+hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, float *out, const int *stop);
+hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *Im, float *Is,
+                            const int *stop);
+hipError_t launch_force(Ctx &c, int variant, float alpha2, const float *S, const float *M, const float *v,
+                        const float *Im, const float *Is, Dims d, float *u, double *partials, const int *stop);
+hipError_t launch_smooth(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out, float *tmp,
+                         const int *stop);
+hipError_t launch_finalize(Ctx &c, const double *partials, int64_t nblocks, double inv_n, double *hist_level, int n,
+                           LevelState *st, double eps);
+hipError_t launch_level_reset(Ctx &c, LevelState *st);
+hipError_t launch_compose(Ctx &c, const float *h, Dims d, int K, float *out);
+hipError_t launch_zero(Ctx &c, float *p, int64_t n);
+
+}  // namespace dir

@@ -1,0 +1,70 @@
+"""The C ABI library loads and exports every function include/demons.h declares.
+
+No GPU is needed: only host-side entry points are called (version, strings,
+timing names, NULL-handle argument checks).
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "demons.h")
+LIB = os.path.join(ROOT, "paper_0909_0928_amd", "libdemons.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdemons.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dir_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dir_create", "dir_register", "dir_warp", "dir_destroy", "dir_strerror", "dir_force",
+                     "dir_smooth", "dir_gradient", "dir_restrict", "dir_prolong", "dir_compose"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (dir_[a-z_]+)\b", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_host_only_entry_points():
+    from paper_0909_0928_amd import binding as B
+    L = B.lib()
+    assert L.dir_abi_version() == 1
+    assert B.dir_strerror(0) == "success"
+    assert B.dir_strerror(-1) == "invalid argument"
+    assert B.dir_strerror(12345) == "unknown status code"
+    names = B.dir_timing_names()
+    assert "force" in names and "smooth_x" in names and len(names) == L.dir_timing_count()
+    assert L.dir_timing_name(-1) is None and L.dir_timing_name(len(names)) is None
+    # NULL handle: rejected before any device call
+    assert L.dir_warp(None, None, None, 4, 4, 4, None) == B.DIR_EINVAL
+    assert L.dir_register(None, None, None, 4, 4, 4, None, None, None, None) == B.DIR_EINVAL
+    assert L.dir_destroy(None) == B.DIR_OK
+    assert L.dir_create(None, 0, None) == B.DIR_EINVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    from paper_0909_0928_amd import binding as B
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "demons.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dir_params), sizeof(dir_stats),'
+                   'offsetof(dir_params, iters), offsetof(dir_params, eps), offsetof(dir_stats, history),'
+                   'offsetof(dir_stats, history_len)); return 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    sizes = [int(s) for s in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(B.dir_params), ctypes.sizeof(B.dir_stats), B.dir_params.iters.offset,
+                     B.dir_params.eps.offset, B.dir_stats.history.offset, B.dir_stats.history_len.offset]
