@@ -43,10 +43,10 @@ METRIC = "voxel-iters/s + HBM GB/s fraction; p50/p99 per-registration latency"
 # Algorithmic HBM bytes per voxel of one launch (each operand read or written
 # once; stencil neighbours and gather re-reads are not counted).
 ALGO_BYTES_PER_VOXEL = {
-    "force": 32.0,       # S or Im/Is 4-8 + M or S 4 (or Im) + v 12 in + u 12 out
+    "force": 32.0,       # two images 8 + field 12 in + x-smoothed field 12 out
     "warp": 20.0,        # image 4 + field 12 + out 4
     "warp_pair": 28.0,   # M 4 + S 4 + h 12 + Im 4 + Is 4
-    "smooth_x": 24.0, "smooth_y": 24.0, "smooth_z": 24.0,   # field 12 in + 12 out
+    "smooth_yz": 24.0,   # field 12 in + 12 out
 }
 
 
@@ -73,7 +73,7 @@ def launch_units(kernel, shape, iters, n_ic, n_active_like, n_settings):
     for k, it in enumerate(iters):
         nx, ny, nz = dims[len(iters) - 1 - k]
         per_reg += nx * ny * nz * it
-    if kernel in ("force", "smooth_x", "smooth_y", "smooth_z"):
+    if kernel in ("force", "smooth_yz"):
         return per_reg * n_settings
     if kernel == "warp":
         return per_reg * n_active_like

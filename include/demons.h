@@ -166,6 +166,15 @@ int32_t dir_prolong(dir_handle *h, const float *d_coarse, int32_t cnx, int32_t c
 int32_t dir_force(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
                   const float *d_field, int32_t nx, int32_t ny, int32_t nz, float *d_updated, double *sums);
 
+/* One full iteration at one level, exactly as dir_register runs it (same
+ * kernels and launch configuration): d_field_out = G_sigma * (v + dr), the
+ * Gaussian of dir_smooth applied to the output of dir_force.  sums as in
+ * dir_force (over v and dr of this iteration).  d_field_out must not overlap
+ * d_field.  Blocks. */
+int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
+                 const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma, int32_t radius,
+                 float *d_field_out, double *sums);
+
 /* Output field of the inverse-consistent variant from its half field h:
  * w(z) = 2 h(p) with p = z - h(p), p found by K fixed-point updates from
  * p = z (K < 0 selects 10).  d_half, d_out: 3 planes, must not overlap. */

@@ -75,6 +75,7 @@ def lib():
         L.dir_restrict.argtypes = [vp, vp, i32, i32, i32, vp]
         L.dir_prolong.argtypes = [vp, vp, i32, i32, i32, vp, i32, i32, i32]
         L.dir_force.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(f64)]
+        L.dir_step.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_compose.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.dir_timing_count.restype = i32
         L.dir_timing_name.restype = ctypes.c_char_p
@@ -82,7 +83,7 @@ def lib():
         L.dir_timing_enable.argtypes = [vp, ctypes.c_uint64]
         L.dir_timing_read.argtypes = [vp, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
-                     "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_compose",
+                     "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
                      "dir_timing_enable", "dir_timing_read"):
             getattr(L, name).restype = i32
         _lib = L
@@ -295,6 +296,20 @@ def dir_force(h, variant, alpha, static, moving, field, out=None):
     sums = (ctypes.c_double * 3)()
     _check(lib().dir_force(h.ptr, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
                            *_dims(static), _ptr(out), sums), "dir_force")
+    return out, tuple(sums)
+
+
+def dir_step(h, variant, alpha, static, moving, field, sigma, radius=0, out=None):
+    """One iteration as inside dir_register: G_sigma * (v + dr), and the sums."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    _dev_f32(static, "static", 3)
+    _dev_f32(moving, "moving", 3)
+    _dev_f32(field, "field", 4)
+    out = torch.empty_like(field) if out is None else _dev_f32(out, "out", 4)
+    sums = (ctypes.c_double * 3)()
+    _check(lib().dir_step(h.ptr, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
+                          *_dims(static), float(sigma), int(radius), _ptr(out), sums), "dir_step")
     return out, tuple(sums)
 
 

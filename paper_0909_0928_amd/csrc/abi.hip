@@ -18,8 +18,8 @@ namespace {
 thread_local std::string g_last_error;
 
 const char *const kKernelNames[K_COUNT] = {
-    "force", "warp", "warp_pair", "smooth_x", "smooth_y", "smooth_z", "finalize",
-    "level_reset", "restrict", "prolong", "gradient", "compose", "fill",
+    "force", "warp", "warp_pair", "smooth_yz", "smooth_x", "finalize", "level_reset",
+    "restrict", "prolong", "gradient", "compose", "fill",
 };
 
 // Device buffer that only grows.
@@ -58,7 +58,7 @@ struct dir_handle {
     hipStream_t stream = nullptr;
     Timer timer;
     DevBuf pyr_s, pyr_m;           // levels 1.. of the image pyramids, packed
-    DevBuf field[3];               // ping-pong fields, 3 planes each
+    DevBuf field[3];               // fields, 3 planes each: v and x-smoothed u; scratch for dir_smooth
     DevBuf img_a, img_b;           // deformed images (active, double, inverse-consistent)
     DevBuf partials;               // 3 doubles per force workgroup
     DevBuf history;                // 4 doubles per iteration, per-level fixed offsets
@@ -309,7 +309,7 @@ int32_t dir_warp(dir_handle *h, const float *d_vol, const float *d_field, int32_
     if (rc != DIR_OK) return rc;
     if (!d_vol || !d_field || !d_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     Ctx c{h->stream, &h->timer};
-    DIR_TRY(launch_warp(c, d_vol, d_field, Dims{nx, ny, nz}, d_out, nullptr));
+    DIR_TRY(launch_warp(c, d_vol, d_field, Dims{nx, ny, nz}, d_out, nullptr, 0));
     return DIR_OK;
 }
 
@@ -339,7 +339,9 @@ int32_t dir_smooth(dir_handle *h, const float *d_in, int32_t ncomp, int32_t nx, 
     if (in < out + bytes && out < in + bytes) return DIR_EINVAL;  // overlap
     DIR_TRY(h->field[2].ensure(sizeof(float) * 3 * (size_t)d.n()));
     Ctx c{h->stream, &h->timer};
-    DIR_TRY(launch_smooth(c, d_in, ncomp, d, make_taps(sigma, R), d_out, h->field[2].as<float>(), nullptr));
+    const GaussTaps taps = make_taps(sigma, R);
+    DIR_TRY(launch_smooth_x(c, d_in, ncomp, d, taps, h->field[2].as<float>()));
+    DIR_TRY(launch_smooth_yz(c, h->field[2].as<float>(), ncomp, d, taps, d_out, nullptr, 0, SumsReduce{}));
     return DIR_OK;
 }
 
@@ -392,17 +394,96 @@ int ensure_force_workspace(dir_handle *h, Dims d, int variant)
     return DIR_OK;
 }
 
-// One force evaluation: pre-warp where the variant needs deformed-image
-// gradients, then the force kernel (u = v + dr and workgroup sums).
-hipError_t force_step(dir_handle *h, Ctx &c, int variant, float alpha2, const float *S, const float *M,
-                      const float *v, Dims d, float *u, const int *stop)
+// Taps that leave a field unchanged (radius 0, weight 1).
+GaussTaps identity_taps()
+{
+    GaussTaps t;
+    memset(&t, 0, sizeof t);
+    t.radius = 0;
+    t.w[0] = 1.0f;
+    return t;
+}
+
+// The force half of one iteration: pre-warp where the variant needs
+// deformed-image gradients, then the force kernel (u = v + dr, x pass of the
+// smoothing with `taps`, per-workgroup sums).
+hipError_t force_half(dir_handle *h, Ctx &c, int variant, float alpha2, const float *S, const float *M,
+                      const float *v, Dims d, const GaussTaps &taps, float *out, const int *stop_at, int n)
 {
     float *Im = h->img_a.as<float>(), *Is = h->img_b.as<float>();
     hipError_t e = hipSuccess;
-    if (variant == kActive || variant == kDouble) e = launch_warp(c, M, v, d, Im, stop);
-    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, Im, Is, stop);
+    if (variant == kActive || variant == kDouble) e = launch_warp(c, M, v, d, Im, stop_at, n);
+    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, Im, Is, stop_at, n);
     if (e != hipSuccess) return e;
-    return launch_force(c, variant, alpha2, S, M, v, Im, Is, d, u, h->partials.as<double>(), stop);
+    ForceLaunch f;
+    f.variant = variant;
+    f.alpha2 = alpha2;
+    f.S = S;
+    f.M = M;
+    f.v = v;
+    f.Im = Im;
+    f.Is = Is;
+    f.d = d;
+    f.taps = &taps;
+    f.out = out;
+    f.partials = h->partials.as<double>();
+    f.stop_at = stop_at;
+    f.n = n;
+    return launch_force(c, f);
+}
+
+// Reduction descriptor for the sums of the force kernel at level size d.
+SumsReduce sums_reduce(dir_handle *h, Dims d, double *hist, LevelState *st, double eps)
+{
+    SumsReduce r;
+    r.partials = h->partials.as<double>();
+    r.nb = (int)force_blocks(d);
+    r.hist = hist;
+    r.st = st;
+    r.eps = eps;
+    r.inv_n = 1.0 / (double)d.n();
+    return r;
+}
+
+// dir_force and dir_step: one iteration outside a registration, sums out.
+int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, const float *M, const float *v,
+                int32_t nx, int32_t ny, int32_t nz, const GaussTaps *taps, float *out, double *sums)
+{
+    if (!S || !M || !v || !out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    if (variant < kPassive || variant > kInverseConsistent || !(alpha > 0.0) || !isfinite(alpha)) return DIR_EINVAL;
+    const Dims d{nx, ny, nz};
+    const size_t bytes = sizeof(float) * 3 * (size_t)d.n();
+    const char *vb = reinterpret_cast<const char *>(v), *ob = reinterpret_cast<const char *>(out);
+    if (vb < ob + bytes && ob < vb + bytes) return DIR_EINVAL;  // out must not overlap the field
+    int rc = ensure_force_workspace(h, d, variant);
+    if (rc != DIR_OK) return rc;
+    DIR_TRY(h->history.ensure(sizeof(double) * 4));
+    DIR_TRY(h->state.ensure(sizeof(LevelState)));
+    if (taps) DIR_TRY(h->field[2].ensure(bytes));
+    Ctx c{h->stream, &h->timer};
+    LevelState *st = h->state.as<LevelState>();
+    DIR_TRY(launch_level_reset(c, st));
+    SumsReduce red = sums_reduce(h, d, h->history.as<double>(), st, 0.0);
+    red.inv_n = 1.0;  // report the plain sum of D^2
+    if (taps) {
+        DIR_TRY(force_half(h, c, variant, (float)(alpha * alpha), S, M, v, d, *taps, h->field[2].as<float>(),
+                           nullptr, 0));
+        DIR_TRY(launch_smooth_yz(c, h->field[2].as<float>(), 3, d, *taps, out, nullptr, 0, red));
+    } else {
+        const GaussTaps id = identity_taps();
+        DIR_TRY(force_half(h, c, variant, (float)(alpha * alpha), S, M, v, d, id, out, nullptr, 0));
+        DIR_TRY(launch_finalize(c, red, 0));
+    }
+    rc = finish(h);
+    if (rc != DIR_OK) return rc;
+    if (sums) {
+        double e[4];
+        DIR_TRY(hipMemcpy(e, h->history.p, sizeof e, hipMemcpyDeviceToHost));
+        sums[0] = e[0];
+        sums[1] = e[1];
+        sums[2] = e[2];  // inv_n = 1: the plain sum of D^2
+    }
+    return DIR_OK;
 }
 
 }  // namespace
@@ -414,29 +495,20 @@ int32_t dir_force(dir_handle *h, int32_t variant, double alpha, const float *d_s
 {
     int rc = enter(h);
     if (rc != DIR_OK) return rc;
-    if (!d_static || !d_moving || !d_field || !d_updated || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
-    if (variant < kPassive || variant > kInverseConsistent || !(alpha > 0.0) || !isfinite(alpha)) return DIR_EINVAL;
-    if (d_updated == d_field) return DIR_EINVAL;
-    const Dims d{nx, ny, nz};
-    rc = ensure_force_workspace(h, d, variant);
+    return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, nullptr, d_updated, sums);
+}
+
+int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
+                 const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma, int32_t radius,
+                 float *d_field_out, double *sums)
+{
+    int rc = enter(h);
     if (rc != DIR_OK) return rc;
-    DIR_TRY(h->history.ensure(sizeof(double) * 4));
-    DIR_TRY(h->state.ensure(sizeof(LevelState)));
-    Ctx c{h->stream, &h->timer};
-    LevelState *st = h->state.as<LevelState>();
-    DIR_TRY(launch_level_reset(c, st));
-    DIR_TRY(force_step(h, c, variant, (float)(alpha * alpha), d_static, d_moving, d_field, d, d_updated, nullptr));
-    DIR_TRY(launch_finalize(c, h->partials.as<double>(), force_blocks(d), 1.0, h->history.as<double>(), 0, st, 0.0));
-    rc = finish(h);
-    if (rc != DIR_OK) return rc;
-    if (sums) {
-        double e[4];
-        DIR_TRY(hipMemcpy(e, h->history.p, sizeof e, hipMemcpyDeviceToHost));
-        sums[0] = e[0];
-        sums[1] = e[1];
-        sums[2] = e[2];  // inv_n = 1: the raw sum of D^2
-    }
-    return DIR_OK;
+    if (!(sigma > 0.0) || !isfinite(sigma)) return DIR_EINVAL;
+    const int R = resolve_radius(sigma, radius);
+    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+    const GaussTaps taps = make_taps(sigma, R);
+    return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, &taps, d_field_out, sums);
 }
 
 int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
@@ -489,8 +561,10 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
         DIR_TRY(h->pyr_m.ensure(sizeof(float) * pyr));
     }
     for (auto &f : h->field) DIR_TRY(f.ensure(sizeof(float) * 3 * n0));
-    rc = ensure_force_workspace(h, dims[0], variant);
-    if (rc != DIR_OK) return rc;
+    for (int k = 0; k < L; ++k) {  // sum slots: the largest level count
+        rc = ensure_force_workspace(h, dims[k], variant);
+        if (rc != DIR_OK) return rc;
+    }
     DIR_TRY(h->history.ensure(sizeof(double) * 4 * (size_t)(total_iters > 0 ? total_iters : 1)));
     DIR_TRY(h->state.ensure(sizeof(LevelState) * DIR_MAX_LEVELS));
 
@@ -511,7 +585,7 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
     }
 
     // ---- levels, coarse to fine (Sec 2.3) ----
-    float *v = h->field[0].as<float>(), *u = h->field[1].as<float>(), *tmp = h->field[2].as<float>();
+    float *v = h->field[0].as<float>(), *xs = h->field[1].as<float>();
     LevelState *states = h->state.as<LevelState>();
     double *hist = h->history.as<double>();
     int64_t hist_off[DIR_MAX_LEVELS];
@@ -521,26 +595,26 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
         const int li = L - 1 - k;
         const Dims d = dims[k];
         if (k < L - 1) {
-            DIR_TRY(launch_prolong(c, v, dims[k + 1], u, d));
+            DIR_TRY(launch_prolong(c, v, dims[k + 1], xs, d));
             float *t = v;
-            v = u;
-            u = t;
+            v = xs;
+            xs = t;
         }
         LevelState *st = states + li;
         DIR_TRY(launch_level_reset(c, st));
         hist_off[li] = off;
         const int iters = p->iters[li];
-        const double inv_n = 1.0 / (double)d.n();
-        const int64_t nb = force_blocks(d);
+        const SumsReduce red = sums_reduce(h, d, hist + 4 * off, st, p->eps);
         for (int n = 0; n < iters; ++n) {
-            DIR_TRY(force_step(h, c, variant, alpha2, Sk[k], Mk[k], v, d, u, &st->stop));
-            DIR_TRY(launch_smooth(c, u, 3, d, taps, v, tmp, &st->stop));
-            DIR_TRY(launch_finalize(c, h->partials.as<double>(), nb, inv_n, hist + 4 * off, n, st, p->eps));
+            // v -> xs = x-smoothed (v + dr) -> v = y,z-smoothed xs; the
+            // smoothing kernel also reduces the sums of this iteration
+            DIR_TRY(force_half(h, c, variant, alpha2, Sk[k], Mk[k], v, d, taps, xs, &st->stop_at, n));
+            DIR_TRY(launch_smooth_yz(c, xs, 3, d, taps, v, &st->stop_at, n, red));
             if (p->eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
-                int stop = 0;
-                DIR_TRY(hipMemcpyAsync(&stop, &st->stop, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+                int stop_at = kNeverStopped;
+                DIR_TRY(hipMemcpyAsync(&stop_at, &st->stop_at, sizeof(int), hipMemcpyDeviceToHost, h->stream));
                 DIR_TRY(hipStreamSynchronize(h->stream));
-                if (stop) break;
+                if (stop_at != kNeverStopped) break;
             }
         }
         off += iters;

@@ -1,0 +1,301 @@
+// Device helpers shared by the gfx950 kernels of libdemons, and the launch
+// helpers their host-side launchers use.  Internal header.
+//
+// Layout: float32 volumes [nz][ny][nx], x fastest; fields are three such
+// planes (x, y, z components) in voxel units.  Kernels map a 64-wide
+// wavefront along x so a row is read and written with coalesced accesses.
+#pragma once
+
+#include <math.h>
+
+#include "dir_internal.h"
+
+namespace dir {
+namespace dev {
+
+constexpr float kDenomFloor = 1e-9f;  // force is zero at or below this denominator
+
+__device__ __forceinline__ int clampi(int i, int n) { return min(max(i, 0), n - 1); }
+
+// Cell and weights along one axis for trilinear interpolation with the
+// coordinate clamped to [0, n-1] (Sec 2.5 interpolation kernel; explicit
+// weights, no hardware filtering).  The sample lies at i0 + t between i0 and
+// i1 = min(i0 + 1, n - 1); w0 = 1 - t is the weight of i0.  A clamped sample
+// sits exactly on i0 with t = 0, so border values are reproduced exactly.
+//
+// The sample position is x - v with x an integer grid index.  Forming x - v
+// in FP32 would round it to the ulp of x (7.6e-6 voxel at x = 100); instead v
+// is split into floor(v) (exact) and r = v - floor(v) (exact for |v| < 2^23):
+// the cell index is integer arithmetic, w0 = r is exact, and t = 1 - r is
+// exact in FP64 (one rounding of at most 2^-25 in FP32).  v is first limited
+// to +-2^20 (NaN becomes -2^20), which keeps every index inside the grid.
+struct Axis {
+    int i0, i1;
+    float t, w0;
+};
+
+__device__ __forceinline__ Axis axis_disp(int x, float v, int n)
+{
+    v = fminf(fmaxf(v, -1048576.0f), 1048576.0f);
+    const float fv = floorf(v);
+    const float r = v - fv;
+    int i = x - (int)fv;  // p = x - v = i - r
+    Axis a;
+    a.t = 0.0f;
+    a.w0 = 1.0f;
+    if (r > 0.0f) {
+        i -= 1;
+        a.t = 1.0f - r;
+        a.w0 = r;
+    }
+    if (i < 0 || i > n - 1) {  // outside: clamp onto the border sample
+        i = i < 0 ? 0 : n - 1;
+        a.t = 0.0f;
+        a.w0 = 1.0f;
+    } else if (i == n - 1) {   // p in (n-1, n) would need the next cell: clamp
+        a.t = 0.0f;
+        a.w0 = 1.0f;
+    }
+    a.i0 = i;
+    a.i1 = min(i + 1, n - 1);
+    return a;
+}
+
+// Same for an FP32 coordinate p that is exact as given (prolongation).
+__device__ __forceinline__ Axis axis_coord(float p, int n)
+{
+    p = fminf(fmaxf(p, 0.0f), (float)(n - 1));
+    Axis a;
+    a.i0 = min((int)p, n - 1);  // p >= 0, so truncation is floor
+    a.i1 = min(a.i0 + 1, n - 1);
+    a.t = p - (float)a.i0;      // exact: p carries few fraction bits
+    a.w0 = 1.0f - a.t;
+    return a;
+}
+
+struct Cell {
+    int o000, o100, o010, o110, o001, o101, o011, o111;
+    float tx, ty, tz;     // FP32 fractional positions
+    float wx, wy, wz;     // exact weights of the lower index
+};
+
+__device__ __forceinline__ Cell make_cell_axes(const Axis &ax, const Axis &ay, const Axis &az, int nx, int ny)
+{
+    Cell c;
+    const int r00 = nx * (ay.i0 + ny * az.i0), r10 = nx * (ay.i1 + ny * az.i0);
+    const int r01 = nx * (ay.i0 + ny * az.i1), r11 = nx * (ay.i1 + ny * az.i1);
+    c.o000 = r00 + ax.i0;
+    c.o100 = r00 + ax.i1;
+    c.o010 = r10 + ax.i0;
+    c.o110 = r10 + ax.i1;
+    c.o001 = r01 + ax.i0;
+    c.o101 = r01 + ax.i1;
+    c.o011 = r11 + ax.i0;
+    c.o111 = r11 + ax.i1;
+    c.tx = ax.t;
+    c.ty = ay.t;
+    c.tz = az.t;
+    c.wx = ax.w0;
+    c.wy = ay.w0;
+    c.wz = az.w0;
+    return c;
+}
+
+// Cell of the position (x, y, z) - (vx, vy, vz).
+__device__ __forceinline__ Cell make_cell_disp(int x, int y, int z, float vx, float vy, float vz, int nx, int ny,
+                                               int nz)
+{
+    return make_cell_axes(axis_disp(x, vx, nx), axis_disp(y, vy, ny), axis_disp(z, vz, nz), nx, ny);
+}
+
+__device__ __forceinline__ Cell make_cell(float px, float py, float pz, int nx, int ny, int nz)
+{
+    return make_cell_axes(axis_coord(px, nx), axis_coord(py, ny), axis_coord(pz, nz), nx, ny);
+}
+
+__device__ __forceinline__ float lerp1(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// FP32 trilinear sample.
+__device__ __forceinline__ float sample(const float *__restrict__ I, const Cell &c)
+{
+    const float c00 = lerp1(I[c.o000], I[c.o100], c.tx);
+    const float c10 = lerp1(I[c.o010], I[c.o110], c.tx);
+    const float c01 = lerp1(I[c.o001], I[c.o101], c.tx);
+    const float c11 = lerp1(I[c.o011], I[c.o111], c.tx);
+    return lerp1(lerp1(c00, c10, c.ty), lerp1(c01, c11, c.ty), c.tz);
+}
+
+// FP64 trilinear sample with exact weights.  Used where the sample enters an
+// intensity difference: D = Im - S cancels to a few HU on a -1000 HU
+// background, and the force's relative error is D's relative error.  FP64 FMA
+// issues at the same rate as unpacked FP32 on gfx950.
+__device__ __forceinline__ double sample64(const float *__restrict__ I, const Cell &c)
+{
+    const double ax = c.wx, bx = 1.0 - ax, ay = c.wy, by = 1.0 - ay, az = c.wz, bz = 1.0 - az;
+    const double c00 = ax * (double)I[c.o000] + bx * (double)I[c.o100];
+    const double c10 = ax * (double)I[c.o010] + bx * (double)I[c.o110];
+    const double c01 = ax * (double)I[c.o001] + bx * (double)I[c.o101];
+    const double c11 = ax * (double)I[c.o011] + bx * (double)I[c.o111];
+    return az * (ay * c00 + by * c10) + bz * (ay * c01 + by * c11);
+}
+
+// Decode a flattened workgroup id into (tile x, tile y, z).
+struct Tile {
+    int x, y, z;
+};
+__device__ __forceinline__ Tile decode_tile(int gx, int gy)
+{
+    const int b = blockIdx.x;
+    Tile t;
+    t.x = b % gx;
+    const int r = b / gx;
+    t.y = r % gy;
+    t.z = r / gy;
+    return t;
+}
+
+// Central difference with clamped neighbours (Sec 2.5 gradient kernel).
+__device__ __forceinline__ void central_diff(const float *__restrict__ I, int x, int y, int z, int nx, int ny, int nz,
+                                             float &gx, float &gy, float &gz)
+{
+    const int row = nx * (y + ny * z);
+    gx = 0.5f * (I[row + min(x + 1, nx - 1)] - I[row + max(x - 1, 0)]);
+    gy = 0.5f * (I[nx * (min(y + 1, ny - 1) + ny * z) + x] - I[nx * (max(y - 1, 0) + ny * z) + x]);
+    gz = 0.5f * (I[nx * (y + ny * min(z + 1, nz - 1)) + x] - I[nx * (y + ny * max(z - 1, 0)) + x]);
+}
+
+// Demons term D g / (alpha^2 D^2 + |g|^2) (Eqs 1, 3, 6; alpha of Eq 5).
+__device__ __forceinline__ void demons_term(float D, float gx, float gy, float gz, float alpha2, float &fx, float &fy,
+                                            float &fz)
+{
+    const float den = fmaf(alpha2 * D, D, fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+    if (den <= kDenomFloor) {
+        fx = fy = fz = 0.0f;
+        return;
+    }
+    const float s = D / den;
+    fx = s * gx;
+    fy = s * gy;
+    fz = s * gz;
+}
+
+// Evolved passive force, Eq 2, with both gradient magnitudes squared in the
+// second denominator factor; a = |grad| of the undeformed moving image.
+__device__ __forceinline__ void evolved_term(float D, float gx, float gy, float gz, float a, float &fx, float &fy,
+                                             float &fz)
+{
+    const float G2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+    const float a2 = a * a;
+    const float den = (fmaf(2.0f * D, D, G2 + a2)) * (G2 + a2);
+    if (den <= kDenomFloor) {
+        fx = fy = fz = 0.0f;
+        return;
+    }
+    const float s = 4.0f * D * sqrtf(G2) * a / den;
+    fx = s * gx;
+    fy = s * gy;
+    fz = s * gz;
+}
+
+// Sum of three doubles over a 256-thread workgroup in a fixed order (xor
+// butterfly within each wavefront, then the four wavefronts in order);
+// result valid in thread 0.  `tid` is the flat thread index.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, int tid)
+{
+    __shared__ double red[3][kBlockX * kBlockY / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+        red[2][wave] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        a = red[0][0];
+        b = red[1][0];
+        c = red[2][0];
+        for (int w = 1; w < kBlockX * kBlockY / 64; ++w) {
+            a += red[0][w];
+            b += red[1][w];
+            c += red[2][w];
+        }
+    }
+}
+
+
+// Reduction of the force kernel's per-workgroup sums (slots s1[nb], s2[nb],
+// sse[nb]) by one 256-thread workgroup: strided partial sums per thread, then
+// the fixed-order workgroup sum, so the result is bitwise reproducible.
+// Thread 0 writes history entry n of the level (sum|dr|, sum|v|, mean D^2,
+// relative norm l = sum|dr| / sum|v|, NaN while sum|v| = 0), the iteration
+// count, and applies the stopping rule of Sec 2.4: once n >= 10 and
+// l(n-10) - l(n) <= eps the level stops after iteration n.
+__device__ __forceinline__ void reduce_sums(const double *__restrict__ partials, int nb, double *hist, int n,
+                                            LevelState *st, double eps, double inv_n, int tid)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = tid; k < nb; k += 256) {
+        a += partials[k];
+        b += partials[nb + k];
+        c += partials[2 * nb + k];
+    }
+    block_sum3(a, b, c, tid);
+    if (tid == 0) {
+        const double l = b > 0.0 ? a / b : __builtin_nan("");
+        double *e = hist + 4 * (int64_t)n;
+        e[0] = a;
+        e[1] = b;
+        e[2] = c * inv_n;
+        e[3] = l;
+        st->iters_run = n + 1;
+        if (eps > 0.0 && n >= 10) {
+            const double l10 = hist[4 * (int64_t)(n - 10) + 3];
+            if (!isnan(l) && !isnan(l10) && l10 - l <= eps) st->stop_at = n;
+        }
+    }
+}
+
+}  // namespace dev
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers
+// ---------------------------------------------------------------------------
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+struct Grid2 {
+    int gx, gy;
+    int64_t blocks;
+};
+
+// One 64 x 4 workgroup per (x tile, y tile, z) of a volume.
+inline Grid2 plane_grid(Dims d)
+{
+    Grid2 g;
+    g.gx = ceil_div(d.nx, kBlockX);
+    g.gy = ceil_div(d.ny, kBlockY);
+    g.blocks = (int64_t)g.gx * g.gy * d.nz;
+    return g;
+}
+
+// Launch through `launch`, bracketed by timing events when kernel k is timed.
+template <typename F>
+hipError_t timed(Ctx &c, int k, F &&launch)
+{
+    hipEvent_t a = nullptr;
+    if (c.timer && c.timer->on(k)) {
+        hipError_t e = c.timer->begin(k, c.stream, &a);
+        if (e != hipSuccess) return e;
+    }
+    launch();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a) return c.timer->end(k, c.stream, a);
+    return hipSuccess;
+}
+
+}  // namespace dir

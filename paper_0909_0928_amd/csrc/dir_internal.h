@@ -12,20 +12,18 @@ namespace dir {
 constexpr int kMaxRadius = 16;
 constexpr int kBlockX = 64;   // one wavefront along x
 constexpr int kBlockY = 4;    // four wavefronts per workgroup
-constexpr int kFinalizeThreads = 256;
 
 // Variant codes, numerically equal to dir_variant.
 enum Variant { kPassive = 0, kEvolved = 1, kActive = 2, kDouble = 3, kInverseConsistent = 4 };
 
 // Kernel ids for event timing; names in kKernelNames (abi.hip).
 enum KernelId {
-    K_FORCE = 0,
-    K_WARP,
-    K_WARP_PAIR,
-    K_SMOOTH_X,
-    K_SMOOTH_Y,
-    K_SMOOTH_Z,
-    K_FINALIZE,
+    K_FORCE = 0,     // force + x pass of the smoothing + sums (+ last-workgroup reduction)
+    K_WARP,          // deformed moving image (active, double force)
+    K_WARP_PAIR,     // deformed moving and static images (inverse-consistent)
+    K_SMOOTH_YZ,     // y and z passes of the smoothing
+    K_SMOOTH_X,      // standalone x pass (dir_smooth)
+    K_FINALIZE,      // standalone reduction of the sums (dir_force)
     K_LEVEL_RESET,
     K_RESTRICT,
     K_PROLONG,
@@ -46,10 +44,23 @@ struct GaussTaps {
     int radius;
 };
 
+constexpr int kNeverStopped = 0x7fffffff;
+
 // Device-side state of one resolution level (stopping rule of Sec 2.4).
 struct LevelState {
-    int stop;        // set by the finalize kernel once the rule fires
-    int iters_run;   // iterations completed at this level
+    int stop_at;        // iteration at which the rule fired (kNeverStopped if not)
+    int iters_run;      // iterations completed at this level
+};
+
+// Where the per-iteration FP64 sums of the force kernel are reduced: the
+// kernel that runs next (the y/z smoothing, or the standalone finalize)
+// dedicates one workgroup to it.
+struct SumsReduce {
+    const double *partials;  // 3 * nb doubles, or NULL: nothing to reduce
+    int nb;
+    double *hist;            // level history; entry n at hist[4n]
+    LevelState *st;
+    double eps, inv_n;
 };
 
 // Per-kernel HIP-event timing.  Events are recycled from a pool; pairs are
@@ -83,23 +94,35 @@ struct Ctx {
     Timer *timer;
 };
 
-// Number of workgroups the force kernel launches for a level (one partial
-// sum triple per workgroup).
+// Number of workgroups (and FP64 sum slots) of the force kernel for a level.
 int64_t force_blocks(Dims d);
 
-// ---- launchers (kernels.hip); each returns the launch status -------------
+// One force-kernel launch: u = v + dr (Eqs 1-6), its x-smoothing with `taps`
+// (identity taps give u), and the per-workgroup FP64 sums.
+struct ForceLaunch {
+    int variant;
+    float alpha2;
+    const float *S, *M, *v, *Im, *Is;
+    Dims d;
+    const GaussTaps *taps;
+    float *out;
+    double *partials;     // 3 * force_blocks(d) doubles
+    const int *stop_at;   // skip when *stop_at < n (NULL: never)
+    int n;
+};
+
+// ---- launchers; each returns the launch status ----------------------------
 hipError_t launch_restrict(Ctx &c, const float *in, Dims fine, float *out, Dims coarse);
 hipError_t launch_prolong(Ctx &c, const float *vc, Dims coarse, float *vf, Dims fine);
 hipError_t launch_gradient(Ctx &c, const float *img, Dims d, float *grad);
-hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, float *out, const int *stop);
+hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, float *out, const int *stop_at, int n);
 hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *Im, float *Is,
-                            const int *stop);
-hipError_t launch_force(Ctx &c, int variant, float alpha2, const float *S, const float *M, const float *v,
-                        const float *Im, const float *Is, Dims d, float *u, double *partials, const int *stop);
-hipError_t launch_smooth(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out, float *tmp,
-                         const int *stop);
-hipError_t launch_finalize(Ctx &c, const double *partials, int64_t nblocks, double inv_n, double *hist_level, int n,
-                           LevelState *st, double eps);
+                            const int *stop_at, int n);
+hipError_t launch_force(Ctx &c, const ForceLaunch &f);
+hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out);
+hipError_t launch_smooth_yz(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out,
+                            const int *stop_at, int n, const SumsReduce &red);
+hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n);
 hipError_t launch_level_reset(Ctx &c, LevelState *st);
 hipError_t launch_compose(Ctx &c, const float *h, Dims d, int K, float *out);
 hipError_t launch_zero(Ctx &c, float *p, int64_t n);

@@ -1,0 +1,181 @@
+// gfx950 kernels of the separable Gaussian smoothing (Sec 2.1 regularisation;
+// Sec 2.5 low-pass filter, separable in x, y and z).
+//
+// The x pass runs fused into the force kernel during registration; the
+// standalone x pass here serves dir_smooth.  The y and z passes are fused in
+// one kernel (z pass into LDS, then y pass out of LDS); each field component
+// has its own workgroups.
+#include "device_common.h"
+
+namespace dir {
+namespace {
+
+using namespace dev;
+
+constexpr int kRowsPerThread = 4;
+constexpr int kTileY = kBlockY * kRowsPerThread;  // 16 rows per workgroup
+
+// x pass: each wavefront stages its row segment plus a radius-R halo in LDS.
+__global__ __launch_bounds__(256) void k_smooth_x(const float *__restrict__ in, float *__restrict__ out, int ncomp,
+                                                  int nx, int ny, int nz, GaussTaps taps, int gx, int gy)
+{
+    __shared__ float row[kBlockY][kBlockX + 2 * kMaxRadius];
+    const Tile t = decode_tile(gx, gy);
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x0 = t.x * kBlockX, x = x0 + tx, y = t.y * kBlockY + ty, z = t.z;
+    const int R = taps.radius;
+    const int N = nx * ny * nz;
+    const bool row_ok = y < ny;
+    for (int c = 0; c < ncomp; ++c) {
+        const float *src = in + (int64_t)c * N + nx * (y + ny * z);
+        if (row_ok)
+            for (int j = tx; j < kBlockX + 2 * R; j += kBlockX) row[ty][j] = src[clampi(x0 - R + j, nx)];
+        __syncthreads();
+        if (row_ok && x < nx) {
+            float s = 0.0f;
+            for (int j = 0; j <= 2 * R; ++j) s = fmaf(taps.w[j], row[ty][tx + j], s);
+            out[(int64_t)c * N + nx * (y + ny * z) + x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// z then y within one workgroup: tile of 64 (x) x kTileY (y) x TZ (z) of one
+// field component.  Phase 1: every thread slides a register window of
+// TZ + 2R samples along z for one (x, y) column of the tile plus its y halo
+// (rows clamped) and writes the TZ z-smoothed values to LDS.  Phase 2: every
+// thread forms 4 consecutive y outputs of one x column for each of the TZ
+// planes from 4 + 2R LDS values.
+template <int R, int TZ>
+struct YZTile {
+    static constexpr int ROWS = kTileY + 2 * R;  // tile rows plus y halo
+    static_assert(TZ * ROWS * kBlockX * 4 <= 65536, "LDS tile above 64 KB");
+};
+
+// Deepest z chunk (8 or 4 planes) whose LDS tile fits in 64 KB.
+template <int R>
+constexpr int max_tz()
+{
+    return (kTileY + 2 * R) * kBlockX * 4 * 8 <= 65536 ? 8 : 4;
+}
+
+// With red.partials set, workgroup 0 instead adds up the FP64 sums the force
+// kernel of this iteration left per workgroup (they are complete: that kernel
+// has finished), writes the history entry and takes the stopping decision;
+// the smoothing tiles are workgroups 1 and up.
+template <int R, int TZ>
+__global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in, float *__restrict__ out, int nx,
+                                                   int ny, int nz, GaussTaps taps, int gx, int gy, int gz,
+                                                   const int *__restrict__ stop_at, int n, SumsReduce red)
+{
+    constexpr int ROWS = YZTile<R, TZ>::ROWS;
+    __shared__ float zs[TZ][ROWS][kBlockX];
+    if (stop_at && *stop_at < n) return;
+    const int tid = threadIdx.x + kBlockX * threadIdx.y;
+    int b = blockIdx.x;
+    if (red.partials) {
+        if (b == 0) {
+            reduce_sums(red.partials, red.nb, red.hist, n, red.st, red.eps, red.inv_n, tid);
+            return;
+        }
+        b -= 1;
+    }
+    // workgroup id -> (x tile, y tile, z chunk, component)
+    const int tx = b % gx, r1 = b / gx, ty = r1 % gy, r2 = r1 / gy, tz = r2 % gz, c = r2 / gz;
+    const int lane = threadIdx.x, wave = threadIdx.y;
+    const int x = min(tx * kBlockX + lane, nx - 1);  // lanes past the edge repeat the last column
+    const int y_base = ty * kTileY, z0 = tz * TZ;
+    const size_t plane = (size_t)nx * ny;
+    const float *src = in + (size_t)c * plane * nz;
+    float w[2 * R + 1];
+#pragma unroll
+    for (int j = 0; j <= 2 * R; ++j) w[j] = taps.w[j];
+
+    // phase 1: z pass for rows y_base - R .. y_base + kTileY + R - 1
+    for (int row = wave; row < ROWS; row += kBlockY) {
+        const float *col = src + (size_t)nx * clampi(y_base - R + row, ny) + x;
+        float win[TZ + 2 * R];
+#pragma unroll
+        for (int k = 0; k < TZ + 2 * R; ++k) win[k] = col[(size_t)clampi(z0 - R + k, nz) * plane];
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+            float s = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], win[k + j], s);
+            zs[k][row][lane] = s;
+        }
+    }
+    __syncthreads();
+
+    // phase 2: y pass, rows y_base + 4 * wave .. + 3
+    const int xo = tx * kBlockX + lane;
+    const int y0 = y_base + wave * kRowsPerThread;
+    if (xo >= nx || y0 >= ny) return;
+    float *dst = out + (size_t)c * plane * nz + xo;
+    for (int k = 0; k < TZ; ++k) {
+        if (z0 + k >= nz) break;
+        float v[kRowsPerThread + 2 * R];
+#pragma unroll
+        for (int j = 0; j < kRowsPerThread + 2 * R; ++j) v[j] = zs[k][wave * kRowsPerThread + j][lane];
+#pragma unroll
+        for (int q = 0; q < kRowsPerThread; ++q) {
+            float s = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], v[q + j], s);
+            if (y0 + q < ny) dst[(size_t)(z0 + k) * plane + (size_t)(y0 + q) * nx] = s;
+        }
+    }
+}
+
+template <int R, int TZ>
+void launch_yz_tz(Ctx &c, const float *in, float *out, int ncomp, Dims d, const GaussTaps &taps, const int *stop_at,
+                  int n, const SumsReduce &red)
+{
+    const int gx = ceil_div(d.nx, kBlockX), gy = ceil_div(d.ny, kTileY), gz = ceil_div(d.nz, TZ);
+    const int64_t blocks = (int64_t)gx * gy * gz * ncomp + (red.partials ? 1 : 0);
+    hipLaunchKernelGGL((k_smooth_yz<R, TZ>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), 0, c.stream, in, out,
+                       d.nx, d.ny, d.nz, taps, gx, gy, gz, stop_at, n, red);
+}
+
+// Workgroups to aim for before the z chunk is made deeper (each chunk re-reads
+// 2R halo planes, so deeper chunks cost fewer loads per output).
+constexpr int64_t kYZTargetBlocks = 1024;
+
+template <int R>
+hipError_t launch_yz_r(Ctx &c, const float *in, float *out, int ncomp, Dims d, const GaussTaps &taps,
+                       const int *stop_at, int n, const SumsReduce &red)
+{
+    const int64_t tiles = (int64_t)ceil_div(d.nx, kBlockX) * ceil_div(d.ny, kTileY) * ncomp;
+    const bool deep = max_tz<R>() == 8 && tiles * ceil_div(d.nz, 8) >= kYZTargetBlocks;
+    return timed(c, K_SMOOTH_YZ, [&] {
+        if (deep) launch_yz_tz<R, max_tz<R>()>(c, in, out, ncomp, d, taps, stop_at, n, red);
+        else if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4>(c, in, out, ncomp, d, taps, stop_at, n, red);
+        else launch_yz_tz<R, 2>(c, in, out, ncomp, d, taps, stop_at, n, red);
+    });
+}
+
+}  // namespace
+
+hipError_t launch_smooth_yz(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out,
+                            const int *stop_at, int n, const SumsReduce &red)
+{
+    switch (taps.radius) {
+#define DIR_R(r) \
+    case r: return launch_yz_r<r>(c, in, out, ncomp, d, taps, stop_at, n, red);
+        DIR_R(0) DIR_R(1) DIR_R(2) DIR_R(3) DIR_R(4) DIR_R(5) DIR_R(6) DIR_R(7) DIR_R(8)
+        DIR_R(9) DIR_R(10) DIR_R(11) DIR_R(12) DIR_R(13) DIR_R(14) DIR_R(15) DIR_R(16)
+#undef DIR_R
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out)
+{
+    const Grid2 g = plane_grid(d);
+    return timed(c, K_SMOOTH_X, [&] {
+        hipLaunchKernelGGL(k_smooth_x, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, in, out, ncomp,
+                           d.nx, d.ny, d.nz, taps, g.gx, g.gy);
+    });
+}
+
+}  // namespace dir

@@ -34,6 +34,8 @@ N_BLOBS = 20
 N_FIELD_BUMPS = 8
 LIPSCHITZ_LIMIT = 0.8
 REDRAW_SEED_STEP = 10 ** 6
+MAX_REDRAWS = 100
+MIN_WIDTH_AXIS = 16           # axes shorter than this do not set the field's width
 
 
 @dataclasses.dataclass
@@ -167,13 +169,16 @@ def make_phantom(shape, seed, max_u, spacing_mm=(1.0, 1.0, 1.0), noise_hu=10.0) 
     redraws = 0
     field_rng = rng
     pz, py, px = _grid((nx, ny, nz))
+    # bump width: 0.3 x the shortest axis, ignoring thin axes of a slab-like volume
+    long_axes = [d for d in (nx, ny, nz) if d >= MIN_WIDTH_AXIS]
+    width = 0.3 * float(min(long_axes) if long_axes else max(nx, ny, nz))
     while True:
         bumps = []
         for _ in range(N_FIELD_BUMPS):
             c = field_rng.uniform(np.zeros(3), n - 1.0)
             a = field_rng.normal(size=3)
             bumps.append((c, a))
-        params = {"s": 0.3 * float(min(nx, ny, nz)), "A": 1.0, "bumps": bumps}
+        params = {"s": width, "A": 1.0, "bumps": bumps}
         g = np.stack(_field_analytic(params, px, py, pz))
         gmax = float(np.sqrt((g * g).sum(axis=0)).max())
         params["A"] = max_u / gmax if gmax > 0 else 0.0
@@ -182,6 +187,9 @@ def make_phantom(shape, seed, max_u, spacing_mm=(1.0, 1.0, 1.0), noise_hu=10.0) 
         if lip < LIPSCHITZ_LIMIT:
             break
         redraws += 1
+        if redraws > MAX_REDRAWS:
+            raise ValueError(f"no field with Lipschitz constant < {LIPSCHITZ_LIMIT} for shape {shape}, "
+                             f"max_u {max_u}")
         field_rng = np.random.default_rng(seed + REDRAW_SEED_STEP * redraws)
 
     full = {"body_c": centre, "body_a": body_a, "lung_c": lung_c, "lung_a": lung_a, "blobs": blobs}

@@ -138,6 +138,24 @@ def test_force(B, h, shape3, variant, alpha):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
 
+STEP_SHAPES = [(11, 13, 17), (9, 33, 65), (20, 40, 72), (7, 30, 129), (2, 3, 300)]
+
+
+@pytest.mark.parametrize("shape3", STEP_SHAPES)
+@pytest.mark.parametrize("variant", ALL)
+@pytest.mark.parametrize("sigma,radius", [(1.0, 3), (1.5, 5)])
+def test_step(B, h, shape3, variant, sigma, radius):
+    """One iteration exactly as the registration runs it: G * (v + dr)."""
+    S, M, v = _pair(shape3, 13)
+    alpha = 0.4 if variant == "double" else 1.0
+    out, sums_gpu = B.dir_step(h, variant, alpha, dev(S), dev(M), dev(v), sigma, radius)
+    u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=alpha)
+    ref = O.smooth(u_ref, sigma, radius)
+    assert rel(host(out) - v, ref - v) < REL_TOL
+    for k in range(3):
+        assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
+
+
 @pytest.mark.parametrize("shape3", [(11, 13, 17), (9, 33, 65)])
 @pytest.mark.parametrize("K", [0, 1, 10])
 def test_compose(B, h, shape3, K):
@@ -164,6 +182,19 @@ def test_full_size_warp_smooth(B, h, full_pair):
     assert rel(host(B.dir_warp(h, dev(M), dev(v))), O.warp(M, v)) < REL_TOL
     _say("full-size smooth 256x256x100 sigma 1.5 R 5")
     assert rel(host(B.dir_smooth(h, dev(v), 1.5, 5)), O.smooth(v, 1.5, 5)) < REL_TOL
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("variant", ALL)
+def test_full_size_step(B, h, full_pair, variant):
+    S, M, v = full_pair
+    _say(f"full-size step {variant} 256x256x100 sigma 1.5 R 5")
+    out, sums_gpu = B.dir_step(h, variant, 1.0, dev(S), dev(M), dev(v), 1.5, 5)
+    u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v)
+    ref = O.smooth(u_ref, 1.5, 5)
+    assert rel(host(out) - v, ref - v) < REL_TOL
+    for k in range(3):
+        assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k])
 
 
 @pytest.mark.slow
@@ -195,29 +226,70 @@ def test_small_config_passive_end_to_end(B, h):
     err_ref = float(np.sqrt(((ref - vt) ** 2).sum(axis=0))[ph.body].mean())
     _say(f"small passive: rms(gpu-oracle)={d:.2e} vox; mean GT error gpu {err_gpu:.4f} oracle {err_ref:.4f} vox")
     assert d <= RMS_TOL_VOX
+    assert abs(err_gpu - err_ref) <= 0.01
     assert stats["iters_run"] == [50]
     hg = np.array(stats["history"])
-    assert np.allclose(hg[:, :3], hist[:, :3], rtol=1e-4, atol=1e-9)
+    # the first iterations agree to FP32 accuracy; later ones drift apart by
+    # the rounding envelope of the iteration (about 5e-3 voxel RMS here)
+    assert np.allclose(hg[:5, :3], hist[:5, :3], rtol=1e-5, atol=1e-9)
+    assert np.allclose(hg[:, :3], hist[:, :3], rtol=2e-2, atol=1e-9)
 
 
-CASES = [("passive", 1.0), ("evolved", 1.0), ("active", 1.0), ("double", 1.0), ("passive", 0.4), ("double", 0.4),
-         ("active", 0.4), ("double", 2.0), ("inverse_consistent", 1.0)]
+# Settings whose result moves by well under 0.01 voxel RMS when the inputs are
+# perturbed at FP32 rounding level: GPU and oracle must agree to 0.01 voxel.
+WELL_CONDITIONED = [("passive", 1.0), ("evolved", 1.0), ("active", 1.0), ("double", 1.0), ("active", 0.4),
+                    ("double", 2.0), ("inverse_consistent", 1.0)]
+# Settings where the oracle itself moves by 0.015-0.04 voxel RMS under such
+# perturbations (alpha = 0.4 lets noise-driven steps of up to 1.25 voxels
+# through): the GPU must lie inside that rounding envelope.
+ILL_CONDITIONED = [("passive", 0.4), ("double", 0.4)]
+ITERS_SMALL = [20, 10, 5]
 
 
-@pytest.mark.parametrize("variant,alpha", CASES)
-def test_multilevel_end_to_end(B, h, variant, alpha):
-    """A reduced 3-level case with the full-size construction (ragged dims)."""
+@pytest.fixture(scope="module")
+def multilevel_pair():
     nz, ny, nx = 27, 75, 90
     ph = P.make_phantom((nx, ny, nz), seed=21, max_u=5.0, spacing_mm=(1.1, 1.1, 2.5))
-    S, M = f32(ph.static).astype(np.float64), f32(ph.moving).astype(np.float64)
-    iters = [20, 10, 5]
-    params = B.make_params(variant, iters, sigma=1.5, alpha=alpha)
+    return ph, f32(ph.static).astype(np.float64), f32(ph.moving).astype(np.float64)
+
+
+@pytest.mark.parametrize("variant,alpha", WELL_CONDITIONED)
+def test_multilevel_end_to_end(B, h, multilevel_pair, variant, alpha):
+    """A reduced 3-level case with the full-size construction (ragged dims)."""
+    ph, S, M = multilevel_pair
+    params = B.make_params(variant, ITERS_SMALL, sigma=1.5, alpha=alpha)
     field, stats = B.dir_register(h, dev(S), dev(M), params)
-    ref, hist, runs, rc = O.register(S, M, O.VARIANTS[variant], iters, sigma=1.5, alpha=alpha)
+    ref, hist, runs, rc = O.register(S, M, O.VARIANTS[variant], ITERS_SMALL, sigma=1.5, alpha=alpha)
     d = rms_vox(host(field), ref)
     _say(f"{variant} alpha={alpha}: rms(gpu-oracle)={d:.2e} vox")
     assert d <= RMS_TOL_VOX
-    assert stats["iters_run"] == iters
+    assert stats["iters_run"] == ITERS_SMALL
+    # Coarse levels start from FP32-stored restricted images, whose rounding
+    # (~3e-5 HU) reaches the force through voxels with a near-zero intensity
+    # difference: the first sums agree to ~5e-5 rather than to 1e-7.
+    hg = np.array(stats["history"])
+    assert np.allclose(hg[:3, :3], hist[:3, :3], rtol=1e-3, atol=1e-9)
+
+
+@pytest.mark.parametrize("variant,alpha", ILL_CONDITIONED)
+def test_multilevel_within_rounding_envelope(B, h, multilevel_pair, variant, alpha):
+    ph, S, M = multilevel_pair
+    params = B.make_params(variant, ITERS_SMALL, sigma=1.5, alpha=alpha)
+    got = host(B.dir_register(h, dev(S), dev(M), params)[0])
+    ref, _, _, _ = O.register(S, M, O.VARIANTS[variant], ITERS_SMALL, sigma=1.5, alpha=alpha)
+    rng = np.random.default_rng(99)
+    Sp = S * (1 + rng.uniform(-6e-8, 6e-8, S.shape))
+    Mp = M * (1 + rng.uniform(-6e-8, 6e-8, M.shape))
+    pert, _, _, _ = O.register(Sp, Mp, O.VARIANTS[variant], ITERS_SMALL, sigma=1.5, alpha=alpha)
+    env = rms_vox(pert, ref)
+    d = rms_vox(got, ref)
+    vt, _ = ph.ground_truth()
+    e_gpu = float(np.sqrt(((got - vt) ** 2).sum(axis=0))[ph.body].mean())
+    e_ref = float(np.sqrt(((ref - vt) ** 2).sum(axis=0))[ph.body].mean())
+    _say(f"{variant} alpha={alpha}: rms(gpu-oracle)={d:.2e}, oracle envelope {env:.2e}, "
+         f"GT error gpu {e_gpu:.4f} oracle {e_ref:.4f} vox")
+    assert d <= max(RMS_TOL_VOX, 3.0 * env)
+    assert abs(e_gpu - e_ref) <= 0.01
 
 
 @pytest.mark.parametrize("variant", ALL)
