@@ -22,7 +22,8 @@
  *   - Out-of-grid samples clamp the coordinate; stencils clamp the index.
  *   - Pointers named d_* are DEVICE pointers on the handle's device, owned by
  *     the caller; host pointers are named without the prefix.
- *   - 3 * nx*ny*nz must be below 2^31.
+ *   - nx*ny*nz must be at most 357,913,941 (a field of 12 bytes per voxel
+ *     stays below 4 GiB); larger sizes return DIR_EINVAL.
  *   - All device work is enqueued on the handle's stream.  dir_register and
  *     dir_force block until their work is complete; the other entry points
  *     only enqueue (call dir_synchronize before reading their outputs on the

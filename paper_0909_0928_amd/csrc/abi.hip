@@ -59,7 +59,7 @@ struct dir_handle {
     Timer timer;
     DevBuf pyr_s, pyr_m;           // levels 1.. of the image pyramids, packed
     DevBuf field[3];               // fields, 3 planes each: v and x-smoothed u; scratch for dir_smooth
-    DevBuf img_a, img_b;           // deformed images (active, double, inverse-consistent)
+    DevBuf img_a, img_b;           // pre-warped D (active, double, IC) and P = Im + Is (IC)
     DevBuf partials;               // 3 doubles per force workgroup
     DevBuf history;                // 4 doubles per iteration, per-level fixed offsets
     DevBuf state;                  // one LevelState per level
@@ -81,11 +81,13 @@ int fail_hip(hipError_t e, const char *what)
         if (_e != hipSuccess) return fail_hip(_e, #expr); \
     } while (0)
 
+// Volumes are addressed through buffer resources with 32-bit byte ranges: a
+// three-component float field must stay below 4 GiB (nx*ny*nz < 357,913,942).
 bool dims_ok(int32_t nx, int32_t ny, int32_t nz)
 {
     if (nx < 1 || ny < 1 || nz < 1) return false;
     const int64_t n = (int64_t)nx * ny * nz;
-    return 3 * n < (int64_t(1) << 31);
+    return 12 * n < (int64_t(1) << 32);
 }
 
 int resolve_radius(double sigma, int32_t radius)
@@ -410,10 +412,10 @@ GaussTaps identity_taps()
 hipError_t force_half(dir_handle *h, Ctx &c, int variant, float alpha2, const float *S, const float *M,
                       const float *v, Dims d, const GaussTaps &taps, float *out, const int *stop_at, int n)
 {
-    float *Im = h->img_a.as<float>(), *Is = h->img_b.as<float>();
+    float *D = h->img_a.as<float>(), *P = h->img_b.as<float>();
     hipError_t e = hipSuccess;
-    if (variant == kActive || variant == kDouble) e = launch_warp(c, M, v, d, Im, stop_at, n);
-    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, Im, Is, stop_at, n);
+    if (variant == kActive || variant == kDouble) e = launch_warp_diff(c, M, S, v, d, D, stop_at, n);
+    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, D, P, stop_at, n);
     if (e != hipSuccess) return e;
     ForceLaunch f;
     f.variant = variant;
@@ -421,8 +423,8 @@ hipError_t force_half(dir_handle *h, Ctx &c, int variant, float alpha2, const fl
     f.S = S;
     f.M = M;
     f.v = v;
-    f.Im = Im;
-    f.Is = Is;
+    f.D = D;
+    f.P = P;
     f.d = d;
     f.taps = &taps;
     f.out = out;

@@ -139,13 +139,59 @@ __device__ __forceinline__ double sample64(const float *__restrict__ I, const Ce
     return az * (ay * c00 + by * c10) + bz * (ay * c01 + by * c11);
 }
 
-// Decode a flattened workgroup id into (tile x, tile y, z).
+// The dispatcher hands workgroup b to XCD b % 8, and each XCD has its own L2.
+// Renumbering so that XCD k runs one contiguous range of logical ids keeps
+// spatial neighbours (which share stencil halos and gather rows) in the same
+// L2.  A bijection on [0, nb).
+constexpr int kXCDs = 8;
+
+__device__ __forceinline__ int xcd_logical_id(int b, int nb)
+{
+    const int per = nb / kXCDs, rem = nb % kXCDs;
+    const int x = b % kXCDs, i = b / kXCDs;
+    return x * per + min(x, rem) + i;
+}
+
+// Raw buffer access: the resource (base, size in bytes) lives in scalar
+// registers, a per-lane byte offset in one VGPR and a wave-uniform byte offset
+// in an SGPR, so addressing costs no 64-bit vector arithmetic.  Offsets past
+// the size read 0 and drop writes (never used on purpose: every offset here
+// is in range by construction).
+constexpr int kBufferDword3 = 0x00020000;  // 32-bit data format (gfx9-family buffer resource word 3)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferDword3);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// Trilinear FP64 sample through a buffer resource (see sample64).
+__device__ __forceinline__ double bsample64(__amdgpu_buffer_rsrc_t I, const Cell &c)
+{
+    const double ax = c.wx, bx = 1.0 - ax, ay = c.wy, by = 1.0 - ay, az = c.wz, bz = 1.0 - az;
+    const double c00 = ax * (double)bload(I, 4u * c.o000, 0) + bx * (double)bload(I, 4u * c.o100, 0);
+    const double c10 = ax * (double)bload(I, 4u * c.o010, 0) + bx * (double)bload(I, 4u * c.o110, 0);
+    const double c01 = ax * (double)bload(I, 4u * c.o001, 0) + bx * (double)bload(I, 4u * c.o101, 0);
+    const double c11 = ax * (double)bload(I, 4u * c.o011, 0) + bx * (double)bload(I, 4u * c.o111, 0);
+    return az * (ay * c00 + by * c10) + bz * (ay * c01 + by * c11);
+}
+
+// Decode a flattened workgroup id into (tile x, tile y, z), XCD-contiguous.
 struct Tile {
     int x, y, z;
 };
 __device__ __forceinline__ Tile decode_tile(int gx, int gy)
 {
-    const int b = blockIdx.x;
+    const int b = xcd_logical_id(blockIdx.x, gridDim.x);
     Tile t;
     t.x = b % gx;
     const int r = b / gx;

@@ -19,8 +19,8 @@ enum Variant { kPassive = 0, kEvolved = 1, kActive = 2, kDouble = 3, kInverseCon
 // Kernel ids for event timing; names in kKernelNames (abi.hip).
 enum KernelId {
     K_FORCE = 0,     // force + x pass of the smoothing + sums (+ last-workgroup reduction)
-    K_WARP,          // deformed moving image (active, double force)
-    K_WARP_PAIR,     // deformed moving and static images (inverse-consistent)
+    K_WARP,          // deformed image (dir_warp) / intensity difference (active, double force)
+    K_WARP_PAIR,     // difference and sum of the two deformed images (inverse-consistent)
     K_SMOOTH_YZ,     // y and z passes of the smoothing
     K_SMOOTH_X,      // standalone x pass (dir_smooth)
     K_FINALIZE,      // standalone reduction of the sums (dir_force)
@@ -102,7 +102,8 @@ int64_t force_blocks(Dims d);
 struct ForceLaunch {
     int variant;
     float alpha2;
-    const float *S, *M, *v, *Im, *Is;
+    const float *S, *M, *v;
+    const float *D, *P;   // from the pre-warp: D (active, double, IC), P = Im + Is (IC)
     Dims d;
     const GaussTaps *taps;
     float *out;
@@ -116,7 +117,9 @@ hipError_t launch_restrict(Ctx &c, const float *in, Dims fine, float *out, Dims 
 hipError_t launch_prolong(Ctx &c, const float *vc, Dims coarse, float *vf, Dims fine);
 hipError_t launch_gradient(Ctx &c, const float *img, Dims d, float *grad);
 hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, float *out, const int *stop_at, int n);
-hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *Im, float *Is,
+hipError_t launch_warp_diff(Ctx &c, const float *M, const float *S, const float *v, Dims d, float *D,
+                            const int *stop_at, int n);
+hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *D, float *P,
                             const int *stop_at, int n);
 hipError_t launch_force(Ctx &c, const ForceLaunch &f);
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out);

@@ -21,7 +21,8 @@ namespace {
 using namespace dev;
 
 struct ForceArgs {
-    const float *S, *M, *v, *Im, *Is;
+    const float *S, *M, *v;
+    const float *Dd, *P;  // pre-warped D (active, double, IC) and P = Im + Is (IC)
     int nx, ny, nz;
     float alpha2;
     float *out;           // x-smoothed u (u itself with identity taps)
@@ -32,52 +33,110 @@ struct ForceArgs {
     int gxt;              // x tiles
 };
 
+// Byte offsets of one wave-uniform row (y, z) and of its stencil neighbour
+// rows (indices clamped), plus the lane's x offsets (x and its clamped
+// neighbours).  Rows go to the scalar offset of a buffer access, x to the
+// vector offset.
+struct RowOffsets {
+    unsigned c, ym, yp, zm, zp;  // rows (y, z), (y -+ 1, z), (y, z -+ 1)
+};
+struct LaneOffsets {
+    unsigned c, xm, xp;          // x, x - 1, x + 1 (clamped)
+};
+
+// Central difference (Sec 2.5 gradient kernel) from a buffer.
+__device__ __forceinline__ void cdiff(__amdgpu_buffer_rsrc_t I, const LaneOffsets &lo, const RowOffsets &ro, float &gx,
+                                      float &gy, float &gz)
+{
+    gx = 0.5f * (bload(I, lo.xp, ro.c) - bload(I, lo.xm, ro.c));
+    gy = 0.5f * (bload(I, lo.c, ro.yp) - bload(I, lo.c, ro.ym));
+    gz = 0.5f * (bload(I, lo.c, ro.zp) - bload(I, lo.c, ro.zm));
+}
+
+// Hardware square root and reciprocal (about 1 ulp): the force's parity
+// tolerance is 1e-5 and the norms only feed FP64 sums.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// D g / (alpha^2 D^2 + |g|^2) (Eqs 1, 3, 6; alpha of Eq 5), zero at or below
+// the denominator floor.
+__device__ __forceinline__ void dterm(float D, float gx, float gy, float gz, float alpha2, float &fx, float &fy,
+                                      float &fz)
+{
+    const float den = fmaf(alpha2 * D, D, fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+    const float s = den > kDenomFloor ? D * fast_rcp(den) : 0.0f;
+    fx = s * gx;
+    fy = s * gy;
+    fz = s * gz;
+}
+
+// Eq 2 with both gradient magnitudes squared (see evolved_term).
+__device__ __forceinline__ void eterm(float D, float gx, float gy, float gz, float a, float &fx, float &fy, float &fz)
+{
+    const float G2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+    const float a2 = a * a;
+    const float den = (fmaf(2.0f * D, D, G2 + a2)) * (G2 + a2);
+    const float s = den > kDenomFloor ? 4.0f * D * fast_sqrt(G2) * a * fast_rcp(den) : 0.0f;
+    fx = s * gx;
+    fy = s * gy;
+    fz = s * gz;
+}
+
+struct Bufs {
+    __amdgpu_buffer_rsrc_t S, M, v, Dd, P, out;
+};
+
 // u = v + dr at voxel (x, y, z) and its contributions |dr|, |v|, D^2.
 template <int V>
-__device__ __forceinline__ void force_point(const ForceArgs &a, int x, int y, int z, float &u0, float &u1, float &u2,
+__device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, int x, int y, int z,
+                                            const RowOffsets &ro, unsigned nbytes, float &u0, float &u1, float &u2,
                                             double &adr, double &av, double &d2)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int N = nx * ny * nz, i = x + nx * (y + ny * z);
-    const float vx = a.v[i], vy = a.v[N + i], vz = a.v[2 * N + i];
+    LaneOffsets lo;
+    lo.c = 4u * (unsigned)x;
+    lo.xm = 4u * (unsigned)max(x - 1, 0);
+    lo.xp = 4u * (unsigned)min(x + 1, nx - 1);
+    const float vx = bload(b.v, lo.c, ro.c), vy = bload(b.v, lo.c, ro.c + nbytes),
+                vz = bload(b.v, lo.c, ro.c + 2u * nbytes);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    // intensity difference in FP64, rounded once (see sample64)
+    // intensity difference: sampled in FP64 here (passive, evolved) or taken
+    // from the pre-warp kernel, which forms it the same way; rounded once
     double D64;
-    if (V == kInverseConsistent)
-        D64 = sample64(a.M, make_cell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) -
-              sample64(a.S, make_cell_disp(x, y, z, -vx, -vy, -vz, nx, ny, nz));
+    if (V == kPassive || V == kEvolved)
+        D64 = bsample64(b.M, make_cell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)bload(b.S, lo.c, ro.c);
     else
-        D64 = sample64(a.M, make_cell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)a.S[i];
+        D64 = (double)bload(b.Dd, lo.c, ro.c);
     const float D = (float)D64;
     if (V == kInverseConsistent) {
-        // Eq 6: g = grad Im + grad Is of the two deformed images
-        float ax, ay, az, bx, by, bz;
-        central_diff(a.Im, x, y, z, nx, ny, nz, ax, ay, az);
-        central_diff(a.Is, x, y, z, nx, ny, nz, bx, by, bz);
-        demons_term(D, ax + bx, ay + by, az + bz, a.alpha2, fx, fy, fz);
+        // Eq 6: g = grad Im + grad Is = grad P of the two deformed images
+        float gx, gy, gz;
+        cdiff(b.P, lo, ro, gx, gy, gz);
+        dterm(D, gx, gy, gz, a.alpha2, fx, fy, fz);
     } else {
-        float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-        if (V == kPassive || V == kDouble || V == kEvolved) central_diff(a.S, x, y, z, nx, ny, nz, sx, sy, sz);
-        if (V == kPassive || V == kDouble) demons_term(D, sx, sy, sz, a.alpha2, fx, fy, fz);  // Eq 1
-        if (V == kActive || V == kDouble) {                                                   // Eq 3
-            float mx, my, mz, bx, by, bz;
-            central_diff(a.Im, x, y, z, nx, ny, nz, mx, my, mz);
-            demons_term(D, mx, my, mz, a.alpha2, bx, by, bz);
+        float sx, sy, sz;
+        cdiff(b.S, lo, ro, sx, sy, sz);
+        if (V == kPassive || V == kDouble) dterm(D, sx, sy, sz, a.alpha2, fx, fy, fz);  // Eq 1
+        if (V == kActive || V == kDouble) {                                             // Eq 3
+            // grad Im = grad (Im - S) + grad S
+            float dx, dy, dz, bx, by, bz;
+            cdiff(b.Dd, lo, ro, dx, dy, dz);
+            dterm(D, dx + sx, dy + sy, dz + sz, a.alpha2, bx, by, bz);
             fx += bx;
             fy += by;
             fz += bz;
         }
-        if (V == kEvolved) {                                                                  // Eq 2
+        if (V == kEvolved) {                                                            // Eq 2
             float mx, my, mz;
-            central_diff(a.M, x, y, z, nx, ny, nz, mx, my, mz);
-            evolved_term(D, sx, sy, sz, sqrtf(fmaf(mx, mx, fmaf(my, my, mz * mz))), fx, fy, fz);
+            cdiff(b.M, lo, ro, mx, my, mz);
+            eterm(D, sx, sy, sz, fast_sqrt(fmaf(mx, mx, fmaf(my, my, mz * mz))), fx, fy, fz);
         }
     }
     u0 = vx + fx;
     u1 = vy + fy;
     u2 = vz + fz;
-    adr = (double)sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
-    av = (double)sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    adr = (double)fast_sqrt(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+    av = (double)fast_sqrt(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
     d2 = D64 * D64;
 }
 
@@ -91,23 +150,40 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
     const int tid = threadIdx.x;
     if (tid <= 2 * kMaxRadius) wl[tid] = taps.w[tid];  // ordered before use by the row barrier
     const int lane = tid % TX, wrow = tid / TX;
-    const int x0 = (blockIdx.x % a.gxt) * TX;
-    const int rb = blockIdx.x / a.gxt;
+    const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
+    const int x0 = (lid % a.gxt) * TX;
+    const int rb = lid / a.gxt;
     const int R = taps.radius;
     const int rows = a.ny * a.nz;
-    const int N = a.nx * rows;
+    const unsigned N = (unsigned)a.nx * (unsigned)rows;
+    const unsigned nbytes = 4u * N;
+    Bufs b;
+    b.S = make_rsrc(a.S, nbytes);
+    b.M = make_rsrc(a.M, nbytes);
+    b.v = make_rsrc(a.v, 3u * nbytes);
+    b.Dd = make_rsrc(a.Dd, nbytes);
+    b.P = make_rsrc(a.P, nbytes);
+    b.out = make_rsrc(a.out, 3u * nbytes);
     double s1 = 0.0, s2 = 0.0, sse = 0.0;
 
     for (int it = 0; it < a.rows_per_block; ++it) {
-        const int r = (rb * a.rows_per_block + it) * W + wrow;  // row index y + ny * z
+        // row index y + ny * z; the same for every lane of a wavefront
+        const int r = __builtin_amdgcn_readfirstlane((rb * a.rows_per_block + it) * W + wrow);
         const bool row_ok = r < rows;
         if (row_ok) {
             const int y = r % a.ny, z = r / a.ny;
+            const unsigned rowb = 4u * (unsigned)a.nx;  // bytes per row
+            RowOffsets ro;
+            ro.c = rowb * (unsigned)r;
+            ro.ym = rowb * (unsigned)(max(y - 1, 0) + a.ny * z);
+            ro.yp = rowb * (unsigned)(min(y + 1, a.ny - 1) + a.ny * z);
+            ro.zm = rowb * (unsigned)(y + a.ny * max(z - 1, 0));
+            ro.zp = rowb * (unsigned)(y + a.ny * min(z + 1, a.nz - 1));
             for (int p = lane; p < TX + 2 * R; p += TX) {
                 const int xx = x0 - R + p;
                 float u0, u1, u2;
                 double adr, av, d2;
-                force_point<V>(a, clampi(xx, a.nx), y, z, u0, u1, u2, adr, av, d2);
+                force_point<V>(a, b, clampi(xx, a.nx), y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
                 ul[0][wrow][p] = u0;
                 ul[1][wrow][p] = u1;
                 ul[2][wrow][p] = u2;
@@ -121,12 +197,12 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
         __syncthreads();
         const int x = x0 + lane;
         if (row_ok && x < a.nx) {
-            const int o = x + a.nx * r;
+            const unsigned rowoff = 4u * (unsigned)a.nx * (unsigned)r;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float s = 0.0f;
                 for (int j = 0; j <= 2 * R; ++j) s = fmaf(wl[j], ul[c][wrow][lane + j], s);
-                a.out[c * N + o] = s;
+                bstore(b.out, s, 4u * (unsigned)x, rowoff + (unsigned)c * nbytes);
             }
         }
         __syncthreads();
@@ -198,8 +274,8 @@ hipError_t launch_force(Ctx &c, const ForceLaunch &f)
     a.S = f.S;
     a.M = f.M;
     a.v = f.v;
-    a.Im = f.Im;
-    a.Is = f.Is;
+    a.Dd = f.D;
+    a.P = f.P;
     a.nx = f.d.nx;
     a.ny = f.d.ny;
     a.nz = f.d.nz;

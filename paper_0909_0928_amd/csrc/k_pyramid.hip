@@ -73,10 +73,29 @@ __global__ __launch_bounds__(256) void k_warp(const float *__restrict__ I, const
     out[i] = (float)sample64(I, make_cell_disp(x, y, z, v[i], v[N + i], v[2 * N + i], nx, ny, nz));
 }
 
-// Inverse-consistent pair: Im = M(x - h), Is = S(x + h) (Sec 2.2, after Eq 6).
+// Intensity difference for the active and double forces: D = M(x - v) - S(x),
+// sampled and subtracted in FP64, rounded once.  The force kernel takes D and
+// its gradient from here (grad Im = grad D + grad S), so the gather happens
+// once per iteration.
+__global__ __launch_bounds__(256) void k_warp_diff(const float *__restrict__ M, const float *__restrict__ S,
+                                                   const float *__restrict__ v, int nx, int ny, int nz,
+                                                   float *__restrict__ D, int gx, int gy,
+                                                   const int *__restrict__ stop_at, int n)
+{
+    if (stop_at && *stop_at < n) return;
+    const Tile t = decode_tile(gx, gy);
+    const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
+    if (x >= nx || y >= ny) return;
+    const int N = nx * ny * nz, i = x + nx * (y + ny * z);
+    D[i] = (float)(sample64(M, make_cell_disp(x, y, z, v[i], v[N + i], v[2 * N + i], nx, ny, nz)) - (double)S[i]);
+}
+
+// Inverse-consistent pair (Sec 2.2, after Eq 6): Im = M(x - h), Is = S(x + h),
+// written as D = Im - Is and P = Im + Is (the force needs D and grad P).
+// Both formed in FP64 and rounded once.
 __global__ __launch_bounds__(256) void k_warp_pair(const float *__restrict__ M, const float *__restrict__ S,
                                                    const float *__restrict__ h, int nx, int ny, int nz,
-                                                   float *__restrict__ Im, float *__restrict__ Is, int gx, int gy,
+                                                   float *__restrict__ D, float *__restrict__ P, int gx, int gy,
                                                    const int *__restrict__ stop_at, int n)
 {
     if (stop_at && *stop_at < n) return;
@@ -85,8 +104,10 @@ __global__ __launch_bounds__(256) void k_warp_pair(const float *__restrict__ M, 
     if (x >= nx || y >= ny) return;
     const int N = nx * ny * nz, i = x + nx * (y + ny * z);
     const float hx = h[i], hy = h[N + i], hz = h[2 * N + i];
-    Im[i] = (float)sample64(M, make_cell_disp(x, y, z, hx, hy, hz, nx, ny, nz));
-    Is[i] = (float)sample64(S, make_cell_disp(x, y, z, -hx, -hy, -hz, nx, ny, nz));
+    const double im = sample64(M, make_cell_disp(x, y, z, hx, hy, hz, nx, ny, nz));
+    const double is = sample64(S, make_cell_disp(x, y, z, -hx, -hy, -hz, nx, ny, nz));
+    D[i] = (float)(im - is);
+    P[i] = (float)(im + is);
 }
 
 // ------------------------------------------------------------------------
@@ -165,13 +186,23 @@ hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, flo
     });
 }
 
-hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *Im, float *Is,
+hipError_t launch_warp_diff(Ctx &c, const float *M, const float *S, const float *v, Dims d, float *D,
+                            const int *stop_at, int n)
+{
+    const Grid2 g = plane_grid(d);
+    return timed(c, K_WARP, [&] {
+        hipLaunchKernelGGL(k_warp_diff, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, M, S, v, d.nx,
+                           d.ny, d.nz, D, g.gx, g.gy, stop_at, n);
+    });
+}
+
+hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *D, float *P,
                             const int *stop_at, int n)
 {
     const Grid2 g = plane_grid(d);
     return timed(c, K_WARP_PAIR, [&] {
         hipLaunchKernelGGL(k_warp_pair, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, M, S, h, d.nx,
-                           d.ny, d.nz, Im, Is, g.gx, g.gy, stop_at, n);
+                           d.ny, d.nz, D, P, g.gx, g.gy, stop_at, n);
     });
 }
 
