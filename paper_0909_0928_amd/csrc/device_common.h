@@ -174,14 +174,67 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
 }
 
+// Trilinear cell in byte offsets for buffer access: the lower corner, the
+// byte step to the upper neighbour along each axis (0 where the sample was
+// clamped onto a single grid point) and the exact weights of the lower
+// corner.  Same sample position and weights as make_cell_disp.
+struct BCell {
+    unsigned o;
+    unsigned dx, dy, dz;
+    float wx, wy, wz;
+};
+
+struct AxisB {
+    int i;
+    bool step;
+    float w0;
+};
+
+__device__ __forceinline__ AxisB axis_b(int x, float v, int n)
+{
+    v = fminf(fmaxf(v, -1048576.0f), 1048576.0f);  // NaN -> -2^20; keeps indices in range
+    const float fv = floorf(v);
+    const float r = v - fv;                          // exact
+    int i = x - (int)fv;                             // p = x - v = i - r
+    AxisB a;
+    a.w0 = 1.0f;
+    if (r > 0.0f) {
+        i -= 1;
+        a.w0 = r;
+    }
+    a.step = i >= 0 && i <= n - 2;
+    if (!a.step) {  // clamped onto the border sample (or the last sample exactly)
+        i = min(max(i, 0), n - 1);
+        a.w0 = 1.0f;
+    }
+    a.i = i;
+    return a;
+}
+
+__device__ __forceinline__ BCell bcell_disp(int x, int y, int z, float vx, float vy, float vz, int nx, int ny, int nz)
+{
+    const AxisB ax = axis_b(x, vx, nx), ay = axis_b(y, vy, ny), az = axis_b(z, vz, nz);
+    BCell c;
+    const unsigned row = 4u * (unsigned)nx, plane = row * (unsigned)ny;
+    c.o = 4u * (unsigned)ax.i + row * (unsigned)ay.i + plane * (unsigned)az.i;
+    c.dx = ax.step ? 4u : 0u;
+    c.dy = ay.step ? row : 0u;
+    c.dz = az.step ? plane : 0u;
+    c.wx = ax.w0;
+    c.wy = ay.w0;
+    c.wz = az.w0;
+    return c;
+}
+
 // Trilinear FP64 sample through a buffer resource (see sample64).
-__device__ __forceinline__ double bsample64(__amdgpu_buffer_rsrc_t I, const Cell &c)
+__device__ __forceinline__ double bsample64(__amdgpu_buffer_rsrc_t I, const BCell &c)
 {
     const double ax = c.wx, bx = 1.0 - ax, ay = c.wy, by = 1.0 - ay, az = c.wz, bz = 1.0 - az;
-    const double c00 = ax * (double)bload(I, 4u * c.o000, 0) + bx * (double)bload(I, 4u * c.o100, 0);
-    const double c10 = ax * (double)bload(I, 4u * c.o010, 0) + bx * (double)bload(I, 4u * c.o110, 0);
-    const double c01 = ax * (double)bload(I, 4u * c.o001, 0) + bx * (double)bload(I, 4u * c.o101, 0);
-    const double c11 = ax * (double)bload(I, 4u * c.o011, 0) + bx * (double)bload(I, 4u * c.o111, 0);
+    const unsigned o = c.o, oy = o + c.dy, oz = o + c.dz, oyz = oz + c.dy;
+    const double c00 = ax * (double)bload(I, o, 0) + bx * (double)bload(I, o + c.dx, 0);
+    const double c10 = ax * (double)bload(I, oy, 0) + bx * (double)bload(I, oy + c.dx, 0);
+    const double c01 = ax * (double)bload(I, oz, 0) + bx * (double)bload(I, oz + c.dx, 0);
+    const double c11 = ax * (double)bload(I, oyz, 0) + bx * (double)bload(I, oyz + c.dx, 0);
     return az * (ay * c00 + by * c10) + bz * (ay * c01 + by * c11);
 }
 

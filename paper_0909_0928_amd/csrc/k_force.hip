@@ -104,7 +104,7 @@ __device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, i
     // from the pre-warp kernel, which forms it the same way; rounded once
     double D64;
     if (V == kPassive || V == kEvolved)
-        D64 = bsample64(b.M, make_cell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)bload(b.S, lo.c, ro.c);
+        D64 = bsample64(b.M, bcell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)bload(b.S, lo.c, ro.c);
     else
         D64 = (double)bload(b.Dd, lo.c, ro.c);
     const float D = (float)D64;

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_warp(const float *__restrict__ I, const
 // Intensity difference for the active and double forces: D = M(x - v) - S(x),
 // sampled and subtracted in FP64, rounded once.  The force kernel takes D and
 // its gradient from here (grad Im = grad D + grad S), so the gather happens
-// once per iteration.
+// once per iteration.  Buffer addressing as in the force kernel.
 __global__ __launch_bounds__(256) void k_warp_diff(const float *__restrict__ M, const float *__restrict__ S,
                                                    const float *__restrict__ v, int nx, int ny, int nz,
                                                    float *__restrict__ D, int gx, int gy,
@@ -86,8 +86,13 @@ __global__ __launch_bounds__(256) void k_warp_diff(const float *__restrict__ M, 
     const Tile t = decode_tile(gx, gy);
     const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
     if (x >= nx || y >= ny) return;
-    const int N = nx * ny * nz, i = x + nx * (y + ny * z);
-    D[i] = (float)(sample64(M, make_cell_disp(x, y, z, v[i], v[N + i], v[2 * N + i], nx, ny, nz)) - (double)S[i]);
+    const unsigned nbytes = 4u * (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, nbytes), rS = make_rsrc(S, nbytes), rv = make_rsrc(v, 3u * nbytes),
+                                 rD = make_rsrc(D, nbytes);
+    const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
+    const float vx = bload(rv, o, 0), vy = bload(rv, o, nbytes), vz = bload(rv, o, 2u * nbytes);
+    const double d = bsample64(rM, bcell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)bload(rS, o, 0);
+    bstore(rD, (float)d, o, 0);
 }
 
 // Inverse-consistent pair (Sec 2.2, after Eq 6): Im = M(x - h), Is = S(x + h),
@@ -102,12 +107,15 @@ __global__ __launch_bounds__(256) void k_warp_pair(const float *__restrict__ M, 
     const Tile t = decode_tile(gx, gy);
     const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
     if (x >= nx || y >= ny) return;
-    const int N = nx * ny * nz, i = x + nx * (y + ny * z);
-    const float hx = h[i], hy = h[N + i], hz = h[2 * N + i];
-    const double im = sample64(M, make_cell_disp(x, y, z, hx, hy, hz, nx, ny, nz));
-    const double is = sample64(S, make_cell_disp(x, y, z, -hx, -hy, -hz, nx, ny, nz));
-    D[i] = (float)(im - is);
-    P[i] = (float)(im + is);
+    const unsigned nbytes = 4u * (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, nbytes), rS = make_rsrc(S, nbytes), rh = make_rsrc(h, 3u * nbytes),
+                                 rD = make_rsrc(D, nbytes), rP = make_rsrc(P, nbytes);
+    const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
+    const float hx = bload(rh, o, 0), hy = bload(rh, o, nbytes), hz = bload(rh, o, 2u * nbytes);
+    const double im = bsample64(rM, bcell_disp(x, y, z, hx, hy, hz, nx, ny, nz));
+    const double is = bsample64(rS, bcell_disp(x, y, z, -hx, -hy, -hz, nx, ny, nz));
+    bstore(rD, (float)(im - is), o, 0);
+    bstore(rP, (float)(im + is), o, 0);
 }
 
 // ------------------------------------------------------------------------
