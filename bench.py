@@ -82,6 +82,20 @@ def launch_units(kernel, shape, iters, n_ic, n_active_like, n_settings):
     return None
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter record
+    (profiles/<kernel>_traffic.json), or None when the record is missing or
+    was taken on different kernel sources."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    from paper_0909_0928_amd import profile_summary as PS
+    rec = json.load(open(path))
+    if kernel not in PS.KERNEL_SOURCES or rec.get("source_sha256") != PS.source_fingerprint(kernel):
+        return None, "profiles/" + os.path.basename(path) + " (stale: kernel sources changed)"
+    return rec["traffic_bytes_per_launch"], "profiles/" + os.path.basename(path)
+
+
 def cpu_baseline(S, M):
     """The FP64 oracle on one full step of the same workload (all six settings)."""
     import oracle as O
@@ -170,6 +184,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kern_ms, kern_launches = B.dir_timing_read(h, dominant)
+    fine_ms, fine_launches = B.dir_timing_read(h, dominant, level=0)
     B.dir_timing_enable(h, ())
 
     total_vi = vi_reg * len(SETTINGS) * args.steps
@@ -185,11 +200,18 @@ def main():
     if units is not None and dominant in ALGO_BYTES_PER_VOXEL and kern_launches:
         bytes_total = units * ALGO_BYTES_PER_VOXEL[dominant] * args.steps
         achieved = bytes_total / (kern_ms * 1e-3) / 1e9
+        traffic, traffic_src = measured_traffic(dominant)
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_us": kern_ms * 1e3 / kern_launches, "launches": kern_launches,
                 "algo_bytes_per_voxel": ALGO_BYTES_PER_VOXEL[dominant],
-                "bytes_per_launch": bytes_total / kern_launches}
+                "bytes_per_launch": bytes_total / kern_launches, "traffic_source": traffic_src}
+        if fine_launches:
+            fine_bytes = SHAPE[0] * SHAPE[1] * SHAPE[2] * ALGO_BYTES_PER_VOXEL[dominant]
+            fine_gbs = fine_bytes * fine_launches / (fine_ms * 1e-3) / 1e9
+            roof["finest_level"] = {"shape_xyz": list(SHAPE), "launches": fine_launches,
+                                    "avg_launch_us": fine_ms * 1e3 / fine_launches, "bytes_per_launch": fine_bytes,
+                                    "achieved": fine_gbs, "frac": fine_gbs / HBM_PEAK_GBS}
 
     # ground-truth error of each setting on a body sample
     rng = np.random.default_rng(0)

@@ -186,15 +186,20 @@ int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, 
  * Kernels are numbered 0 .. dir_timing_count()-1; dir_timing_name(k) gives
  * the kernel's name (NULL if k is out of range).
  * dir_timing_enable(h, mask) zeroes the totals and, for every kernel k whose
- * bit (1 << k) is set, brackets each later launch with a pair of events on
- * the handle's stream; mask 0 stops recording.  dir_timing_read returns the
- * accumulated device milliseconds and launch count of kernel k over the
- * launches of blocking calls (dir_register, dir_force) and of calls followed
- * by dir_synchronize. */
+ * bit (1 << k) is set, launches each later instance of k with a start and a
+ * stop event that the dispatch stamps at kernel begin and end (so the time is
+ * the kernel's own, as a kernel trace reports it); mask 0 stops recording.
+ * dir_timing_read returns the accumulated device milliseconds and launch
+ * count of kernel k over the launches of blocking calls (dir_register,
+ * dir_force) and of calls followed by dir_synchronize;
+ * dir_timing_read_level the same restricted to pyramid level `level`
+ * (0 = finest; launches outside dir_register count as level 0).  Both return
+ * DIR_EINVAL for a NULL handle or an index out of range. */
 int32_t dir_timing_count(void);
 const char *dir_timing_name(int32_t kernel);
 int32_t dir_timing_enable(dir_handle *h, uint64_t kernel_mask);
 int32_t dir_timing_read(dir_handle *h, int32_t kernel, double *total_ms, int64_t *launches);
+int32_t dir_timing_read_level(dir_handle *h, int32_t kernel, int32_t level, double *total_ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -82,9 +82,10 @@ def lib():
         L.dir_timing_name.argtypes = [i32]
         L.dir_timing_enable.argtypes = [vp, ctypes.c_uint64]
         L.dir_timing_read.argtypes = [vp, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
+        L.dir_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
-                     "dir_timing_enable", "dir_timing_read"):
+                     "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -334,10 +335,16 @@ def dir_timing_enable(h, kernels=()):
     _check(lib().dir_timing_enable(h.ptr, ctypes.c_uint64(mask)), "dir_timing_enable")
 
 
-def dir_timing_read(h, kernel):
+def dir_timing_read(h, kernel, level=None):
+    """(device ms, launches) of a timed kernel; `level` (0 = finest) restricts
+    the totals to one pyramid level."""
     names = dir_timing_names()
     k = names.index(kernel) if isinstance(kernel, str) else int(kernel)
     ms = ctypes.c_double()
     n = ctypes.c_int64()
-    _check(lib().dir_timing_read(h.ptr, k, ctypes.byref(ms), ctypes.byref(n)), "dir_timing_read")
+    if level is None:
+        _check(lib().dir_timing_read(h.ptr, k, ctypes.byref(ms), ctypes.byref(n)), "dir_timing_read")
+    else:
+        _check(lib().dir_timing_read_level(h.ptr, k, int(level), ctypes.byref(ms), ctypes.byref(n)),
+               "dir_timing_read_level")
     return ms.value, n.value

@@ -119,6 +119,7 @@ int enter(dir_handle *h)
     if (!h) return DIR_EINVAL;
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    h->timer.level = 0;
     return DIR_OK;
 }
 
@@ -131,6 +132,8 @@ int finish(dir_handle *h)
 }
 
 }  // namespace
+
+static_assert(dir::kTimerLevels >= DIR_MAX_LEVELS, "timer keeps one slot per pyramid level");
 
 // ---------------------------------------------------------------------------
 // Timer
@@ -147,22 +150,18 @@ hipError_t Timer::take(hipEvent_t *ev)
     return hipEventCreate(ev);
 }
 
-hipError_t Timer::begin(int, hipStream_t s, hipEvent_t *ev)
+hipError_t Timer::pair(hipEvent_t *start, hipEvent_t *stop)
 {
-    hipError_t e = take(ev);
+    hipError_t e = take(start);
     if (e != hipSuccess) return e;
-    return hipEventRecord(*ev, s);
+    e = take(stop);
+    if (e != hipSuccess) pool_.push_back(*start);
+    return e;
 }
 
-hipError_t Timer::end(int k, hipStream_t s, hipEvent_t start)
+void Timer::record(int k, hipEvent_t start, hipEvent_t stop)
 {
-    hipEvent_t b;
-    hipError_t e = take(&b);
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, s);
-    if (e != hipSuccess) return e;
-    pending_.push_back(Rec{k, start, b});
-    return hipSuccess;
+    pending_.push_back(Rec{k, level < 0 ? 0 : (level < kTimerLevels ? level : kTimerLevels - 1), start, stop});
 }
 
 hipError_t Timer::harvest()
@@ -172,8 +171,8 @@ hipError_t Timer::harvest()
         float ms = 0.0f;
         hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
         if (e == hipSuccess) {
-            total_ms[r.k] += ms;
-            launches[r.k] += 1;
+            total_ms[r.k][r.level] += ms;
+            launches[r.k][r.level] += 1;
         } else if (err == hipSuccess) {
             err = e;
         }
@@ -186,10 +185,11 @@ hipError_t Timer::harvest()
 
 void Timer::reset()
 {
-    for (int k = 0; k < K_COUNT; ++k) {
-        total_ms[k] = 0.0;
-        launches[k] = 0;
-    }
+    for (int k = 0; k < K_COUNT; ++k)
+        for (int l = 0; l < kTimerLevels; ++l) {
+            total_ms[k][l] = 0.0;
+            launches[k][l] = 0;
+        }
 }
 
 void Timer::release()
@@ -299,8 +299,22 @@ int32_t dir_timing_enable(dir_handle *h, uint64_t kernel_mask)
 int32_t dir_timing_read(dir_handle *h, int32_t kernel, double *total_ms, int64_t *launches)
 {
     if (!h || kernel < 0 || kernel >= K_COUNT) return DIR_EINVAL;
-    if (total_ms) *total_ms = h->timer.total_ms[kernel];
-    if (launches) *launches = h->timer.launches[kernel];
+    double ms = 0.0;
+    int64_t n = 0;
+    for (int l = 0; l < kTimerLevels; ++l) {
+        ms += h->timer.total_ms[kernel][l];
+        n += h->timer.launches[kernel][l];
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+    return DIR_OK;
+}
+
+int32_t dir_timing_read_level(dir_handle *h, int32_t kernel, int32_t level, double *total_ms, int64_t *launches)
+{
+    if (!h || kernel < 0 || kernel >= K_COUNT || level < 0 || level >= kTimerLevels) return DIR_EINVAL;
+    if (total_ms) *total_ms = h->timer.total_ms[kernel][level];
+    if (launches) *launches = h->timer.launches[kernel][level];
     return DIR_OK;
 }
 
@@ -578,6 +592,7 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
         size_t off = 0;
         for (int k = 1; k < L; ++k) {
             float *s = h->pyr_s.as<float>() + off, *m = h->pyr_m.as<float>() + off;
+            h->timer.level = k;
             DIR_TRY(launch_restrict(c, Sk[k - 1], dims[k - 1], s, dims[k]));
             DIR_TRY(launch_restrict(c, Mk[k - 1], dims[k - 1], m, dims[k]));
             Sk[k] = s;
@@ -591,11 +606,13 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
     LevelState *states = h->state.as<LevelState>();
     double *hist = h->history.as<double>();
     int64_t hist_off[DIR_MAX_LEVELS];
+    h->timer.level = L - 1;
     DIR_TRY(launch_zero(c, v, 3 * dims[L - 1].n()));
     int64_t off = 0;
     for (int k = L - 1; k >= 0; --k) {
         const int li = L - 1 - k;
         const Dims d = dims[k];
+        h->timer.level = k;
         if (k < L - 1) {
             DIR_TRY(launch_prolong(c, v, dims[k + 1], xs, d));
             float *t = v;
@@ -623,6 +640,7 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
     }
 
     // ---- output ----
+    h->timer.level = 0;
     if (variant == kInverseConsistent) DIR_TRY(launch_compose(c, v, dims[0], K, d_field_out));
     else DIR_TRY(hipMemcpyAsync(d_field_out, v, sizeof(float) * 3 * n0, hipMemcpyDeviceToDevice, h->stream));
     rc = finish(h);

@@ -8,6 +8,8 @@
 
 #include <math.h>
 
+#include <hip/hip_ext.h>
+
 #include "dir_internal.h"
 
 namespace dir {
@@ -381,19 +383,33 @@ inline Grid2 plane_grid(Dims d)
     return g;
 }
 
-// Launch through `launch`, bracketed by timing events when kernel k is timed.
+// Start and stop events of one launch; both null when it is not timed.
+struct Ev {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+// Enqueue `kernel` on the context's stream with the launch's timing events.
+template <typename K, typename... A>
+void go(Ctx &c, const Ev &ev, K kernel, dim3 grid, dim3 block, A... args)
+{
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, c.stream, ev.a, ev.b, 0, args...);
+}
+
+// Run `launch(ev)`, which enqueues exactly one kernel through go(); when
+// kernel k is timed, ev carries a fresh event pair that the timer collects.
 template <typename F>
 hipError_t timed(Ctx &c, int k, F &&launch)
 {
-    hipEvent_t a = nullptr;
-    if (c.timer && c.timer->on(k)) {
-        hipError_t e = c.timer->begin(k, c.stream, &a);
+    Ev ev;
+    const bool on = c.timer && c.timer->on(k);
+    if (on) {
+        hipError_t e = c.timer->pair(&ev.a, &ev.b);
         if (e != hipSuccess) return e;
     }
-    launch();
+    launch(ev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (a) return c.timer->end(k, c.stream, a);
+    if (on) c.timer->record(k, ev.a, ev.b);
     return hipSuccess;
 }
 

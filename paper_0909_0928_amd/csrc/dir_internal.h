@@ -63,24 +63,32 @@ struct SumsReduce {
     double eps, inv_n;
 };
 
-// Per-kernel HIP-event timing.  Events are recycled from a pool; pairs are
-// read back by harvest() after the stream has completed.
+// Per-kernel HIP-event timing.  A timed launch goes through
+// hipExtLaunchKernelGGL with a start and a stop event, which the dispatch
+// itself stamps when the kernel begins and ends, so a pair measures the
+// kernel's execution and not the stream around it.  Totals are kept per
+// pyramid level (0 = finest; `level` is the level whose launches are being
+// issued).  Events are recycled from a pool; pairs are read back by harvest()
+// after the stream has completed.
+constexpr int kTimerLevels = 8;
+
 class Timer {
   public:
     uint64_t mask = 0;
-    double total_ms[K_COUNT] = {};
-    int64_t launches[K_COUNT] = {};
+    int level = 0;
+    double total_ms[K_COUNT][kTimerLevels] = {};
+    int64_t launches[K_COUNT][kTimerLevels] = {};
 
     bool on(int k) const { return (mask >> k) & 1ull; }
-    hipError_t begin(int k, hipStream_t s, hipEvent_t *ev);
-    hipError_t end(int k, hipStream_t s, hipEvent_t start);
+    hipError_t pair(hipEvent_t *start, hipEvent_t *stop);  // two events for one launch
+    void record(int k, hipEvent_t start, hipEvent_t stop);  // after the launch was enqueued
     hipError_t harvest();   // stream must be complete
     void reset();
     void release();         // destroy all events
 
   private:
     struct Rec {
-        int k;
+        int k, level;
         hipEvent_t a, b;
     };
     std::vector<hipEvent_t> pool_;

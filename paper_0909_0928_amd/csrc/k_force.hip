@@ -255,12 +255,12 @@ ForceGrid force_grid(Dims d)
 }
 
 template <int V>
-void launch_force_v(Ctx &c, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
+void launch_force_v(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
 {
     const dim3 grid((unsigned)g.blocks), block(256);
-    if (g.tx == 64) hipLaunchKernelGGL((k_force_x<V, 64>), grid, block, 0, c.stream, a, taps);
-    else if (g.tx == 128) hipLaunchKernelGGL((k_force_x<V, 128>), grid, block, 0, c.stream, a, taps);
-    else hipLaunchKernelGGL((k_force_x<V, 256>), grid, block, 0, c.stream, a, taps);
+    if (g.tx == 64) go(c, ev, (k_force_x<V, 64>), grid, block, a, taps);
+    else if (g.tx == 128) go(c, ev, (k_force_x<V, 128>), grid, block, a, taps);
+    else go(c, ev, (k_force_x<V, 256>), grid, block, a, taps);
 }
 
 }  // namespace
@@ -286,25 +286,25 @@ hipError_t launch_force(Ctx &c, const ForceLaunch &f)
     a.n = f.n;
     a.rows_per_block = g.rows_per_block;
     a.gxt = g.gxt;
-    return timed(c, K_FORCE, [&] {
+    return timed(c, K_FORCE, [&](const Ev &ev) {
         switch (f.variant) {
-        case kPassive: launch_force_v<kPassive>(c, g, a, *f.taps); break;
-        case kEvolved: launch_force_v<kEvolved>(c, g, a, *f.taps); break;
-        case kActive: launch_force_v<kActive>(c, g, a, *f.taps); break;
-        case kDouble: launch_force_v<kDouble>(c, g, a, *f.taps); break;
-        default: launch_force_v<kInverseConsistent>(c, g, a, *f.taps); break;
+        case kPassive: launch_force_v<kPassive>(c, ev, g, a, *f.taps); break;
+        case kEvolved: launch_force_v<kEvolved>(c, ev, g, a, *f.taps); break;
+        case kActive: launch_force_v<kActive>(c, ev, g, a, *f.taps); break;
+        case kDouble: launch_force_v<kDouble>(c, ev, g, a, *f.taps); break;
+        default: launch_force_v<kInverseConsistent>(c, ev, g, a, *f.taps); break;
         }
     });
 }
 
 hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n)
 {
-    return timed(c, K_FINALIZE, [&] { hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c.stream, red, n); });
+    return timed(c, K_FINALIZE, [&](const Ev &ev) { go(c, ev, k_finalize, dim3(1), dim3(256), red, n); });
 }
 
 hipError_t launch_level_reset(Ctx &c, LevelState *st)
 {
-    return timed(c, K_LEVEL_RESET, [&] { hipLaunchKernelGGL(k_level_reset, dim3(1), dim3(64), 0, c.stream, st); });
+    return timed(c, K_LEVEL_RESET, [&](const Ev &ev) { go(c, ev, k_level_reset, dim3(1), dim3(64), st); });
 }
 
 }  // namespace dir

@@ -155,14 +155,14 @@ hipError_t launch_zero(Ctx &c, float *p, int64_t n)
 {
     const int64_t want = (n + 255) / 256;
     const unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    return timed(c, K_FILL, [&] { hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, c.stream, p, n); });
+    return timed(c, K_FILL, [&](const Ev &ev) { go(c, ev, k_zero, dim3(blocks), dim3(256), p, n); });
 }
 
 hipError_t launch_restrict(Ctx &c, const float *in, Dims fine, float *out, Dims coarse)
 {
     const Grid2 g = plane_grid(coarse);
-    return timed(c, K_RESTRICT, [&] {
-        hipLaunchKernelGGL(k_restrict, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, in, fine.nx,
+    return timed(c, K_RESTRICT, [&](const Ev &ev) {
+        go(c, ev, k_restrict, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), in, fine.nx,
                            fine.ny, fine.nz, out, coarse.nx, coarse.ny, coarse.nz, g.gx, g.gy);
     });
 }
@@ -170,8 +170,8 @@ hipError_t launch_restrict(Ctx &c, const float *in, Dims fine, float *out, Dims 
 hipError_t launch_prolong(Ctx &c, const float *vc, Dims coarse, float *vf, Dims fine)
 {
     const Grid2 g = plane_grid(fine);
-    return timed(c, K_PROLONG, [&] {
-        hipLaunchKernelGGL(k_prolong, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, vc, coarse.nx,
+    return timed(c, K_PROLONG, [&](const Ev &ev) {
+        go(c, ev, k_prolong, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), vc, coarse.nx,
                            coarse.ny, coarse.nz, vf, fine.nx, fine.ny, fine.nz, g.gx, g.gy);
     });
 }
@@ -179,8 +179,8 @@ hipError_t launch_prolong(Ctx &c, const float *vc, Dims coarse, float *vf, Dims 
 hipError_t launch_gradient(Ctx &c, const float *img, Dims d, float *grad)
 {
     const Grid2 g = plane_grid(d);
-    return timed(c, K_GRADIENT, [&] {
-        hipLaunchKernelGGL(k_gradient, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, img, d.nx, d.ny,
+    return timed(c, K_GRADIENT, [&](const Ev &ev) {
+        go(c, ev, k_gradient, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), img, d.nx, d.ny,
                            d.nz, grad, g.gx, g.gy);
     });
 }
@@ -188,8 +188,8 @@ hipError_t launch_gradient(Ctx &c, const float *img, Dims d, float *grad)
 hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, float *out, const int *stop_at, int n)
 {
     const Grid2 g = plane_grid(d);
-    return timed(c, K_WARP, [&] {
-        hipLaunchKernelGGL(k_warp, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, img, field, d.nx,
+    return timed(c, K_WARP, [&](const Ev &ev) {
+        go(c, ev, k_warp, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), img, field, d.nx,
                            d.ny, d.nz, out, g.gx, g.gy, stop_at, n);
     });
 }
@@ -198,8 +198,8 @@ hipError_t launch_warp_diff(Ctx &c, const float *M, const float *S, const float 
                             const int *stop_at, int n)
 {
     const Grid2 g = plane_grid(d);
-    return timed(c, K_WARP, [&] {
-        hipLaunchKernelGGL(k_warp_diff, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, M, S, v, d.nx,
+    return timed(c, K_WARP, [&](const Ev &ev) {
+        go(c, ev, k_warp_diff, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, v, d.nx,
                            d.ny, d.nz, D, g.gx, g.gy, stop_at, n);
     });
 }
@@ -208,8 +208,8 @@ hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float 
                             const int *stop_at, int n)
 {
     const Grid2 g = plane_grid(d);
-    return timed(c, K_WARP_PAIR, [&] {
-        hipLaunchKernelGGL(k_warp_pair, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, M, S, h, d.nx,
+    return timed(c, K_WARP_PAIR, [&](const Ev &ev) {
+        go(c, ev, k_warp_pair, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, h, d.nx,
                            d.ny, d.nz, D, P, g.gx, g.gy, stop_at, n);
     });
 }
@@ -217,8 +217,8 @@ hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float 
 hipError_t launch_compose(Ctx &c, const float *h, Dims d, int K, float *out)
 {
     const Grid2 g = plane_grid(d);
-    return timed(c, K_COMPOSE, [&] {
-        hipLaunchKernelGGL(k_compose, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, h, d.nx, d.ny,
+    return timed(c, K_COMPOSE, [&](const Ev &ev) {
+        go(c, ev, k_compose, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), h, d.nx, d.ny,
                            d.nz, K, out, g.gx, g.gy);
     });
 }

@@ -129,12 +129,12 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
 }
 
 template <int R, int TZ>
-void launch_yz_tz(Ctx &c, const float *in, float *out, int ncomp, Dims d, const GaussTaps &taps, const int *stop_at,
+void launch_yz_tz(Ctx &c, const Ev &ev, const float *in, float *out, int ncomp, Dims d, const GaussTaps &taps, const int *stop_at,
                   int n, const SumsReduce &red)
 {
     const int gx = ceil_div(d.nx, kBlockX), gy = ceil_div(d.ny, kTileY), gz = ceil_div(d.nz, TZ);
     const int64_t blocks = (int64_t)gx * gy * gz * ncomp + (red.partials ? 1 : 0);
-    hipLaunchKernelGGL((k_smooth_yz<R, TZ>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), 0, c.stream, in, out,
+    go(c, ev, (k_smooth_yz<R, TZ>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), in, out,
                        d.nx, d.ny, d.nz, taps, gx, gy, gz, stop_at, n, red);
 }
 
@@ -148,10 +148,10 @@ hipError_t launch_yz_r(Ctx &c, const float *in, float *out, int ncomp, Dims d, c
 {
     const int64_t tiles = (int64_t)ceil_div(d.nx, kBlockX) * ceil_div(d.ny, kTileY) * ncomp;
     const bool deep = max_tz<R>() == 8 && tiles * ceil_div(d.nz, 8) >= kYZTargetBlocks;
-    return timed(c, K_SMOOTH_YZ, [&] {
-        if (deep) launch_yz_tz<R, max_tz<R>()>(c, in, out, ncomp, d, taps, stop_at, n, red);
-        else if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4>(c, in, out, ncomp, d, taps, stop_at, n, red);
-        else launch_yz_tz<R, 2>(c, in, out, ncomp, d, taps, stop_at, n, red);
+    return timed(c, K_SMOOTH_YZ, [&](const Ev &ev) {
+        if (deep) launch_yz_tz<R, max_tz<R>()>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
+        else if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
+        else launch_yz_tz<R, 2>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
     });
 }
 
@@ -173,8 +173,8 @@ hipError_t launch_smooth_yz(Ctx &c, const float *in, int ncomp, Dims d, const Ga
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out)
 {
     const Grid2 g = plane_grid(d);
-    return timed(c, K_SMOOTH_X, [&] {
-        hipLaunchKernelGGL(k_smooth_x, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), 0, c.stream, in, out, ncomp,
+    return timed(c, K_SMOOTH_X, [&](const Ev &ev) {
+        go(c, ev, k_smooth_x, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), in, out, ncomp,
                            d.nx, d.ny, d.nz, taps, g.gx, g.gy);
     });
 }

@@ -49,6 +49,8 @@ def test_host_only_entry_points():
     names = B.dir_timing_names()
     assert "force" in names and "smooth_x" in names and len(names) == L.dir_timing_count()
     assert L.dir_timing_name(-1) is None and L.dir_timing_name(len(names)) is None
+    assert L.dir_timing_read(None, 0, None, None) == B.DIR_EINVAL
+    assert L.dir_timing_read_level(None, 0, 0, None, None) == B.DIR_EINVAL
     # NULL handle: rejected before any device call
     assert L.dir_warp(None, None, None, 4, 4, 4, None) == B.DIR_EINVAL
     assert L.dir_register(None, None, None, 4, 4, 4, None, None, None, None) == B.DIR_EINVAL

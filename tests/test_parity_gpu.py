@@ -310,6 +310,30 @@ def test_bitwise_reproducible(B, h):
                                                             equal_nan=True)
 
 
+def test_timing_per_level_and_unchanged_results(B, h):
+    """Timed launches (dispatch-stamped events) give the same field, and the
+    per-level counts follow the iteration schedule."""
+    S, M, _ = _pair((12, 40, 48), 41)
+    params = B.make_params("active", [6, 4], sigma=1.0)
+    f0, _ = B.dir_register(h, dev(S), dev(M), params)
+    B.dir_timing_enable(h, ["force", "smooth_yz", "warp", "restrict"])
+    try:
+        f1, _ = B.dir_register(h, dev(S), dev(M), params)
+        reads = {k: (B.dir_timing_read(h, k), B.dir_timing_read(h, k, level=0), B.dir_timing_read(h, k, level=1))
+                 for k in ("force", "smooth_yz", "warp", "restrict", "compose")}
+    finally:
+        B.dir_timing_enable(h, ())
+    assert torch.equal(f0, f1)
+    for k in ("force", "smooth_yz", "warp"):
+        (ms, n), (ms0, n0), (ms1, n1) = reads[k]
+        assert (n, n0, n1) == (10, 4, 6), k
+        assert ms > 0 and ms0 > 0 and ms1 > 0 and abs(ms - ms0 - ms1) <= 1e-9 * max(ms, 1.0), k
+    assert reads["restrict"][0][1] == 2 and reads["restrict"][2][1] == 2   # S and M into level 1
+    assert reads["compose"][0] == (0.0, 0)                                   # not enabled
+    with pytest.raises(B.DemonsError):
+        B.dir_timing_read(h, "force", level=8)
+
+
 def test_stopping_rule(B, h):
     t = (0.6, -0.4, 0.5)
     S, M = P.smooth_translation_pair((20, 20, 20), t, seed=4)
