@@ -6,13 +6,21 @@ Workload: a seeded synthetic 4DCT-shaped pair of 256x256x100 voxels
 100/50/25 iterations coarse to fine, Gaussian sigma 1.5 voxels (R = 5), and
 the six force settings: passive, active, double force, alpha-normalised
 passive (alpha = 0.4), inverse-consistent, and double force with alpha = 0.4.
-One step registers the pair once with each of the six.
+One step registers the pair once with each of the six; the six are enqueued
+with dir_register_async on six handles, each with its own stream, so they
+overlap on the device, and the step ends when all six are collected.
 
-Prints one JSON line: voxel-iterations per second over the timed steps,
-per-registration latency percentiles, the roofline position of the kernel
-that takes the most device time (timed with HIP events on the library's
-stream during the timed steps), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line:
+  - value: voxel-iterations per second over the timed steps (no timing
+    events inside them);
+  - latency_ms: per-registration latency with each registration run alone
+    (blocking dir_register, one after another), and the step (batch) latency;
+  - sequential: the rate of the same steps run one registration at a time;
+  - roofline: the kernel that takes the most device time, its algorithmic
+    bytes per launch over its average launch time, from a separate pass of
+    sequential steps in which its launches carry dispatch-stamped HIP events
+    (each launch then runs alone on the device, as in a kernel trace);
+  - cpu_baseline: the FP64 CPU oracle on a bounded sample of the workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -44,8 +52,8 @@ METRIC = "voxel-iters/s + HBM GB/s fraction; p50/p99 per-registration latency"
 # once; stencil neighbours and gather re-reads are not counted).
 ALGO_BYTES_PER_VOXEL = {
     "force": 32.0,       # two images 8 + field 12 in + x-smoothed field 12 out
-    "warp": 20.0,        # image 4 + field 12 + out 4
-    "warp_pair": 28.0,   # M 4 + S 4 + h 12 + Im 4 + Is 4
+    "warp": 24.0,        # M 4 (gathered) + S 4 + field 12 + D = Im - S 4
+    "warp_pair": 28.0,   # M 4 + S 4 (both gathered) + h 12 + D 4 + P 4
     "smooth_yz": 24.0,   # field 12 in + 12 out
 }
 
@@ -114,6 +122,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--latency-steps", type=int, default=3,
+                    help="sequential steps for the latency and for the roofline pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gt", action="store_true", help="skip the ground-truth error pass (profiling runs)")
     ap.add_argument("--roofline-kernel", default=None, help="kernel to time for the roofline (default: largest)")
@@ -146,51 +156,77 @@ def main():
     dev = torch.device("cuda:0")
     S = torch.from_numpy(ph.static.astype(np.float32)).to(dev)
     M = torch.from_numpy(ph.moving.astype(np.float32)).to(dev)
-    out = torch.empty((3,) + tuple(S.shape), dtype=torch.float32, device=dev)
+    outs = [torch.empty((3,) + tuple(S.shape), dtype=torch.float32, device=dev) for _ in SETTINGS]
     params = {name: B.make_params(var, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha) for name, var, alpha in SETTINGS}
-    h = B.dir_create(0)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(device=dev) for _ in SETTINGS]       # default priority
+    handles = [B.dir_create(0, stream=st) for st in streams]
+    h = B.dir_create(0)                                                 # sequential passes
     vi_reg = voxel_iters(SHAPE, ITERS)
 
-    def step(lat=None):
-        for name, _, _ in SETTINGS:
+    def step():
+        """The six registrations, overlapped on the device."""
+        for hh, (name, _, _), o in zip(handles, SETTINGS, outs):
+            B.dir_register_async(hh, S, M, params[name], field_out=o, history=False)
+        for hh in handles:
+            B.dir_wait(hh)
+
+    def step_sequential(lat=None):
+        for (name, _, _), o in zip(SETTINGS, outs):
             t0 = time.perf_counter()
-            B.dir_register(h, S, M, params[name], field_out=out, history=False)
+            B.dir_register(h, S, M, params[name], field_out=o, history=False)
             if lat is not None:
                 lat.append((name, (time.perf_counter() - t0) * 1e3))
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
+        step_sequential()
     torch.cuda.synchronize()
 
-    # which kernel takes the most device time (one untimed step, all kernels timed)
+    # timed region: no timing events
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    step_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        step()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total_vi = vi_reg * len(SETTINGS) * args.steps
+    value = total_vi / elapsed
+
+    # the same steps one registration at a time: per-registration latency
+    print(f"[bench] sequential {args.latency_steps} steps", file=sys.stderr, flush=True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.latency_steps):
+        step_sequential(lat)
+    torch.cuda.synchronize()
+    seq_elapsed = time.perf_counter() - t0
+    lats = np.array([l for _, l in lat])
+    per_var = {name: float(np.median([l for n, l in lat if n == name])) for name, _, _ in SETTINGS}
+
+    # which kernel takes the most device time (one sequential step, all kernels timed)
     names = B.dir_timing_names()
     B.dir_timing_enable(h, names)
-    step()
+    step_sequential()
     per_kernel = {k: B.dir_timing_read(h, k) for k in names}
     B.dir_timing_enable(h, ())
     dominant = args.roofline_kernel or max(per_kernel, key=lambda k: per_kernel[k][0])
     print(f"[bench] per-kernel ms in one step: "
           + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in per_kernel.items() if v[1]), file=sys.stderr, flush=True)
 
-    # timed region: events bracket only the dominant kernel
+    # roofline pass: events on the dominant kernel only
     B.dir_timing_enable(h, [dominant])
-    lat = []
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(lat)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    for _ in range(args.latency_steps):
+        step_sequential()
     kern_ms, kern_launches = B.dir_timing_read(h, dominant)
     fine_ms, fine_launches = B.dir_timing_read(h, dominant, level=0)
     B.dir_timing_enable(h, ())
-
-    total_vi = vi_reg * len(SETTINGS) * args.steps
-    value = total_vi / elapsed
-    lats = np.array([l for _, l in lat])
-    per_var = {name: float(np.median([l for n, l in lat if n == name])) for name, _, _ in SETTINGS}
 
     # roofline of the dominant kernel: algorithmic bytes over its measured time
     n_ic = sum(1 for _, v, _ in SETTINGS if v == "inverse_consistent")
@@ -198,14 +234,15 @@ def main():
     units = launch_units(dominant, SHAPE, ITERS, n_ic, n_act, len(SETTINGS))
     roof = None
     if units is not None and dominant in ALGO_BYTES_PER_VOXEL and kern_launches:
-        bytes_total = units * ALGO_BYTES_PER_VOXEL[dominant] * args.steps
+        bytes_total = units * ALGO_BYTES_PER_VOXEL[dominant] * args.latency_steps
         achieved = bytes_total / (kern_ms * 1e-3) / 1e9
         traffic, traffic_src = measured_traffic(dominant)
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_us": kern_ms * 1e3 / kern_launches, "launches": kern_launches,
                 "algo_bytes_per_voxel": ALGO_BYTES_PER_VOXEL[dominant],
-                "bytes_per_launch": bytes_total / kern_launches, "traffic_source": traffic_src}
+                "bytes_per_launch": bytes_total / kern_launches, "traffic_source": traffic_src,
+                "timed_in": f"{args.latency_steps} sequential steps after the timed region"}
         if fine_launches:
             fine_bytes = SHAPE[0] * SHAPE[1] * SHAPE[2] * ALGO_BYTES_PER_VOXEL[dominant]
             fine_gbs = fine_bytes * fine_launches / (fine_ms * 1e-3) / 1e9
@@ -221,12 +258,14 @@ def main():
     vt, _ = ph.ground_truth(x.astype(float), y.astype(float), z.astype(float))
     gt = {}
     for name, _, _ in ([] if args.no_gt else SETTINGS):
-        B.dir_register(h, S, M, params[name], field_out=out, history=False)
-        f = out.view(3, -1)[:, torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
+        B.dir_register(h, S, M, params[name], field_out=outs[0], history=False)
+        f = outs[0].view(3, -1)[:, torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
         d = f - vt
         mm = np.sqrt((d[0] * SPACING[0]) ** 2 + (d[1] * SPACING[1]) ** 2 + (d[2] * SPACING[2]) ** 2)
         gt[name] = {"mean_vox": float(np.sqrt((d ** 2).sum(axis=0)).mean()), "mean_mm": float(mm.mean())}
     B.dir_destroy(h)
+    for hh in handles:
+        B.dir_destroy(hh)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -242,7 +281,10 @@ def main():
                    "shape_xyz": list(SHAPE), "iters_coarse_to_fine": ITERS, "sigma": SIGMA, "radius": RADIUS,
                    "settings": [s[0] for s in SETTINGS], "voxel_iters_per_step": vi_reg * len(SETTINGS)},
         "latency_ms": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99)),
-                       "per_setting_p50": per_var},
+                       "per_setting_p50": per_var, "alone": True,
+                       "step_p50": float(np.percentile(step_ms, 50)), "step_p99": float(np.percentile(step_ms, 99))},
+        "sequential": {"value": vi_reg * len(SETTINGS) * args.latency_steps / seq_elapsed,
+                       "ms_per_step": seq_elapsed * 1e3 / args.latency_steps, "steps": args.latency_steps},
         "roofline": roof,
         "cpu_baseline": cpu,
         "gt_error": gt,

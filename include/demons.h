@@ -24,10 +24,13 @@
  *     the caller; host pointers are named without the prefix.
  *   - nx*ny*nz must be at most 357,913,941 (a field of 12 bytes per voxel
  *     stays below 4 GiB); larger sizes return DIR_EINVAL.
- *   - All device work is enqueued on the handle's stream.  dir_register and
- *     dir_force block until their work is complete; the other entry points
- *     only enqueue (call dir_synchronize before reading their outputs on the
- *     host).
+ *   - All device work is enqueued on the handle's stream.  dir_register,
+ *     dir_force and dir_step block until their work is complete; the other
+ *     entry points only enqueue (call dir_synchronize before reading their
+ *     outputs on the host).  dir_register_async enqueues a whole registration
+ *     and returns; while it is in flight the handle refuses further work with
+ *     DIR_EBUSY until dir_wait collects it.  Registrations on distinct
+ *     handles with distinct streams run concurrently on the device.
  *   - Return value: DIR_OK or a negative dir_status; no exception crosses the
  *     ABI.  After an error the contents of output buffers are unspecified.
  *   - A handle is not thread-safe; distinct handles are independent.
@@ -51,7 +54,8 @@ typedef enum {
     DIR_EINVAL = -1,   /* bad argument (null pointer, size, parameter range) */
     DIR_ENOMEM = -2,   /* device or host allocation failed */
     DIR_EDEVICE = -3,  /* a HIP runtime call or kernel launch failed */
-    DIR_ENUMERIC = -4  /* a non-finite value appeared in the per-iteration sums */
+    DIR_ENUMERIC = -4, /* a non-finite value appeared in the per-iteration sums */
+    DIR_EBUSY = -5     /* a registration is in flight on the handle (dir_wait first) */
 } dir_status;
 
 /* Demons force variants (Sec 2.1-2.2).  The Pennec/Wang normalisation factor
@@ -132,6 +136,23 @@ int32_t dir_synchronize(dir_handle *h);
 int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
                      int32_t nz, const double *spacing_mm, const dir_params *params, float *d_field_out,
                      dir_stats *stats);
+
+/* dir_register without the wait: validates the arguments (same rules and
+ * codes as dir_register), enqueues every kernel of the registration on the
+ * handle's stream and returns DIR_OK.  d_static, d_moving and d_field_out
+ * must stay allocated and unmodified by other work until dir_wait returns;
+ * work that produced them on another stream must be ordered before the
+ * handle's stream by the caller.  Under the stopping rule (eps > 0) every
+ * iteration is enqueued and those after the rule fires return without work,
+ * so the result equals dir_register's.  One registration per handle may be
+ * in flight. */
+int32_t dir_register_async(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                           int32_t nz, const double *spacing_mm, const dir_params *params, float *d_field_out);
+
+/* Wait for the registration enqueued by dir_register_async and fill `stats`
+ * (may be NULL) as dir_register does; returns its status (DIR_ENUMERIC for a
+ * non-finite sum) or DIR_EINVAL when none is in flight. */
+int32_t dir_wait(dir_handle *h, dir_stats *stats);
 
 /* Deformed image (Sec 2.5 interpolation kernel): d_out(x) = vol(x - v(x)),
  * trilinear, coordinates clamped.  d_field: 3 planes. */

@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdemons.so")
 
-DIR_OK, DIR_EINVAL, DIR_ENOMEM, DIR_EDEVICE, DIR_ENUMERIC = 0, -1, -2, -3, -4
+DIR_OK, DIR_EINVAL, DIR_ENOMEM, DIR_EDEVICE, DIR_ENUMERIC, DIR_EBUSY = 0, -1, -2, -3, -4, -5
 DIR_PASSIVE, DIR_EVOLVED_PASSIVE, DIR_ACTIVE, DIR_DOUBLE, DIR_INVERSE_CONSISTENT = 0, 1, 2, 3, 4
 DIR_MAX_LEVELS = 8
 DIR_MAX_RADIUS = 16
@@ -76,6 +76,8 @@ def lib():
         L.dir_prolong.argtypes = [vp, vp, i32, i32, i32, vp, i32, i32, i32]
         L.dir_force.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(f64)]
         L.dir_step.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
+        L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
+        L.dir_wait.argtypes = [vp, vp]
         L.dir_compose.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.dir_timing_count.restype = i32
         L.dir_timing_name.restype = ctypes.c_char_p
@@ -85,6 +87,7 @@ def lib():
         L.dir_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
+                     "dir_register_async", "dir_wait",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
             getattr(L, name).restype = i32
         _lib = L
@@ -138,9 +141,11 @@ def _stream_ptr(stream, device):
 class Handle:
     """Owns one dir_handle; use as a context manager or call dir_destroy."""
 
-    def __init__(self, ptr, device):
+    def __init__(self, ptr, device, stream=None):
         self.ptr = ptr
         self.device = device
+        self.stream = stream      # torch stream the handle enqueues on (None: the current one at creation)
+        self.inflight = None      # tensors and stats buffer of a registration not yet collected
 
     def __enter__(self):
         return self
@@ -163,12 +168,17 @@ def dir_strerror(code):
 
 def dir_create(device=0, stream=None):
     h = ctypes.c_void_p()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
     _check(lib().dir_create(ctypes.byref(h), int(device), _stream_ptr(stream, device)), "dir_create")
-    return Handle(h, device)
+    return Handle(h, device, stream if isinstance(stream, torch.cuda.Stream) else None)
 
 
 def dir_set_stream(h, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream(h.device)
     _check(lib().dir_set_stream(h.ptr, _stream_ptr(stream, h.device)), "dir_set_stream")
+    h.stream = stream if isinstance(stream, torch.cuda.Stream) else None
 
 
 def dir_destroy(h):
@@ -204,16 +214,19 @@ def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_ite
     return p
 
 
-def dir_register(h, static, moving, params, field_out=None, spacing_mm=None, history=True):
-    """Register `moving` onto `static`; returns (field [3,nz,ny,nx], stats dict)."""
+def _register_args(static, moving, params, field_out, spacing_mm):
     _dev_f32(static, "static", 3)
     _dev_f32(moving, "moving", 3)
     if static.shape != moving.shape:
         raise ValueError("static and moving differ in shape")
-    nx, ny, nz = _dims(static)
     if field_out is None:
         field_out = torch.empty((3,) + tuple(static.shape), dtype=torch.float32, device=static.device)
     _dev_f32(field_out, "field_out", 4)
+    sp = (ctypes.c_double * 3)(*spacing_mm) if spacing_mm is not None else None
+    return field_out, sp
+
+
+def _new_stats(params, history):
     st = dir_stats()
     st.struct_size = ctypes.sizeof(dir_stats)
     total = sum(params.iters[k] for k in range(params.levels))
@@ -221,15 +234,56 @@ def dir_register(h, static, moving, params, field_out=None, spacing_mm=None, his
     if history:
         st.history = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
         st.history_capacity = total
-    sp = (ctypes.c_double * 3)(*spacing_mm) if spacing_mm is not None else None
-    rc = lib().dir_register(h.ptr, _ptr(static), _ptr(moving), nx, ny, nz, sp, ctypes.byref(params),
-                            _ptr(field_out), ctypes.byref(st))
+    return st, buf
+
+
+def _stats_dict(rc, st, buf):
     stats = {"rc": rc, "levels": st.levels, "iters_run": list(st.iters_run)[:st.levels],
              "mse_final": st.mse_final, "relnorm_final": st.relnorm_final, "history": None}
-    if history:
+    if buf is not None:
         stats["history"] = [tuple(buf[4 * i:4 * i + 4]) for i in range(st.history_len)]
+    return stats
+
+
+def dir_register(h, static, moving, params, field_out=None, spacing_mm=None, history=True):
+    """Register `moving` onto `static`; returns (field [3,nz,ny,nx], stats dict)."""
+    field_out, sp = _register_args(static, moving, params, field_out, spacing_mm)
+    nx, ny, nz = _dims(static)
+    st, buf = _new_stats(params, history)
+    rc = lib().dir_register(h.ptr, _ptr(static), _ptr(moving), nx, ny, nz, sp, ctypes.byref(params),
+                            _ptr(field_out), ctypes.byref(st))
+    stats = _stats_dict(rc, st, buf)
     if rc != DIR_OK:
         raise DemonsError(rc, "dir_register")
+    return field_out, stats
+
+
+def dir_register_async(h, static, moving, params, field_out=None, spacing_mm=None, history=True):
+    """Enqueue a registration on the handle's stream and return at once; the
+    field is complete when dir_wait(h) returns.  The handle's stream first
+    waits for the caller's current stream (where the inputs were made)."""
+    field_out, sp = _register_args(static, moving, params, field_out, spacing_mm)
+    nx, ny, nz = _dims(static)
+    if h.stream is not None and h.stream != torch.cuda.current_stream(h.device):
+        h.stream.wait_stream(torch.cuda.current_stream(h.device))
+    rc = lib().dir_register_async(h.ptr, _ptr(static), _ptr(moving), nx, ny, nz, sp, ctypes.byref(params),
+                                  _ptr(field_out))
+    _check(rc, "dir_register_async")
+    st, buf = _new_stats(params, history)
+    h.inflight = (static, moving, field_out, params, st, buf)
+    return field_out
+
+
+def dir_wait(h):
+    """Collect the registration enqueued by dir_register_async: (field, stats)."""
+    if h.inflight is None:
+        raise DemonsError(DIR_EINVAL, "dir_wait: nothing in flight")
+    _, _, field_out, _, st, buf = h.inflight
+    rc = lib().dir_wait(h.ptr, ctypes.byref(st))
+    h.inflight = None
+    stats = _stats_dict(rc, st, buf)
+    if rc != DIR_OK:
+        raise DemonsError(rc, "dir_wait")
     return field_out, stats
 
 

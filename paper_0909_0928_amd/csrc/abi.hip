@@ -53,6 +53,15 @@ struct DevBuf {
 
 }  // namespace
 
+// A registration enqueued by dir_register_async (or dir_register) whose
+// statistics have not been collected yet.
+struct InFlight {
+    bool active = false;
+    int levels = 0;
+    int64_t total_iters = 0;
+    int64_t hist_off[DIR_MAX_LEVELS] = {};
+};
+
 struct dir_handle {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -63,6 +72,7 @@ struct dir_handle {
     DevBuf partials;               // 3 doubles per force workgroup
     DevBuf history;                // 4 doubles per iteration, per-level fixed offsets
     DevBuf state;                  // one LevelState per level
+    InFlight inflight;             // registration enqueued and not yet collected
 };
 
 namespace {
@@ -120,6 +130,23 @@ int enter(dir_handle *h)
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
     h->timer.level = 0;
+    return DIR_OK;
+}
+
+// enter() for calls that enqueue work: refused while a registration is in
+// flight on the handle (its workspace is in use until dir_wait).
+int enter_idle(dir_handle *h)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    return h->inflight.active ? DIR_EBUSY : DIR_OK;
+}
+
+// Copy device bytes to the host on the handle's stream and wait for them.
+int copy_to_host(dir_handle *h, void *dst, const void *src, size_t bytes)
+{
+    DIR_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    DIR_TRY(hipStreamSynchronize(h->stream));
     return DIR_OK;
 }
 
@@ -220,6 +247,7 @@ const char *dir_strerror(int32_t code)
     case DIR_ENOMEM: return "out of memory";
     case DIR_EDEVICE: return "HIP device error";
     case DIR_ENUMERIC: return "non-finite value in the registration sums";
+    case DIR_EBUSY: return "a registration is in flight on this handle (collect it with dir_wait)";
     default: return "unknown status code";
     }
 }
@@ -246,7 +274,7 @@ int32_t dir_create(dir_handle **out, int32_t device, void *stream)
 
 int32_t dir_set_stream(dir_handle *h, void *stream)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     rc = finish(h);  // work already enqueued on the old stream completes first
     h->stream = static_cast<hipStream_t>(stream);
@@ -321,7 +349,7 @@ int32_t dir_timing_read_level(dir_handle *h, int32_t kernel, int32_t level, doub
 int32_t dir_warp(dir_handle *h, const float *d_vol, const float *d_field, int32_t nx, int32_t ny, int32_t nz,
                  float *d_out)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     if (!d_vol || !d_field || !d_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     Ctx c{h->stream, &h->timer};
@@ -331,7 +359,7 @@ int32_t dir_warp(dir_handle *h, const float *d_vol, const float *d_field, int32_
 
 int32_t dir_gradient(dir_handle *h, const float *d_img, int32_t nx, int32_t ny, int32_t nz, float *d_grad)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     if (!d_img || !d_grad || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     Ctx c{h->stream, &h->timer};
@@ -342,7 +370,7 @@ int32_t dir_gradient(dir_handle *h, const float *d_img, int32_t nx, int32_t ny, 
 int32_t dir_smooth(dir_handle *h, const float *d_in, int32_t ncomp, int32_t nx, int32_t ny, int32_t nz,
                    double sigma, int32_t radius, float *d_out)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     if (!d_in || !d_out || ncomp < 1 || ncomp > 3 || !dims_ok(nx, ny, nz) || !(sigma > 0.0) || !isfinite(sigma))
         return DIR_EINVAL;
@@ -363,7 +391,7 @@ int32_t dir_smooth(dir_handle *h, const float *d_in, int32_t ncomp, int32_t nx, 
 
 int32_t dir_restrict(dir_handle *h, const float *d_in, int32_t nx, int32_t ny, int32_t nz, float *d_out)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     if (!d_in || !d_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     const Dims f{nx, ny, nz};
@@ -375,7 +403,7 @@ int32_t dir_restrict(dir_handle *h, const float *d_in, int32_t nx, int32_t ny, i
 int32_t dir_prolong(dir_handle *h, const float *d_coarse, int32_t cnx, int32_t cny, int32_t cnz, float *d_fine,
                     int32_t fnx, int32_t fny, int32_t fnz)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     if (!d_coarse || !d_fine || !dims_ok(cnx, cny, cnz) || !dims_ok(fnx, fny, fnz)) return DIR_EINVAL;
     Ctx c{h->stream, &h->timer};
@@ -386,7 +414,7 @@ int32_t dir_prolong(dir_handle *h, const float *d_coarse, int32_t cnx, int32_t c
 int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, int32_t nz, int32_t K,
                     float *d_out)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     if (!d_half || !d_out || !dims_ok(nx, ny, nz) || d_half == d_out) return DIR_EINVAL;
     if (K < 0) K = DIR_DEFAULT_COMPOSE_ITERS;
@@ -494,7 +522,8 @@ int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, co
     if (rc != DIR_OK) return rc;
     if (sums) {
         double e[4];
-        DIR_TRY(hipMemcpy(e, h->history.p, sizeof e, hipMemcpyDeviceToHost));
+        rc = copy_to_host(h, e, h->history.p, sizeof e);
+        if (rc != DIR_OK) return rc;
         sums[0] = e[0];
         sums[1] = e[1];
         sums[2] = e[2];  // inv_n = 1: the plain sum of D^2
@@ -509,7 +538,7 @@ extern "C" {
 int32_t dir_force(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
                   const float *d_field, int32_t nx, int32_t ny, int32_t nz, float *d_updated, double *sums)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, nullptr, d_updated, sums);
 }
@@ -518,7 +547,7 @@ int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_st
                  const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma, int32_t radius,
                  float *d_field_out, double *sums)
 {
-    int rc = enter(h);
+    int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
     if (!(sigma > 0.0) || !isfinite(sigma)) return DIR_EINVAL;
     const int R = resolve_radius(sigma, radius);
@@ -527,16 +556,22 @@ int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_st
     return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, &taps, d_field_out, sums);
 }
 
-int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
-                     int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out,
-                     dir_stats *stats)
+}  // extern "C"
+
+namespace {
+
+// Validate and enqueue one registration on the handle's stream and record it
+// as in flight.  With `poll`, a level run under the stopping rule (eps > 0)
+// reads its stop flag every 10 iterations and enqueues no further
+// iterations once the rule has fired; without it every iteration is enqueued
+// and the kernels of iterations after the stop return at once.
+int submit_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                    int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out, bool poll)
 {
-    int rc = enter(h);
-    if (rc != DIR_OK) return rc;
+    int rc = DIR_OK;
     // ---- validation ----
     if (!d_static || !d_moving || !p || !d_field_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     if (p->struct_size != (int32_t)sizeof(dir_params) || p->reserved != 0) return DIR_EINVAL;
-    if (stats && stats->struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
     if (spacing_mm)
         for (int k = 0; k < 3; ++k)
             if (!(spacing_mm[k] > 0.0) || !isfinite(spacing_mm[k])) return DIR_EINVAL;
@@ -629,7 +664,7 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
             // smoothing kernel also reduces the sums of this iteration
             DIR_TRY(force_half(h, c, variant, alpha2, Sk[k], Mk[k], v, d, taps, xs, &st->stop_at, n));
             DIR_TRY(launch_smooth_yz(c, xs, 3, d, taps, v, &st->stop_at, n, red));
-            if (p->eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
+            if (poll && p->eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
                 int stop_at = kNeverStopped;
                 DIR_TRY(hipMemcpyAsync(&stop_at, &st->stop_at, sizeof(int), hipMemcpyDeviceToHost, h->stream));
                 DIR_TRY(hipStreamSynchronize(h->stream));
@@ -643,14 +678,36 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
     h->timer.level = 0;
     if (variant == kInverseConsistent) DIR_TRY(launch_compose(c, v, dims[0], K, d_field_out));
     else DIR_TRY(hipMemcpyAsync(d_field_out, v, sizeof(float) * 3 * n0, hipMemcpyDeviceToDevice, h->stream));
-    rc = finish(h);
+    InFlight &f = h->inflight;
+    f.active = true;
+    f.levels = L;
+    f.total_iters = total_iters;
+    for (int li = 0; li < L; ++li) f.hist_off[li] = hist_off[li];
+    return DIR_OK;
+}
+
+// Wait for the in-flight registration and fill `stats` (may be NULL).
+int collect_register(dir_handle *h, dir_stats *stats)
+{
+    InFlight f = h->inflight;
+    h->inflight.active = false;
+    const int L = f.levels;
+    const int64_t total_iters = f.total_iters;
+    const int64_t *hist_off = f.hist_off;
+    LevelState *states = h->state.as<LevelState>();
+    double *hist = h->history.as<double>();
+    int rc = finish(h);
     if (rc != DIR_OK) return rc;
 
     // ---- statistics and the numeric check ----
     LevelState hs[DIR_MAX_LEVELS];
-    DIR_TRY(hipMemcpy(hs, states, sizeof(LevelState) * L, hipMemcpyDeviceToHost));
+    rc = copy_to_host(h, hs, states, sizeof(LevelState) * L);
+    if (rc != DIR_OK) return rc;
     std::vector<double> hh((size_t)4 * (size_t)(total_iters > 0 ? total_iters : 1));
-    if (total_iters > 0) DIR_TRY(hipMemcpy(hh.data(), hist, sizeof(double) * 4 * total_iters, hipMemcpyDeviceToHost));
+    if (total_iters > 0) {
+        rc = copy_to_host(h, hh.data(), hist, sizeof(double) * 4 * total_iters);
+        if (rc != DIR_OK) return rc;
+    }
     bool finite = true;
     int64_t packed = 0;
     double last_mse = 0.0, last_l = __builtin_nan("");
@@ -675,6 +732,40 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
                                                       : 0);
     }
     return finite ? DIR_OK : DIR_ENUMERIC;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                     int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out,
+                     dir_stats *stats)
+{
+    int rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    if (stats && stats->struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
+    rc = submit_register(h, d_static, d_moving, nx, ny, nz, spacing_mm, p, d_field_out, true);
+    if (rc != DIR_OK) return rc;
+    return collect_register(h, stats);
+}
+
+int32_t dir_register_async(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                           int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out)
+{
+    int rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    return submit_register(h, d_static, d_moving, nx, ny, nz, spacing_mm, p, d_field_out, false);
+}
+
+int32_t dir_wait(dir_handle *h, dir_stats *stats)
+{
+    int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!h->inflight.active) return DIR_EINVAL;
+    if (stats && stats->struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
+    return collect_register(h, stats);
 }
 
 }  // extern "C"

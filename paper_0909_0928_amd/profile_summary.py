@@ -63,9 +63,18 @@ def trace_summary(d: str, command: str, out: str) -> None:
     stats = list(csv.DictReader(open(_one(os.path.join(d, "*kernel_stats.csv")))))
     trace = list(csv.DictReader(open(_one(os.path.join(d, "*kernel_trace.csv")))))
     per = collections.defaultdict(list)
-    for r in trace:
+    solo = collections.defaultdict(list)   # launches during which no other kernel ran
+    recs = sorted(((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r) for r in trace), key=lambda t: t[0])
+    max_end = -1
+    for i, (t0, t1, r) in enumerate(recs):
         g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
-        per[(_short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        k = _short(r["Kernel_Name"])
+        us = (t1 - t0) / 1e3
+        per[(k, g)].append(us)
+        alone = max_end <= t0 and (i + 1 == len(recs) or recs[i + 1][0] >= t1)
+        if alone:
+            solo[(re.sub(r"<.*", "", k), g)].append(us)
+        max_end = max(max_end, t1)
     lines = ["# rocprofv3 kernel trace summary", "", "Command (repository root, on one MI355X):", "",
              "```", command, "```", "",
              "## Per kernel (rocprofv3 --stats)", "",
@@ -80,6 +89,16 @@ def trace_summary(d: str, command: str, out: str) -> None:
               "| kernel | calls | average us | total ms |", "|---|---|---|---|"]
     for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / len(v):.2f} | {sum(v) / 1e3:.2f} |")
+    lines += ["", "## Launches that ran alone on the device (no other kernel overlapping), per library kernel",
+              "", "| kernel | grid threads | calls | average us |", "|---|---|---|---|"]
+    sagg = collections.defaultdict(list)
+    for (k, g), v in solo.items():
+        sagg[k] += v
+    for k, v in sorted(sagg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{k}` | all | {len(v)} | {sum(v) / len(v):.2f} |")
+        for (k2, g), v2 in sorted(solo.items(), key=lambda kv: -kv[0][1]):
+            if k2 == k:
+                lines.append(f"| `{k}` | {g} | {len(v2)} | {sum(v2) / len(v2):.2f} |")
     lines += ["", "## Per kernel and grid size (from the kernel trace)", "",
               "| kernel | grid threads | calls | average us | total ms |", "|---|---|---|---|---|"]
     for (k, g), v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:30]:
