@@ -161,7 +161,7 @@ def main():
     torch.cuda.synchronize()
     streams = [torch.cuda.Stream(device=dev) for _ in SETTINGS]       # default priority
     handles = [B.dir_create(0, stream=st) for st in streams]
-    h = B.dir_create(0)                                                 # sequential passes
+    h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))           # sequential passes
     vi_reg = voxel_iters(SHAPE, ITERS)
 
     def step():

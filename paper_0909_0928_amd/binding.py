@@ -78,6 +78,7 @@ def lib():
         L.dir_step.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.dir_wait.argtypes = [vp, vp]
+        L.dir_set_graphs.argtypes = [vp, i32]
         L.dir_compose.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.dir_timing_count.restype = i32
         L.dir_timing_name.restype = ctypes.c_char_p
@@ -87,7 +88,7 @@ def lib():
         L.dir_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
-                     "dir_register_async", "dir_wait",
+                     "dir_register_async", "dir_wait", "dir_set_graphs",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
             getattr(L, name).restype = i32
         _lib = L
@@ -186,6 +187,10 @@ def dir_destroy(h):
         rc = lib().dir_destroy(h.ptr)
         h.ptr = ctypes.c_void_p()
         _check(rc, "dir_destroy")
+
+
+def dir_set_graphs(h, enable):
+    _check(lib().dir_set_graphs(h.ptr, int(bool(enable))), "dir_set_graphs")
 
 
 def dir_synchronize(h):

@@ -53,6 +53,17 @@ struct DevBuf {
 
 }  // namespace
 
+// Key of a captured registration: the call's arguments and every workspace
+// address its kernels use.  Replaying the graph is only valid for an equal key.
+// Laid out without implicit padding, so keys compare with memcmp.
+struct GraphKey {
+    const void *S, *M, *out;
+    const void *ws[10];
+    dir_params params;
+    int32_t nx, ny, nz, pad;
+};
+static_assert(sizeof(GraphKey) == 13 * sizeof(void *) + sizeof(dir_params) + 16, "GraphKey has padding");
+
 // A registration enqueued by dir_register_async (or dir_register) whose
 // statistics have not been collected yet.
 struct InFlight {
@@ -73,6 +84,9 @@ struct dir_handle {
     DevBuf history;                // 4 doubles per iteration, per-level fixed offsets
     DevBuf state;                  // one LevelState per level
     InFlight inflight;             // registration enqueued and not yet collected
+    bool graphs = false;           // capture registrations into HIP graphs (dir_set_graphs)
+    hipGraphExec_t graph_exec = nullptr;  // the last captured registration
+    GraphKey graph_key;            // ... and what it was captured for
 };
 
 namespace {
@@ -287,6 +301,7 @@ int32_t dir_destroy(dir_handle *h)
     int rc = enter(h);
     if (rc == DIR_OK) hipStreamSynchronize(h->stream);
     h->timer.release();
+    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
     h->pyr_s.release();
     h->pyr_m.release();
     for (auto &f : h->field) f.release();
@@ -304,6 +319,19 @@ int32_t dir_synchronize(dir_handle *h)
     int rc = enter(h);
     if (rc != DIR_OK) return rc;
     return finish(h);
+}
+
+int32_t dir_set_graphs(dir_handle *h, int32_t enable)
+{
+    int rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    h->graphs = enable != 0;
+    if (!h->graphs && h->graph_exec) {
+        rc = finish(h);
+        hipGraphExecDestroy(h->graph_exec);
+        h->graph_exec = nullptr;
+    }
+    return rc;
 }
 
 int32_t dir_timing_count(void) { return K_COUNT; }
@@ -560,13 +588,24 @@ int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_st
 
 namespace {
 
-// Validate and enqueue one registration on the handle's stream and record it
-// as in flight.  With `poll`, a level run under the stopping rule (eps > 0)
-// reads its stop flag every 10 iterations and enqueues no further
-// iterations once the rule has fired; without it every iteration is enqueued
-// and the kernels of iterations after the stop return at once.
-int submit_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
-                    int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out, bool poll)
+// Everything one registration needs to enqueue its kernels: validated
+// arguments, level sizes and the history layout.
+struct RegPlan {
+    const float *S, *M;
+    float *out;
+    int variant, L, K;
+    float alpha2;
+    double eps;
+    GaussTaps taps;
+    Dims dims[DIR_MAX_LEVELS];
+    int iters[DIR_MAX_LEVELS];
+    int64_t total_iters;
+    int64_t hist_off[DIR_MAX_LEVELS];
+};
+
+// Validate the arguments of a registration and size the workspace for it.
+int plan_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny, int32_t nz,
+                  const double *spacing_mm, const dir_params *p, float *d_field_out, RegPlan &pl)
 {
     int rc = DIR_OK;
     // ---- validation ----
@@ -619,6 +658,40 @@ int submit_register(dir_handle *h, const float *d_static, const float *d_moving,
     DIR_TRY(h->history.ensure(sizeof(double) * 4 * (size_t)(total_iters > 0 ? total_iters : 1)));
     DIR_TRY(h->state.ensure(sizeof(LevelState) * DIR_MAX_LEVELS));
 
+    pl.S = d_static;
+    pl.M = d_moving;
+    pl.out = d_field_out;
+    pl.variant = variant;
+    pl.L = L;
+    pl.K = K;
+    pl.alpha2 = alpha2;
+    pl.eps = p->eps;
+    pl.taps = taps;
+    pl.total_iters = total_iters;
+    int64_t off = 0;
+    for (int k = 0; k < L; ++k) {
+        pl.dims[k] = dims[k];
+        pl.iters[k] = p->iters[k];  // coarsest first
+        pl.hist_off[k] = off;
+        off += p->iters[k];
+    }
+    return DIR_OK;
+}
+
+// Enqueue the kernels of a planned registration on the handle's stream.  With
+// `poll`, a level run under the stopping rule (eps > 0) reads its stop flag
+// every 10 iterations and enqueues no further iterations once the rule has
+// fired; without it every iteration is enqueued and the kernels of
+// iterations after the stop return at once.
+int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
+{
+    const int L = pl.L, variant = pl.variant, K = pl.K;
+    const Dims *dims = pl.dims;
+    const GaussTaps &taps = pl.taps;
+    const float alpha2 = pl.alpha2;
+    const float *d_static = pl.S, *d_moving = pl.M;
+    float *d_field_out = pl.out;
+
     Ctx c{h->stream, &h->timer};
     const float *Sk[DIR_MAX_LEVELS], *Mk[DIR_MAX_LEVELS];
     Sk[0] = d_static;
@@ -637,52 +710,121 @@ int submit_register(dir_handle *h, const float *d_static, const float *d_moving,
     }
 
     // ---- levels, coarse to fine (Sec 2.3) ----
-    float *v = h->field[0].as<float>(), *xs = h->field[1].as<float>();
+    // The finest level's field lives in d_field_out itself, except for the
+    // inverse-consistent variant, whose half field is composed into it.
+    float *const fa = h->field[0].as<float>(), *const fb = h->field[1].as<float>();
+    float *const final_v = variant == kInverseConsistent ? nullptr : d_field_out;
+    float *v = (L == 1 && final_v) ? final_v : fa;
     LevelState *states = h->state.as<LevelState>();
     double *hist = h->history.as<double>();
-    int64_t hist_off[DIR_MAX_LEVELS];
     h->timer.level = L - 1;
     DIR_TRY(launch_zero(c, v, 3 * dims[L - 1].n()));
-    int64_t off = 0;
     for (int k = L - 1; k >= 0; --k) {
         const int li = L - 1 - k;
         const Dims d = dims[k];
         h->timer.level = k;
         if (k < L - 1) {
-            DIR_TRY(launch_prolong(c, v, dims[k + 1], xs, d));
-            float *t = v;
-            v = xs;
-            xs = t;
+            float *dst = (k == 0 && final_v) ? final_v : (v == fa ? fb : fa);
+            DIR_TRY(launch_prolong(c, v, dims[k + 1], dst, d));
+            v = dst;
         }
+        float *const xs = v == fa ? fb : fa;  // x-smoothed u of this level
         LevelState *st = states + li;
         DIR_TRY(launch_level_reset(c, st));
-        hist_off[li] = off;
-        const int iters = p->iters[li];
-        const SumsReduce red = sums_reduce(h, d, hist + 4 * off, st, p->eps);
+        const int iters = pl.iters[li];
+        const SumsReduce red = sums_reduce(h, d, hist + 4 * pl.hist_off[li], st, pl.eps);
         for (int n = 0; n < iters; ++n) {
             // v -> xs = x-smoothed (v + dr) -> v = y,z-smoothed xs; the
             // smoothing kernel also reduces the sums of this iteration
             DIR_TRY(force_half(h, c, variant, alpha2, Sk[k], Mk[k], v, d, taps, xs, &st->stop_at, n));
             DIR_TRY(launch_smooth_yz(c, xs, 3, d, taps, v, &st->stop_at, n, red));
-            if (poll && p->eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
+            if (poll && pl.eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
                 int stop_at = kNeverStopped;
                 DIR_TRY(hipMemcpyAsync(&stop_at, &st->stop_at, sizeof(int), hipMemcpyDeviceToHost, h->stream));
                 DIR_TRY(hipStreamSynchronize(h->stream));
                 if (stop_at != kNeverStopped) break;
             }
         }
-        off += iters;
     }
 
     // ---- output ----
     h->timer.level = 0;
     if (variant == kInverseConsistent) DIR_TRY(launch_compose(c, v, dims[0], K, d_field_out));
-    else DIR_TRY(hipMemcpyAsync(d_field_out, v, sizeof(float) * 3 * n0, hipMemcpyDeviceToDevice, h->stream));
+    return DIR_OK;
+}
+
+GraphKey graph_key(dir_handle *h, const RegPlan &pl, const dir_params *p)
+{
+    GraphKey k;
+    memset(&k, 0, sizeof k);
+    k.S = pl.S;
+    k.M = pl.M;
+    k.out = pl.out;
+    k.nx = pl.dims[0].nx;
+    k.ny = pl.dims[0].ny;
+    k.nz = pl.dims[0].nz;
+    memcpy(&k.params, p, sizeof k.params);
+    const DevBuf *bufs[10] = {&h->pyr_s, &h->pyr_m, &h->field[0], &h->field[1], &h->field[2],
+                              &h->img_a, &h->img_b, &h->partials, &h->history, &h->state};
+    for (int i = 0; i < 10; ++i) k.ws[i] = bufs[i]->p;
+    return k;
+}
+
+// Capture the registration's launches into a graph and instantiate it.
+int capture_register(dir_handle *h, const RegPlan &pl, hipGraphExec_t *exec)
+{
+    DIR_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+    const int rc = enqueue_register(h, pl, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != DIR_OK) {
+        if (e == hipSuccess && g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+    const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail_hip(ei, "hipGraphInstantiate");
+    return DIR_OK;
+}
+
+// Validate and enqueue one registration on the handle's stream and record it
+// as in flight.  Without a host wait inside the registration (no polled
+// stopping rule) and without kernel timing, the launches are captured once
+// into a HIP graph and the graph is replayed while the arguments and the
+// workspace stay the same; otherwise (or on the null stream, which cannot be
+// captured) they are enqueued one by one.
+int submit_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                    int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out, bool poll)
+{
+    RegPlan pl;
+    int rc = plan_register(h, d_static, d_moving, nx, ny, nz, spacing_mm, p, d_field_out, pl);
+    if (rc != DIR_OK) return rc;
+    const bool graph = h->graphs && h->stream != nullptr && h->timer.mask == 0 && !(poll && pl.eps > 0.0);
+    if (graph) {
+        const GraphKey key = graph_key(h, pl, p);
+        if (!h->graph_exec || memcmp(&key, &h->graph_key, sizeof key) != 0) {
+            if (h->graph_exec) {
+                hipGraphExecDestroy(h->graph_exec);
+                h->graph_exec = nullptr;
+            }
+            rc = capture_register(h, pl, &h->graph_exec);
+            if (rc != DIR_OK) {
+                h->graph_exec = nullptr;
+                return rc;
+            }
+            memcpy(&h->graph_key, &key, sizeof key);
+        }
+        DIR_TRY(hipGraphLaunch(h->graph_exec, h->stream));
+    } else {
+        rc = enqueue_register(h, pl, poll);
+        if (rc != DIR_OK) return rc;
+    }
     InFlight &f = h->inflight;
     f.active = true;
-    f.levels = L;
-    f.total_iters = total_iters;
-    for (int li = 0; li < L; ++li) f.hist_off[li] = hist_off[li];
+    f.levels = pl.L;
+    f.total_iters = pl.total_iters;
+    for (int li = 0; li < pl.L; ++li) f.hist_off[li] = pl.hist_off[li];
     return DIR_OK;
 }
 

@@ -240,6 +240,31 @@ __device__ __forceinline__ double bsample64(__amdgpu_buffer_rsrc_t I, const BCel
     return az * (ay * c00 + by * c10) + bz * (ay * c01 + by * c11);
 }
 
+// FP32 trilinear samples of three planes `plane` bytes apart (a field's
+// components) at one cell: the corner offsets are formed once and the plane
+// goes to the scalar offset.  Lower-corner weight w0: w0 * a + (1 - w0) * b.
+__device__ __forceinline__ void bsample3(__amdgpu_buffer_rsrc_t I, const BCell &c, unsigned plane, float &s0,
+                                         float &s1, float &s2)
+{
+    const unsigned o = c.o, oy = o + c.dy, oz = o + c.dz, oyz = oz + c.dy;
+    float r[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const unsigned so = (unsigned)k * plane;
+        const float b00 = bload(I, o + c.dx, so), b10 = bload(I, oy + c.dx, so);
+        const float b01 = bload(I, oz + c.dx, so), b11 = bload(I, oyz + c.dx, so);
+        const float c00 = fmaf(c.wx, bload(I, o, so) - b00, b00);
+        const float c10 = fmaf(c.wx, bload(I, oy, so) - b10, b10);
+        const float c01 = fmaf(c.wx, bload(I, oz, so) - b01, b01);
+        const float c11 = fmaf(c.wx, bload(I, oyz, so) - b11, b11);
+        const float d0 = fmaf(c.wy, c00 - c10, c10), d1 = fmaf(c.wy, c01 - c11, c11);
+        r[k] = fmaf(c.wz, d0 - d1, d1);
+    }
+    s0 = r[0];
+    s1 = r[1];
+    s2 = r[2];
+}
+
 // Decode a flattened workgroup id into (tile x, tile y, z), XCD-contiguous.
 struct Tile {
     int x, y, z;

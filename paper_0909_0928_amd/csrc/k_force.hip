@@ -5,8 +5,10 @@
 // A workgroup of 256 threads owns an x tile of TX voxels (TX = 64, 128 or
 // 256; 256/TX rows in flight) and walks `rows_per_block` row steps.  For each
 // row it evaluates u = v + dr at the TX tile voxels plus an R-voxel halo on
-// both sides (indices clamped, so a halo entry equals u at the clamped
-// voxel), stages u in LDS and writes the x-smoothed field.  The per-voxel sums
+// both sides where the halo lies inside the row (past a row end the halo is
+// the end voxel's u, by index clamping, and is copied, not recomputed: a
+// tile spanning the whole row evaluates each voxel once), stages u in LDS
+// and writes the x-smoothed field.  The per-voxel sums
 // sum|dr|, sum|v| and sum D^2 are accumulated in FP64 over the tile voxels
 // only, reduced per workgroup in a fixed order and written to per-workgroup
 // slots.  The slots are added up, in slot order, by one workgroup of the
@@ -179,15 +181,33 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
             ro.yp = rowb * (unsigned)(min(y + 1, a.ny - 1) + a.ny * z);
             ro.zm = rowb * (unsigned)(y + a.ny * max(z - 1, 0));
             ro.zp = rowb * (unsigned)(y + a.ny * min(z + 1, a.nz - 1));
-            for (int p = lane; p < TX + 2 * R; p += TX) {
-                const int xx = x0 - R + p;
+            // Evaluate only the points of the tile and its halo that lie in
+            // the row: a halo slot beyond a row end holds the end voxel's u
+            // (clamped index), so the end lanes copy theirs there instead.
+            const int p_lo = max(R - x0, 0), p_hi = min(TX + 2 * R, a.nx - x0 + R);
+            for (int p = p_lo + lane; p < p_hi; p += TX) {
+                const int xx = x0 - R + p;  // in [0, nx)
                 float u0, u1, u2;
                 double adr, av, d2;
-                force_point<V>(a, b, clampi(xx, a.nx), y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
+                force_point<V>(a, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
                 ul[0][wrow][p] = u0;
                 ul[1][wrow][p] = u1;
                 ul[2][wrow][p] = u2;
-                if (p >= R && p < TX + R && xx < a.nx) {  // a tile voxel: counted once
+                if (xx == 0)
+                    for (int q = 0; q < p; ++q) {
+                        ul[0][wrow][q] = u0;
+                        ul[1][wrow][q] = u1;
+                        ul[2][wrow][q] = u2;
+                    }
+                // slots past the row end up to the last one the x pass reads:
+                // min(TX, nx - x0) - 1 + 2R = min(p + R, TX + 2R - 1)
+                if (xx == a.nx - 1)
+                    for (int q = p + 1; q <= min(p + R, TX + 2 * R - 1); ++q) {
+                        ul[0][wrow][q] = u0;
+                        ul[1][wrow][q] = u1;
+                        ul[2][wrow][q] = u2;
+                    }
+                if (p >= R && p < TX + R) {  // a tile voxel: counted once
                     s1 += adr;
                     s2 += av;
                     sse += d2;

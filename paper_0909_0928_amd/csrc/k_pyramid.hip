@@ -127,20 +127,18 @@ __global__ __launch_bounds__(256) void k_compose(const float *__restrict__ h, in
     const Tile t = decode_tile(gx, gy);
     const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
     if (x >= nx || y >= ny) return;
-    const int N = nx * ny * nz, i = x + nx * (y + ny * z);
+    const unsigned nbytes = 4u * (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    const __amdgpu_buffer_rsrc_t H = make_rsrc(h, 3u * nbytes);
     // p = (x, y, z) - (hx, hy, hz): the position is kept as the displacement
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-    for (int k = 0; k < K; ++k) {
-        const Cell c = make_cell_disp(x, y, z, hx, hy, hz, nx, ny, nz);
-        const float ax = sample(h, c), ay = sample(h + N, c), az = sample(h + 2 * N, c);
-        hx = ax;
-        hy = ay;
-        hz = az;
-    }
-    const Cell c = make_cell_disp(x, y, z, hx, hy, hz, nx, ny, nz);
-    out[i] = 2.0f * sample(h, c);
-    out[N + i] = 2.0f * sample(h + N, c);
-    out[2 * N + i] = 2.0f * sample(h + 2 * N, c);
+    for (int k = 0; k < K; ++k) bsample3(H, bcell_disp(x, y, z, hx, hy, hz, nx, ny, nz), nbytes, hx, hy, hz);
+    float ax, ay, az;
+    bsample3(H, bcell_disp(x, y, z, hx, hy, hz, nx, ny, nz), nbytes, ax, ay, az);
+    const __amdgpu_buffer_rsrc_t O = make_rsrc(out, 3u * nbytes);
+    const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
+    bstore(O, 2.0f * ax, o, 0u);
+    bstore(O, 2.0f * ay, o, nbytes);
+    bstore(O, 2.0f * az, o, 2u * nbytes);
 }
 
 __global__ __launch_bounds__(256) void k_zero(float *__restrict__ p, int64_t n)

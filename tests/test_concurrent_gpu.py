@@ -108,3 +108,41 @@ def test_busy_handle_refuses_work(B):
         assert torch.equal(f, f2)
     finally:
         B.dir_destroy(h)
+
+
+def test_graph_replays_equal_eager(B):
+    """Captured registrations replayed several times, with eager work and
+    synchronisations in between, give the eager result every time; changed
+    parameters or buffers are captured anew."""
+    ph = P.make_phantom((40, 36, 20), seed=21, max_u=2.5)
+    S, M = _dev(ph.static), _dev(ph.moving)
+    pa = B.make_params("inverse_consistent", [6, 4], sigma=1.0)
+    pb = B.make_params("double", [5, 5], sigma=1.0, alpha=0.4)
+    s = torch.cuda.Stream()
+    h = B.dir_create(0, stream=s)
+    try:
+        B.dir_set_graphs(h, False)
+        ref_a, st_a = B.dir_register(h, S, M, pa)
+        ref_a = ref_a.clone()
+        ref_b, _ = B.dir_register(h, S, M, pb)
+        ref_b = ref_b.clone()
+        B.dir_set_graphs(h, True)
+        out = torch.empty_like(ref_a)
+        for rep in range(4):
+            out.fill_(float("nan"))
+            torch.cuda.synchronize()
+            f, st = B.dir_register(h, S, M, pa, field_out=out)
+            assert torch.equal(f, ref_a), rep
+            np.testing.assert_array_equal(np.array(st["history"]), np.array(st_a["history"]))
+            B.dir_warp(h, S, f)                       # eager work on the same stream between replays
+            (S * 2.0).sum().item()                    # and on the default stream
+        f, _ = B.dir_register(h, S, M, pb, field_out=out)   # new parameters: captured anew
+        assert torch.equal(f, ref_b)
+        other = torch.empty_like(ref_a)
+        f, _ = B.dir_register(h, S, M, pb, field_out=other)  # new output buffer: captured anew
+        assert torch.equal(f, ref_b)
+        f = B.dir_register_async(h, S, M, pa, field_out=out)
+        f, _ = B.dir_wait(h)
+        assert torch.equal(f, ref_a)
+    finally:
+        B.dir_destroy(h)

@@ -138,7 +138,7 @@ def test_force(B, h, shape3, variant, alpha):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
 
-STEP_SHAPES = [(11, 13, 17), (9, 33, 65), (20, 40, 72), (7, 30, 129), (2, 3, 300)]
+STEP_SHAPES = [(11, 13, 17), (9, 33, 65), (20, 40, 72), (7, 30, 129), (2, 3, 300), (1, 2, 257), (3, 4, 530)]
 
 
 @pytest.mark.parametrize("shape3", STEP_SHAPES)
@@ -151,6 +151,19 @@ def test_step(B, h, shape3, variant, sigma, radius):
     out, sums_gpu = B.dir_step(h, variant, alpha, dev(S), dev(M), dev(v), sigma, radius)
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=alpha)
     ref = O.smooth(u_ref, sigma, radius)
+    assert rel(host(out) - v, ref - v) < REL_TOL
+    for k in range(3):
+        assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
+
+
+@pytest.mark.parametrize("shape3", [(3, 4, 5), (2, 3, 40), (1, 2, 257)])
+@pytest.mark.parametrize("variant", ["passive", "inverse_consistent"])
+def test_step_widest_radius(B, h, shape3, variant):
+    """R = 16 (the largest): halos wider than short rows, and a one-voxel last tile."""
+    S, M, v = _pair(shape3, 14)
+    out, sums_gpu = B.dir_step(h, variant, 1.0, dev(S), dev(M), dev(v), 4.0, 16)
+    u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=1.0)
+    ref = O.smooth(u_ref, 4.0, 16)
     assert rel(host(out) - v, ref - v) < REL_TOL
     for k in range(3):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
