@@ -142,7 +142,10 @@ __device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, i
     d2 = D64 * D64;
 }
 
-template <int V, int TX>
+// RC >= 0: the smoothing radius is RC, known at compile time (taps from the
+// kernel arguments, LDS reads issued together); RC < 0: taps.radius, taps
+// from LDS.
+template <int V, int TX, int RC>
 __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
 {
     if (a.stop_at && *a.stop_at < a.n) return;
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
     const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
     const int x0 = (lid % a.gxt) * TX;
     const int rb = lid / a.gxt;
-    const int R = taps.radius;
+    const int R = RC >= 0 ? RC : taps.radius;
     const int rows = a.ny * a.nz;
     const unsigned N = (unsigned)a.nx * (unsigned)rows;
     const unsigned nbytes = 4u * N;
@@ -221,7 +224,15 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float s = 0.0f;
-                for (int j = 0; j <= 2 * R; ++j) s = fmaf(wl[j], ul[c][wrow][lane + j], s);
+                if constexpr (RC >= 0) {
+                    float u[2 * RC + 1];
+#pragma unroll
+                    for (int j = 0; j <= 2 * RC; ++j) u[j] = ul[c][wrow][lane + j];
+#pragma unroll
+                    for (int j = 0; j <= 2 * RC; ++j) s = fmaf(taps.w[j], u[j], s);
+                } else {
+                    for (int j = 0; j <= 2 * R; ++j) s = fmaf(wl[j], ul[c][wrow][lane + j], s);
+                }
                 bstore(b.out, s, 4u * (unsigned)x, rowoff + (unsigned)c * nbytes);
             }
         }
@@ -274,13 +285,26 @@ ForceGrid force_grid(Dims d)
     return g;
 }
 
+template <int V, int RC>
+void launch_force_vr(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
+{
+    const dim3 grid((unsigned)g.blocks), block(256);
+    if (g.tx == 64) go(c, ev, (k_force_x<V, 64, RC>), grid, block, a, taps);
+    else if (g.tx == 128) go(c, ev, (k_force_x<V, 128, RC>), grid, block, a, taps);
+    else go(c, ev, (k_force_x<V, 256, RC>), grid, block, a, taps);
+}
+
+// Radii with their own kernels: 0 (the force alone), and ceil(3 sigma) for
+// sigma = 1 and 1.5 voxels; others take the runtime-radius kernel.
 template <int V>
 void launch_force_v(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
 {
-    const dim3 grid((unsigned)g.blocks), block(256);
-    if (g.tx == 64) go(c, ev, (k_force_x<V, 64>), grid, block, a, taps);
-    else if (g.tx == 128) go(c, ev, (k_force_x<V, 128>), grid, block, a, taps);
-    else go(c, ev, (k_force_x<V, 256>), grid, block, a, taps);
+    switch (taps.radius) {
+    case 0: launch_force_vr<V, 0>(c, ev, g, a, taps); break;
+    case 3: launch_force_vr<V, 3>(c, ev, g, a, taps); break;
+    case 5: launch_force_vr<V, 5>(c, ev, g, a, taps); break;
+    default: launch_force_vr<V, -1>(c, ev, g, a, taps); break;
+    }
 }
 
 }  // namespace

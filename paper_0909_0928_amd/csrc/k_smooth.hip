@@ -62,8 +62,7 @@ constexpr int max_tz()
 // With red.partials set, workgroup 0 instead adds up the FP64 sums the force
 // kernel of this iteration left per workgroup (they are complete: that kernel
 // has finished), writes the history entry and takes the stopping decision;
-// the smoothing tiles are workgroups 1 and up.  (Renumbering the tiles
-// XCD-contiguously measured slower here: 50 us against 40 us at 256x256x100.)
+// the smoothing tiles are workgroups 1 and up.
 template <int R, int TZ>
 __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in, float *__restrict__ out, int nx,
                                                    int ny, int nz, GaussTaps taps, int gx, int gy, int gz,
@@ -73,16 +72,18 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
     __shared__ float zs[TZ][ROWS][kBlockX];
     if (stop_at && *stop_at < n) return;
     const int tid = threadIdx.x + kBlockX * threadIdx.y;
-    int b = blockIdx.x;
-    if (red.partials) {
-        if (b == 0) {
-            reduce_sums(red.partials, red.nb, red.hist, n, red.st, red.eps, red.inv_n, tid);
-            return;
-        }
-        b -= 1;
+    if (red.partials && blockIdx.x == 0) {
+        reduce_sums(red.partials, red.nb, red.hist, n, red.st, red.eps, red.inv_n, tid);
+        return;
     }
-    // workgroup id -> (x tile, y tile, z chunk, component)
-    const int tx = b % gx, r1 = b / gx, ty = r1 % gy, r2 = r1 / gy, tz = r2 % gz, c = r2 / gz;
+    // workgroup id -> (z chunk, y tile, x tile, component), numbered so that
+    // each XCD runs one contiguous range with z chunks fastest, then y tiles:
+    // the tiles an XCD has in flight at once form a compact (y, z) block of
+    // one x column, whose shared 2R halo planes and rows are then served from
+    // that XCD's L2.  Workgroup 0 has logical id 0, so with a reducer the
+    // tiles are ids 1 and up.
+    const int b = xcd_logical_id(blockIdx.x, gridDim.x) - (red.partials ? 1 : 0);
+    const int tz = b % gz, r1 = b / gz, ty = r1 % gy, r2 = r1 / gy, tx = r2 % gx, c = r2 / gx;
     const int lane = threadIdx.x, wave = threadIdx.y;
     const int x = min(tx * kBlockX + lane, nx - 1);  // lanes past the edge repeat the last column
     const int y_base = ty * kTileY, z0 = tz * TZ;
