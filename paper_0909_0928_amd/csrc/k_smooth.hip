@@ -84,27 +84,53 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
     // tiles are ids 1 and up.
     const int b = xcd_logical_id(blockIdx.x, gridDim.x) - (red.partials ? 1 : 0);
     const int tz = b % gz, r1 = b / gz, ty = r1 % gy, r2 = r1 / gy, tx = r2 % gx, c = r2 / gx;
-    const int lane = threadIdx.x, wave = threadIdx.y;
+    // threadIdx.y is the wavefront index (64 x 4 workgroup): uniform, which
+    // lets the row offsets below live in scalar registers
+    const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int x = min(tx * kBlockX + lane, nx - 1);  // lanes past the edge repeat the last column
     const int y_base = ty * kTileY, z0 = tz * TZ;
-    const size_t plane = (size_t)nx * ny;
-    const float *src = in + (size_t)c * plane * nz;
+    const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    const unsigned rowb = 4u * (unsigned)nx, planeb = rowb * (unsigned)ny;
+    const __amdgpu_buffer_rsrc_t src = make_rsrc(in + (size_t)c * N, 4u * N);
+    const __amdgpu_buffer_rsrc_t dst = make_rsrc(out + (size_t)c * N, 4u * N);
+    const unsigned xb = 4u * (unsigned)x;
     float w[2 * R + 1];
 #pragma unroll
     for (int j = 0; j <= 2 * R; ++j) w[j] = taps.w[j];
-
-    // phase 1: z pass for rows y_base - R .. y_base + kTileY + R - 1
-    for (int row = wave; row < ROWS; row += kBlockY) {
-        const float *col = src + (size_t)nx * clampi(y_base - R + row, ny) + x;
-        float win[TZ + 2 * R];
+    // byte offsets of the window's planes (clamped), wave-uniform
+    unsigned zoff[TZ + 2 * R];
 #pragma unroll
-        for (int k = 0; k < TZ + 2 * R; ++k) win[k] = col[(size_t)clampi(z0 - R + k, nz) * plane];
+    for (int k = 0; k < TZ + 2 * R; ++k) zoff[k] = planeb * (unsigned)clampi(z0 - R + k, nz);
+
+    // phase 1: z pass for rows y_base - R .. y_base + kTileY + R - 1, two rows
+    // per step with the loads of both windows issued before any arithmetic
+    for (int row = wave; row < ROWS; row += 2 * kBlockY) {
+        const int row2 = row + kBlockY;
+        const bool two = row2 < ROWS;  // wave-uniform
+        const unsigned ra = rowb * (unsigned)clampi(y_base - R + row, ny);
+        const unsigned rb = rowb * (unsigned)clampi(y_base - R + (two ? row2 : row), ny);
+        float wa[TZ + 2 * R], wb[TZ + 2 * R];
+#pragma unroll
+        for (int k = 0; k < TZ + 2 * R; ++k) wa[k] = bload(src, xb, ra + zoff[k]);
+        if (two) {
+#pragma unroll
+            for (int k = 0; k < TZ + 2 * R; ++k) wb[k] = bload(src, xb, rb + zoff[k]);
+        }
 #pragma unroll
         for (int k = 0; k < TZ; ++k) {
             float s = 0.0f;
 #pragma unroll
-            for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], win[k + j], s);
+            for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], wa[k + j], s);
             zs[k][row][lane] = s;
+        }
+        if (two) {
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) {
+                float s = 0.0f;
+#pragma unroll
+                for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], wb[k + j], s);
+                zs[k][row2][lane] = s;
+            }
         }
     }
     __syncthreads();
@@ -113,18 +139,19 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
     const int xo = tx * kBlockX + lane;
     const int y0 = y_base + wave * kRowsPerThread;
     if (xo >= nx || y0 >= ny) return;
-    float *dst = out + (size_t)c * plane * nz + xo;
+    const unsigned ob = 4u * (unsigned)xo;
     for (int k = 0; k < TZ; ++k) {
         if (z0 + k >= nz) break;
         float v[kRowsPerThread + 2 * R];
 #pragma unroll
         for (int j = 0; j < kRowsPerThread + 2 * R; ++j) v[j] = zs[k][wave * kRowsPerThread + j][lane];
+        const unsigned zb = planeb * (unsigned)(z0 + k);
 #pragma unroll
         for (int q = 0; q < kRowsPerThread; ++q) {
             float s = 0.0f;
 #pragma unroll
             for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], v[q + j], s);
-            if (y0 + q < ny) dst[(size_t)(z0 + k) * plane + (size_t)(y0 + q) * nx] = s;
+            if (y0 + q < ny) bstore(dst, s, ob, zb + rowb * (unsigned)(y0 + q));
         }
     }
 }
