@@ -81,8 +81,20 @@ typedef struct {
     int32_t iters[DIR_MAX_LEVELS];   /* iterations per level, COARSEST FIRST; each >= 0 */
     double eps;                      /* 0: fixed counts; > 0: stop a level once l(n-10) - l(n) <= eps (Sec 2.4) */
     int32_t compose_iters;           /* fixed-point steps of the IC output composition; < 0 selects 10 */
-    int32_t reserved;                /* must be 0 */
+    int32_t storage;                 /* dir_storage of images and fields inside the registration */
 } dir_params;
+
+/* Storage format of the image pyramids, fields and deformed-image buffers
+ * inside a registration.  Arithmetic is FP32 and the sums, the relative norm
+ * and the intensity difference are FP64 in every format; a 16-bit format
+ * halves the bytes each iteration moves at the cost of rounding every stored
+ * value (relative 2^-11 for F16, 2^-8 for BF16).  Inputs and the output field
+ * stay FP32. */
+typedef enum {
+    DIR_STORE_F32 = 0,
+    DIR_STORE_F16 = 1,   /* IEEE binary16 (range +-65504: intensities and fields fit) */
+    DIR_STORE_BF16 = 2   /* bfloat16 (8-bit significand) */
+} dir_storage;
 
 /* Optional registration statistics.  Set struct_size = sizeof(dir_stats).
  * history, if not NULL, is a caller-owned host buffer of 4 * history_capacity
@@ -208,6 +220,15 @@ int32_t dir_force(dir_handle *h, int32_t variant, double alpha, const float *d_s
 int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
                  const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma, int32_t radius,
                  float *d_field_out, double *sums);
+
+/* dir_step with the images and field held in a 16-bit storage format, as a
+ * registration with params->storage = `storage` holds them: d_static,
+ * d_moving and d_field (FP32) are first rounded to that format, the iteration
+ * runs with its intermediates stored in it, and d_field_out receives the
+ * stored result converted back to FP32.  DIR_STORE_F32 equals dir_step. */
+int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double alpha, const float *d_static,
+                        const float *d_moving, const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma,
+                        int32_t radius, float *d_field_out, double *sums);
 
 /* Output field of the inverse-consistent variant from its half field h:
  * w(z) = 2 h(p) with p = z - h(p), p found by K fixed-point updates from

@@ -20,6 +20,8 @@ DIR_OK, DIR_EINVAL, DIR_ENOMEM, DIR_EDEVICE, DIR_ENUMERIC, DIR_EBUSY = 0, -1, -2
 DIR_PASSIVE, DIR_EVOLVED_PASSIVE, DIR_ACTIVE, DIR_DOUBLE, DIR_INVERSE_CONSISTENT = 0, 1, 2, 3, 4
 DIR_MAX_LEVELS = 8
 DIR_MAX_RADIUS = 16
+DIR_STORE_F32, DIR_STORE_F16, DIR_STORE_BF16 = 0, 1, 2
+STORAGE = {"f32": DIR_STORE_F32, "f16": DIR_STORE_F16, "bf16": DIR_STORE_BF16}
 VARIANTS = {"passive": DIR_PASSIVE, "evolved": DIR_EVOLVED_PASSIVE, "active": DIR_ACTIVE, "double": DIR_DOUBLE,
             "inverse_consistent": DIR_INVERSE_CONSISTENT}
 
@@ -38,7 +40,7 @@ class dir_params(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("variant", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("sigma", ctypes.c_double), ("radius", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("iters", ctypes.c_int32 * DIR_MAX_LEVELS), ("eps", ctypes.c_double),
-                ("compose_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("compose_iters", ctypes.c_int32), ("storage", ctypes.c_int32)]
 
 
 class dir_stats(ctypes.Structure):
@@ -76,6 +78,7 @@ def lib():
         L.dir_prolong.argtypes = [vp, vp, i32, i32, i32, vp, i32, i32, i32]
         L.dir_force.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(f64)]
         L.dir_step.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
+        L.dir_step_stored.argtypes = [vp, i32, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.dir_wait.argtypes = [vp, vp]
         L.dir_set_graphs.argtypes = [vp, i32]
@@ -88,7 +91,7 @@ def lib():
         L.dir_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
-                     "dir_register_async", "dir_wait", "dir_set_graphs",
+                     "dir_register_async", "dir_wait", "dir_set_graphs", "dir_step_stored",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
             getattr(L, name).restype = i32
         _lib = L
@@ -197,7 +200,7 @@ def dir_synchronize(h):
     _check(lib().dir_synchronize(h.ptr), "dir_synchronize")
 
 
-def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_iters=-1):
+def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_iters=-1, storage="f32"):
     """dir_params; `iters` lists the levels coarsest first."""
     if isinstance(variant, str):
         variant = VARIANTS[variant]
@@ -215,7 +218,7 @@ def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_ite
         p.iters[k] = n
     p.eps = float(eps)
     p.compose_iters = int(compose_iters)
-    p.reserved = 0
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     return p
 
 
@@ -370,6 +373,21 @@ def dir_step(h, variant, alpha, static, moving, field, sigma, radius=0, out=None
     sums = (ctypes.c_double * 3)()
     _check(lib().dir_step(h.ptr, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
                           *_dims(static), float(sigma), int(radius), _ptr(out), sums), "dir_step")
+    return out, tuple(sums)
+
+
+def dir_step_stored(h, storage, variant, alpha, static, moving, field, sigma, radius=0, out=None):
+    """dir_step with images and field held in `storage` ("f32", "f16", "bf16")."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    st = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    _dev_f32(static, "static", 3)
+    _dev_f32(moving, "moving", 3)
+    _dev_f32(field, "field", 4)
+    out = torch.empty_like(field) if out is None else _dev_f32(out, "out", 4)
+    sums = (ctypes.c_double * 3)()
+    _check(lib().dir_step_stored(h.ptr, st, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
+                                 *_dims(static), float(sigma), int(radius), _ptr(out), sums), "dir_step_stored")
     return out, tuple(sums)
 
 

@@ -19,7 +19,7 @@ thread_local std::string g_last_error;
 
 const char *const kKernelNames[K_COUNT] = {
     "force", "warp", "warp_pair", "smooth_yz", "smooth_x", "finalize", "level_reset",
-    "restrict", "prolong", "gradient", "compose", "fill",
+    "restrict", "prolong", "gradient", "compose", "fill", "convert",
 };
 
 // Device buffer that only grows.
@@ -58,11 +58,11 @@ struct DevBuf {
 // Laid out without implicit padding, so keys compare with memcmp.
 struct GraphKey {
     const void *S, *M, *out;
-    const void *ws[10];
+    const void *ws[12];
     dir_params params;
     int32_t nx, ny, nz, pad;
 };
-static_assert(sizeof(GraphKey) == 13 * sizeof(void *) + sizeof(dir_params) + 16, "GraphKey has padding");
+static_assert(sizeof(GraphKey) == 15 * sizeof(void *) + sizeof(dir_params) + 16, "GraphKey has padding");
 
 // A registration enqueued by dir_register_async (or dir_register) whose
 // statistics have not been collected yet.
@@ -80,6 +80,7 @@ struct dir_handle {
     DevBuf pyr_s, pyr_m;           // levels 1.. of the image pyramids, packed
     DevBuf field[3];               // fields, 3 planes each: v and x-smoothed u; scratch for dir_smooth
     DevBuf img_a, img_b;           // pre-warped D (active, double, IC) and P = Im + Is (IC)
+    DevBuf img0_s, img0_m;         // finest-level S and M in a 16-bit storage format
     DevBuf partials;               // 3 doubles per force workgroup
     DevBuf history;                // 4 doubles per iteration, per-level fixed offsets
     DevBuf state;                  // one LevelState per level
@@ -307,6 +308,8 @@ int32_t dir_destroy(dir_handle *h)
     for (auto &f : h->field) f.release();
     h->img_a.release();
     h->img_b.release();
+    h->img0_s.release();
+    h->img0_m.release();
     h->partials.release();
     h->history.release();
     h->state.release();
@@ -413,7 +416,7 @@ int32_t dir_smooth(dir_handle *h, const float *d_in, int32_t ncomp, int32_t nx, 
     Ctx c{h->stream, &h->timer};
     const GaussTaps taps = make_taps(sigma, R);
     DIR_TRY(launch_smooth_x(c, d_in, ncomp, d, taps, h->field[2].as<float>()));
-    DIR_TRY(launch_smooth_yz(c, h->field[2].as<float>(), ncomp, d, taps, d_out, nullptr, 0, SumsReduce{}));
+    DIR_TRY(launch_smooth_yz(c, h->field[2].as<float>(), ncomp, d, taps, d_out, kStoreF32, nullptr, 0, SumsReduce{}));
     return DIR_OK;
 }
 
@@ -424,7 +427,7 @@ int32_t dir_restrict(dir_handle *h, const float *d_in, int32_t nx, int32_t ny, i
     if (!d_in || !d_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     const Dims f{nx, ny, nz};
     Ctx c{h->stream, &h->timer};
-    DIR_TRY(launch_restrict(c, d_in, f, d_out, coarser(f)));
+    DIR_TRY(launch_restrict(c, d_in, kStoreF32, f, d_out, kStoreF32, coarser(f)));
     return DIR_OK;
 }
 
@@ -435,7 +438,7 @@ int32_t dir_prolong(dir_handle *h, const float *d_coarse, int32_t cnx, int32_t c
     if (rc != DIR_OK) return rc;
     if (!d_coarse || !d_fine || !dims_ok(cnx, cny, cnz) || !dims_ok(fnx, fny, fnz)) return DIR_EINVAL;
     Ctx c{h->stream, &h->timer};
-    DIR_TRY(launch_prolong(c, d_coarse, Dims{cnx, cny, cnz}, d_fine, Dims{fnx, fny, fnz}));
+    DIR_TRY(launch_prolong(c, d_coarse, Dims{cnx, cny, cnz}, d_fine, Dims{fnx, fny, fnz}, kStoreF32));
     return DIR_OK;
 }
 
@@ -447,7 +450,7 @@ int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, 
     if (!d_half || !d_out || !dims_ok(nx, ny, nz) || d_half == d_out) return DIR_EINVAL;
     if (K < 0) K = DIR_DEFAULT_COMPOSE_ITERS;
     Ctx c{h->stream, &h->timer};
-    DIR_TRY(launch_compose(c, d_half, Dims{nx, ny, nz}, K, d_out));
+    DIR_TRY(launch_compose(c, d_half, kStoreF32, Dims{nx, ny, nz}, K, d_out));
     return DIR_OK;
 }
 
@@ -456,12 +459,11 @@ int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, 
 namespace {
 
 // Device buffers one force evaluation needs at level size d.
-int ensure_force_workspace(dir_handle *h, Dims d, int variant)
+int ensure_force_workspace(dir_handle *h, Dims d, int variant, int storage)
 {
-    const size_t n = (size_t)d.n();
-    if (variant == kActive || variant == kDouble || variant == kInverseConsistent)
-        DIR_TRY(h->img_a.ensure(sizeof(float) * n));
-    if (variant == kInverseConsistent) DIR_TRY(h->img_b.ensure(sizeof(float) * n));
+    const size_t n = (size_t)d.n() * storage_bytes(storage);
+    if (variant == kActive || variant == kDouble || variant == kInverseConsistent) DIR_TRY(h->img_a.ensure(n));
+    if (variant == kInverseConsistent) DIR_TRY(h->img_b.ensure(sizeof(float) * (size_t)d.n()));  // P: FP32
     DIR_TRY(h->partials.ensure(sizeof(double) * 3 * (size_t)force_blocks(d)));
     return DIR_OK;
 }
@@ -479,16 +481,17 @@ GaussTaps identity_taps()
 // The force half of one iteration: pre-warp where the variant needs
 // deformed-image gradients, then the force kernel (u = v + dr, x pass of the
 // smoothing with `taps`, per-workgroup sums).
-hipError_t force_half(dir_handle *h, Ctx &c, int variant, float alpha2, const float *S, const float *M,
-                      const float *v, Dims d, const GaussTaps &taps, float *out, const int *stop_at, int n)
+hipError_t force_half(dir_handle *h, Ctx &c, int variant, int storage, float alpha2, const void *S, const void *M,
+                      const void *v, Dims d, const GaussTaps &taps, void *out, const int *stop_at, int n)
 {
-    float *D = h->img_a.as<float>(), *P = h->img_b.as<float>();
+    void *D = h->img_a.p, *P = h->img_b.p;
     hipError_t e = hipSuccess;
-    if (variant == kActive || variant == kDouble) e = launch_warp_diff(c, M, S, v, d, D, stop_at, n);
-    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, D, P, stop_at, n);
+    if (variant == kActive || variant == kDouble) e = launch_warp_diff(c, M, S, v, d, D, storage, stop_at, n);
+    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, D, P, storage, stop_at, n);
     if (e != hipSuccess) return e;
     ForceLaunch f;
     f.variant = variant;
+    f.storage = storage;
     f.alpha2 = alpha2;
     f.S = S;
     f.M = M;
@@ -517,35 +520,60 @@ SumsReduce sums_reduce(dir_handle *h, Dims d, double *hist, LevelState *st, doub
     return r;
 }
 
-// dir_force and dir_step: one iteration outside a registration, sums out.
+// dir_force, dir_step and dir_step_stored: one iteration outside a
+// registration, sums out.  With a 16-bit storage format the FP32 inputs are
+// converted first (S, M, v into the workspace) and the result converted back.
 int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, const float *M, const float *v,
-                int32_t nx, int32_t ny, int32_t nz, const GaussTaps *taps, float *out, double *sums)
+                int32_t nx, int32_t ny, int32_t nz, const GaussTaps *taps, float *out, double *sums,
+                int storage = kStoreF32)
 {
     if (!S || !M || !v || !out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     if (variant < kPassive || variant > kInverseConsistent || !(alpha > 0.0) || !isfinite(alpha)) return DIR_EINVAL;
+    if (storage < kStoreF32 || storage > kStoreBF16) return DIR_EINVAL;
     const Dims d{nx, ny, nz};
-    const size_t bytes = sizeof(float) * 3 * (size_t)d.n();
+    const size_t n = (size_t)d.n();
+    const size_t bytes = sizeof(float) * 3 * n;
     const char *vb = reinterpret_cast<const char *>(v), *ob = reinterpret_cast<const char *>(out);
     if (vb < ob + bytes && ob < vb + bytes) return DIR_EINVAL;  // out must not overlap the field
-    int rc = ensure_force_workspace(h, d, variant);
+    const bool conv = storage != kStoreF32;
+    const size_t es = storage_bytes(storage);
+    int rc = ensure_force_workspace(h, d, variant, storage);
     if (rc != DIR_OK) return rc;
     DIR_TRY(h->history.ensure(sizeof(double) * 4));
     DIR_TRY(h->state.ensure(sizeof(LevelState)));
-    if (taps) DIR_TRY(h->field[2].ensure(bytes));
+    if (taps || conv) DIR_TRY(h->field[2].ensure(bytes));
+    if (conv) {
+        DIR_TRY(h->img0_s.ensure(es * n));
+        DIR_TRY(h->img0_m.ensure(es * n));
+        DIR_TRY(h->field[0].ensure(es * 3 * n));
+        DIR_TRY(h->field[1].ensure(es * 3 * n));
+    }
     Ctx c{h->stream, &h->timer};
+    const void *Sx = S, *Mx = M, *vx = v;
+    void *fout = out;  // where the step leaves its result, in the storage format
+    if (conv) {
+        DIR_TRY(launch_convert(c, S, kStoreF32, h->img0_s.p, storage, (int64_t)n));
+        DIR_TRY(launch_convert(c, M, kStoreF32, h->img0_m.p, storage, (int64_t)n));
+        DIR_TRY(launch_convert(c, v, kStoreF32, h->field[0].p, storage, 3 * (int64_t)n));
+        Sx = h->img0_s.p;
+        Mx = h->img0_m.p;
+        vx = h->field[0].p;
+        fout = h->field[1].p;
+    }
     LevelState *st = h->state.as<LevelState>();
     DIR_TRY(launch_level_reset(c, st));
     SumsReduce red = sums_reduce(h, d, h->history.as<double>(), st, 0.0);
     red.inv_n = 1.0;  // report the plain sum of D^2
     if (taps) {
-        DIR_TRY(force_half(h, c, variant, (float)(alpha * alpha), S, M, v, d, *taps, h->field[2].as<float>(),
+        DIR_TRY(force_half(h, c, variant, storage, (float)(alpha * alpha), Sx, Mx, vx, d, *taps, h->field[2].p,
                            nullptr, 0));
-        DIR_TRY(launch_smooth_yz(c, h->field[2].as<float>(), 3, d, *taps, out, nullptr, 0, red));
+        DIR_TRY(launch_smooth_yz(c, h->field[2].p, 3, d, *taps, fout, storage, nullptr, 0, red));
     } else {
         const GaussTaps id = identity_taps();
-        DIR_TRY(force_half(h, c, variant, (float)(alpha * alpha), S, M, v, d, id, out, nullptr, 0));
+        DIR_TRY(force_half(h, c, variant, storage, (float)(alpha * alpha), Sx, Mx, vx, d, id, fout, nullptr, 0));
         DIR_TRY(launch_finalize(c, red, 0));
     }
+    if (conv) DIR_TRY(launch_convert(c, fout, storage, out, kStoreF32, 3 * (int64_t)n));
     rc = finish(h);
     if (rc != DIR_OK) return rc;
     if (sums) {
@@ -584,6 +612,20 @@ int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_st
     return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, &taps, d_field_out, sums);
 }
 
+int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double alpha, const float *d_static,
+                        const float *d_moving, const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma,
+                        int32_t radius, float *d_field_out, double *sums)
+{
+    int rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    if (!(sigma > 0.0) || !isfinite(sigma)) return DIR_EINVAL;
+    const int R = resolve_radius(sigma, radius);
+    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+    const GaussTaps taps = make_taps(sigma, R);
+    return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, &taps, d_field_out, sums,
+                       storage);
+}
+
 }  // extern "C"
 
 namespace {
@@ -593,7 +635,7 @@ namespace {
 struct RegPlan {
     const float *S, *M;
     float *out;
-    int variant, L, K;
+    int variant, storage, L, K;
     float alpha2;
     double eps;
     GaussTaps taps;
@@ -610,7 +652,8 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     int rc = DIR_OK;
     // ---- validation ----
     if (!d_static || !d_moving || !p || !d_field_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
-    if (p->struct_size != (int32_t)sizeof(dir_params) || p->reserved != 0) return DIR_EINVAL;
+    if (p->struct_size != (int32_t)sizeof(dir_params)) return DIR_EINVAL;
+    if (p->storage < kStoreF32 || p->storage > kStoreBF16) return DIR_EINVAL;
     if (spacing_mm)
         for (int k = 0; k < 3; ++k)
             if (!(spacing_mm[k] > 0.0) || !isfinite(spacing_mm[k])) return DIR_EINVAL;
@@ -646,13 +689,18 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
         pyr += (size_t)dims[k].n();
     }
     const size_t n0 = (size_t)dims[0].n();
+    const size_t es = storage_bytes(p->storage);  // bytes per stored value
     if (L > 1) {
-        DIR_TRY(h->pyr_s.ensure(sizeof(float) * pyr));
-        DIR_TRY(h->pyr_m.ensure(sizeof(float) * pyr));
+        DIR_TRY(h->pyr_s.ensure(es * pyr));
+        DIR_TRY(h->pyr_m.ensure(es * pyr));
     }
-    for (auto &f : h->field) DIR_TRY(f.ensure(sizeof(float) * 3 * n0));
+    if (p->storage != kStoreF32) {
+        DIR_TRY(h->img0_s.ensure(es * n0));
+        DIR_TRY(h->img0_m.ensure(es * n0));
+    }
+    for (auto &f : h->field) DIR_TRY(f.ensure(es * 3 * n0));
     for (int k = 0; k < L; ++k) {  // sum slots: the largest level count
-        rc = ensure_force_workspace(h, dims[k], variant);
+        rc = ensure_force_workspace(h, dims[k], variant, p->storage);
         if (rc != DIR_OK) return rc;
     }
     DIR_TRY(h->history.ensure(sizeof(double) * 4 * (size_t)(total_iters > 0 ? total_iters : 1)));
@@ -662,6 +710,7 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     pl.M = d_moving;
     pl.out = d_field_out;
     pl.variant = variant;
+    pl.storage = p->storage;
     pl.L = L;
     pl.K = K;
     pl.alpha2 = alpha2;
@@ -685,50 +734,62 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
 // iterations after the stop return at once.
 int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
 {
-    const int L = pl.L, variant = pl.variant, K = pl.K;
+    const int L = pl.L, variant = pl.variant, K = pl.K, st_fmt = pl.storage;
     const Dims *dims = pl.dims;
     const GaussTaps &taps = pl.taps;
     const float alpha2 = pl.alpha2;
-    const float *d_static = pl.S, *d_moving = pl.M;
-    float *d_field_out = pl.out;
-
+    const size_t es = storage_bytes(st_fmt);
+    const bool f32 = st_fmt == kStoreF32;
     Ctx c{h->stream, &h->timer};
-    const float *Sk[DIR_MAX_LEVELS], *Mk[DIR_MAX_LEVELS];
-    Sk[0] = d_static;
-    Mk[0] = d_moving;
+
+    // ---- image pyramids in the storage format (Sec 2.3) ----
+    // Level 1 is restricted from the caller's FP32 images; with 16-bit
+    // storage the finest level itself is a converted copy.
+    const void *Sk[DIR_MAX_LEVELS], *Mk[DIR_MAX_LEVELS];
+    Sk[0] = pl.S;
+    Mk[0] = pl.M;
     {
         size_t off = 0;
         for (int k = 1; k < L; ++k) {
-            float *s = h->pyr_s.as<float>() + off, *m = h->pyr_m.as<float>() + off;
+            char *s = static_cast<char *>(h->pyr_s.p) + es * off, *m = static_cast<char *>(h->pyr_m.p) + es * off;
+            const int in_fmt = k == 1 ? kStoreF32 : st_fmt;
             h->timer.level = k;
-            DIR_TRY(launch_restrict(c, Sk[k - 1], dims[k - 1], s, dims[k]));
-            DIR_TRY(launch_restrict(c, Mk[k - 1], dims[k - 1], m, dims[k]));
+            DIR_TRY(launch_restrict(c, Sk[k - 1], in_fmt, dims[k - 1], s, st_fmt, dims[k]));
+            DIR_TRY(launch_restrict(c, Mk[k - 1], in_fmt, dims[k - 1], m, st_fmt, dims[k]));
             Sk[k] = s;
             Mk[k] = m;
             off += (size_t)dims[k].n();
         }
     }
+    if (!f32) {
+        h->timer.level = 0;
+        DIR_TRY(launch_convert(c, pl.S, kStoreF32, h->img0_s.p, st_fmt, dims[0].n()));
+        DIR_TRY(launch_convert(c, pl.M, kStoreF32, h->img0_m.p, st_fmt, dims[0].n()));
+        Sk[0] = h->img0_s.p;
+        Mk[0] = h->img0_m.p;
+    }
 
     // ---- levels, coarse to fine (Sec 2.3) ----
-    // The finest level's field lives in d_field_out itself, except for the
-    // inverse-consistent variant, whose half field is composed into it.
-    float *const fa = h->field[0].as<float>(), *const fb = h->field[1].as<float>();
-    float *const final_v = variant == kInverseConsistent ? nullptr : d_field_out;
-    float *v = (L == 1 && final_v) ? final_v : fa;
+    // With FP32 storage the finest level's field lives in d_field_out itself,
+    // except for the inverse-consistent variant, whose half field is composed
+    // into it; 16-bit fields are converted into it at the end.
+    void *const fa = h->field[0].p, *const fb = h->field[1].p;
+    void *const final_v = (variant == kInverseConsistent || !f32) ? nullptr : static_cast<void *>(pl.out);
+    void *v = (L == 1 && final_v) ? final_v : fa;
     LevelState *states = h->state.as<LevelState>();
     double *hist = h->history.as<double>();
     h->timer.level = L - 1;
-    DIR_TRY(launch_zero(c, v, 3 * dims[L - 1].n()));
+    DIR_TRY(launch_zero(c, v, 3 * dims[L - 1].n(), st_fmt));
     for (int k = L - 1; k >= 0; --k) {
         const int li = L - 1 - k;
         const Dims d = dims[k];
         h->timer.level = k;
         if (k < L - 1) {
-            float *dst = (k == 0 && final_v) ? final_v : (v == fa ? fb : fa);
-            DIR_TRY(launch_prolong(c, v, dims[k + 1], dst, d));
+            void *dst = (k == 0 && final_v) ? final_v : (v == fa ? fb : fa);
+            DIR_TRY(launch_prolong(c, v, dims[k + 1], dst, d, st_fmt));
             v = dst;
         }
-        float *const xs = v == fa ? fb : fa;  // x-smoothed u of this level
+        void *const xs = v == fa ? fb : fa;  // x-smoothed u of this level
         LevelState *st = states + li;
         DIR_TRY(launch_level_reset(c, st));
         const int iters = pl.iters[li];
@@ -736,8 +797,8 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
         for (int n = 0; n < iters; ++n) {
             // v -> xs = x-smoothed (v + dr) -> v = y,z-smoothed xs; the
             // smoothing kernel also reduces the sums of this iteration
-            DIR_TRY(force_half(h, c, variant, alpha2, Sk[k], Mk[k], v, d, taps, xs, &st->stop_at, n));
-            DIR_TRY(launch_smooth_yz(c, xs, 3, d, taps, v, &st->stop_at, n, red));
+            DIR_TRY(force_half(h, c, variant, st_fmt, alpha2, Sk[k], Mk[k], v, d, taps, xs, &st->stop_at, n));
+            DIR_TRY(launch_smooth_yz(c, xs, 3, d, taps, v, st_fmt, &st->stop_at, n, red));
             if (poll && pl.eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
                 int stop_at = kNeverStopped;
                 DIR_TRY(hipMemcpyAsync(&stop_at, &st->stop_at, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -747,9 +808,10 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
         }
     }
 
-    // ---- output ----
+    // ---- output (FP32) ----
     h->timer.level = 0;
-    if (variant == kInverseConsistent) DIR_TRY(launch_compose(c, v, dims[0], K, d_field_out));
+    if (variant == kInverseConsistent) DIR_TRY(launch_compose(c, v, st_fmt, dims[0], K, pl.out));
+    else if (!f32) DIR_TRY(launch_convert(c, v, st_fmt, pl.out, kStoreF32, 3 * dims[0].n()));
     return DIR_OK;
 }
 
@@ -764,9 +826,9 @@ GraphKey graph_key(dir_handle *h, const RegPlan &pl, const dir_params *p)
     k.ny = pl.dims[0].ny;
     k.nz = pl.dims[0].nz;
     memcpy(&k.params, p, sizeof k.params);
-    const DevBuf *bufs[10] = {&h->pyr_s, &h->pyr_m, &h->field[0], &h->field[1], &h->field[2],
-                              &h->img_a, &h->img_b, &h->partials, &h->history, &h->state};
-    for (int i = 0; i < 10; ++i) k.ws[i] = bufs[i]->p;
+    const DevBuf *bufs[12] = {&h->pyr_s, &h->pyr_m,  &h->field[0], &h->field[1], &h->field[2],  &h->img_a,
+                              &h->img_b, &h->img0_s, &h->img0_m,   &h->partials, &h->history, &h->state};
+    for (int i = 0; i < 12; ++i) k.ws[i] = bufs[i]->p;
     return k;
 }
 

@@ -9,6 +9,7 @@
 #include <math.h>
 
 #include <hip/hip_ext.h>
+#include <hip/hip_fp16.h>
 
 #include "dir_internal.h"
 
@@ -176,6 +177,49 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, float v, unsign
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
 }
 
+// Storage formats of images and fields.  Arithmetic is FP32 throughout: a
+// 16-bit value converts to float exactly on load and a float is rounded to
+// nearest-even on store.  kBytes is the element size that every byte offset
+// of a volume of that format is scaled by.
+struct StF32 {
+    static constexpr unsigned kBytes = 4;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+    {
+        return bload(r, voff, soff);
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+    {
+        bstore(r, v, voff, soff);
+    }
+};
+
+struct StF16 {  // IEEE binary16
+    static constexpr unsigned kBytes = 2;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+    {
+        return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, 0);
+    }
+};
+
+struct StBF16 {  // bfloat16: the upper half of a binary32
+    static constexpr unsigned kBytes = 2;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+    {
+        return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0) << 16);
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+    {
+        // round to nearest, ties to even, on the 16 bits dropped (finite v)
+        unsigned u = __float_as_uint(v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(u >> 16), r, voff, soff, 0);
+    }
+};
+
 // Trilinear cell in byte offsets for buffer access: the lower corner, the
 // byte step to the upper neighbour along each axis (0 where the sample was
 // clamped onto a single grid point) and the exact weights of the lower
@@ -213,13 +257,15 @@ __device__ __forceinline__ AxisB axis_b(int x, float v, int n)
     return a;
 }
 
+// ES: element size in bytes of the volume the cell addresses.
+template <unsigned ES = 4>
 __device__ __forceinline__ BCell bcell_disp(int x, int y, int z, float vx, float vy, float vz, int nx, int ny, int nz)
 {
     const AxisB ax = axis_b(x, vx, nx), ay = axis_b(y, vy, ny), az = axis_b(z, vz, nz);
     BCell c;
-    const unsigned row = 4u * (unsigned)nx, plane = row * (unsigned)ny;
-    c.o = 4u * (unsigned)ax.i + row * (unsigned)ay.i + plane * (unsigned)az.i;
-    c.dx = ax.step ? 4u : 0u;
+    const unsigned row = ES * (unsigned)nx, plane = row * (unsigned)ny;
+    c.o = ES * (unsigned)ax.i + row * (unsigned)ay.i + plane * (unsigned)az.i;
+    c.dx = ax.step ? ES : 0u;
     c.dy = ay.step ? row : 0u;
     c.dz = az.step ? plane : 0u;
     c.wx = ax.w0;
@@ -228,21 +274,24 @@ __device__ __forceinline__ BCell bcell_disp(int x, int y, int z, float vx, float
     return c;
 }
 
-// Trilinear FP64 sample through a buffer resource (see sample64).
+// Trilinear FP64 sample through a buffer resource (see sample64) of a volume
+// stored in format St.
+template <class St = StF32>
 __device__ __forceinline__ double bsample64(__amdgpu_buffer_rsrc_t I, const BCell &c)
 {
     const double ax = c.wx, bx = 1.0 - ax, ay = c.wy, by = 1.0 - ay, az = c.wz, bz = 1.0 - az;
     const unsigned o = c.o, oy = o + c.dy, oz = o + c.dz, oyz = oz + c.dy;
-    const double c00 = ax * (double)bload(I, o, 0) + bx * (double)bload(I, o + c.dx, 0);
-    const double c10 = ax * (double)bload(I, oy, 0) + bx * (double)bload(I, oy + c.dx, 0);
-    const double c01 = ax * (double)bload(I, oz, 0) + bx * (double)bload(I, oz + c.dx, 0);
-    const double c11 = ax * (double)bload(I, oyz, 0) + bx * (double)bload(I, oyz + c.dx, 0);
+    const double c00 = ax * (double)St::load(I, o, 0) + bx * (double)St::load(I, o + c.dx, 0);
+    const double c10 = ax * (double)St::load(I, oy, 0) + bx * (double)St::load(I, oy + c.dx, 0);
+    const double c01 = ax * (double)St::load(I, oz, 0) + bx * (double)St::load(I, oz + c.dx, 0);
+    const double c11 = ax * (double)St::load(I, oyz, 0) + bx * (double)St::load(I, oyz + c.dx, 0);
     return az * (ay * c00 + by * c10) + bz * (ay * c01 + by * c11);
 }
 
 // FP32 trilinear samples of three planes `plane` bytes apart (a field's
 // components) at one cell: the corner offsets are formed once and the plane
 // goes to the scalar offset.  Lower-corner weight w0: w0 * a + (1 - w0) * b.
+template <class St = StF32>
 __device__ __forceinline__ void bsample3(__amdgpu_buffer_rsrc_t I, const BCell &c, unsigned plane, float &s0,
                                          float &s1, float &s2)
 {
@@ -251,12 +300,12 @@ __device__ __forceinline__ void bsample3(__amdgpu_buffer_rsrc_t I, const BCell &
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const unsigned so = (unsigned)k * plane;
-        const float b00 = bload(I, o + c.dx, so), b10 = bload(I, oy + c.dx, so);
-        const float b01 = bload(I, oz + c.dx, so), b11 = bload(I, oyz + c.dx, so);
-        const float c00 = fmaf(c.wx, bload(I, o, so) - b00, b00);
-        const float c10 = fmaf(c.wx, bload(I, oy, so) - b10, b10);
-        const float c01 = fmaf(c.wx, bload(I, oz, so) - b01, b01);
-        const float c11 = fmaf(c.wx, bload(I, oyz, so) - b11, b11);
+        const float b00 = St::load(I, o + c.dx, so), b10 = St::load(I, oy + c.dx, so);
+        const float b01 = St::load(I, oz + c.dx, so), b11 = St::load(I, oyz + c.dx, so);
+        const float c00 = fmaf(c.wx, St::load(I, o, so) - b00, b00);
+        const float c10 = fmaf(c.wx, St::load(I, oy, so) - b10, b10);
+        const float c01 = fmaf(c.wx, St::load(I, oz, so) - b01, b01);
+        const float c11 = fmaf(c.wx, St::load(I, oyz, so) - b11, b11);
         const float d0 = fmaf(c.wy, c00 - c10, c10), d1 = fmaf(c.wy, c01 - c11, c11);
         r[k] = fmaf(c.wz, d0 - d1, d1);
     }
@@ -406,6 +455,19 @@ inline Grid2 plane_grid(Dims d)
     g.gy = ceil_div(d.ny, kBlockY);
     g.blocks = (int64_t)g.gx * g.gy * d.nz;
     return g;
+}
+
+// Call f(Tag<St>{}) with the storage trait of format code `st` (host side).
+template <class T>
+struct Tag {
+    using type = T;
+};
+template <class F>
+void with_storage(int st, F &&f)
+{
+    if (st == kStoreF16) f(Tag<dev::StF16>{});
+    else if (st == kStoreBF16) f(Tag<dev::StBF16>{});
+    else f(Tag<dev::StF32>{});
 }
 
 // Start and stop events of one launch; both null when it is not timed.

@@ -16,6 +16,11 @@ constexpr int kBlockY = 4;    // four wavefronts per workgroup
 // Variant codes, numerically equal to dir_variant.
 enum Variant { kPassive = 0, kEvolved = 1, kActive = 2, kDouble = 3, kInverseConsistent = 4 };
 
+// Storage formats of images and fields inside a registration, numerically
+// equal to dir_storage: FP32, IEEE half, bfloat16.
+enum Storage { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2 };
+inline unsigned storage_bytes(int st) { return st == kStoreF32 ? 4u : 2u; }
+
 // Kernel ids for event timing; names in kKernelNames (abi.hip).
 enum KernelId {
     K_FORCE = 0,     // force + x pass of the smoothing + sums (+ last-workgroup reduction)
@@ -30,6 +35,7 @@ enum KernelId {
     K_GRADIENT,
     K_COMPOSE,
     K_FILL,
+    K_CONVERT,       // storage-format conversion (reduced-precision registrations)
     K_COUNT
 };
 
@@ -106,36 +112,41 @@ struct Ctx {
 int64_t force_blocks(Dims d);
 
 // One force-kernel launch: u = v + dr (Eqs 1-6), its x-smoothing with `taps`
-// (identity taps give u), and the per-workgroup FP64 sums.
+// (identity taps give u), and the per-workgroup FP64 sums.  Every volume is
+// in format `storage`.
 struct ForceLaunch {
     int variant;
+    int storage;
     float alpha2;
-    const float *S, *M, *v;
-    const float *D, *P;   // from the pre-warp: D (active, double, IC), P = Im + Is (IC)
+    const void *S, *M, *v;
+    const void *D, *P;    // from the pre-warp: D (active, double, IC), P = Im + Is (IC)
     Dims d;
     const GaussTaps *taps;
-    float *out;
+    void *out;
     double *partials;     // 3 * force_blocks(d) doubles
     const int *stop_at;   // skip when *stop_at < n (NULL: never)
     int n;
 };
 
 // ---- launchers; each returns the launch status ----------------------------
-hipError_t launch_restrict(Ctx &c, const float *in, Dims fine, float *out, Dims coarse);
-hipError_t launch_prolong(Ctx &c, const float *vc, Dims coarse, float *vf, Dims fine);
+// `st`, `in_st`, `out_st`: storage format (Storage) of the volume next to it;
+// volumes without one are FP32.
+hipError_t launch_restrict(Ctx &c, const void *in, int in_st, Dims fine, void *out, int out_st, Dims coarse);
+hipError_t launch_prolong(Ctx &c, const void *vc, Dims coarse, void *vf, Dims fine, int st);
 hipError_t launch_gradient(Ctx &c, const float *img, Dims d, float *grad);
 hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, float *out, const int *stop_at, int n);
-hipError_t launch_warp_diff(Ctx &c, const float *M, const float *S, const float *v, Dims d, float *D,
+hipError_t launch_warp_diff(Ctx &c, const void *M, const void *S, const void *v, Dims d, void *D, int st,
                             const int *stop_at, int n);
-hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *D, float *P,
+hipError_t launch_warp_pair(Ctx &c, const void *M, const void *S, const void *h, Dims d, void *D, void *P, int st,
                             const int *stop_at, int n);
 hipError_t launch_force(Ctx &c, const ForceLaunch &f);
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out);
-hipError_t launch_smooth_yz(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out,
+hipError_t launch_smooth_yz(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out, int st,
                             const int *stop_at, int n, const SumsReduce &red);
 hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n);
 hipError_t launch_level_reset(Ctx &c, LevelState *st);
-hipError_t launch_compose(Ctx &c, const float *h, Dims d, int K, float *out);
-hipError_t launch_zero(Ctx &c, float *p, int64_t n);
+hipError_t launch_compose(Ctx &c, const void *h, int h_st, Dims d, int K, float *out);
+hipError_t launch_zero(Ctx &c, void *p, int64_t n, int st);
+hipError_t launch_convert(Ctx &c, const void *in, int in_st, void *out, int out_st, int64_t n);
 
 }  // namespace dir

@@ -22,12 +22,14 @@ namespace {
 
 using namespace dev;
 
+// Volumes are in the storage format of the kernel instance (StF32, StF16 or
+// StBF16); the pointers are untyped.
 struct ForceArgs {
-    const float *S, *M, *v;
-    const float *Dd, *P;  // pre-warped D (active, double, IC) and P = Im + Is (IC)
+    const void *S, *M, *v;
+    const void *Dd, *P;   // pre-warped D (active, double, IC) and P = Im + Is (IC, always FP32)
     int nx, ny, nz;
     float alpha2;
-    float *out;           // x-smoothed u (u itself with identity taps)
+    void *out;            // x-smoothed u (u itself with identity taps)
     double *partials;     // 3 * gridDim.x doubles: s1[], s2[], sse[]
     const int *stop_at;   // skip when *stop_at < n (NULL: never)
     int n;                // iteration index within the level
@@ -47,12 +49,13 @@ struct LaneOffsets {
 };
 
 // Central difference (Sec 2.5 gradient kernel) from a buffer.
+template <class St>
 __device__ __forceinline__ void cdiff(__amdgpu_buffer_rsrc_t I, const LaneOffsets &lo, const RowOffsets &ro, float &gx,
                                       float &gy, float &gz)
 {
-    gx = 0.5f * (bload(I, lo.xp, ro.c) - bload(I, lo.xm, ro.c));
-    gy = 0.5f * (bload(I, lo.c, ro.yp) - bload(I, lo.c, ro.ym));
-    gz = 0.5f * (bload(I, lo.c, ro.zp) - bload(I, lo.c, ro.zm));
+    gx = 0.5f * (St::load(I, lo.xp, ro.c) - St::load(I, lo.xm, ro.c));
+    gy = 0.5f * (St::load(I, lo.c, ro.yp) - St::load(I, lo.c, ro.ym));
+    gz = 0.5f * (St::load(I, lo.c, ro.zp) - St::load(I, lo.c, ro.zm));
 }
 
 // Hardware square root and reciprocal (about 1 ulp): the force's parity
@@ -89,40 +92,46 @@ struct Bufs {
 };
 
 // u = v + dr at voxel (x, y, z) and its contributions |dr|, |v|, D^2.
-template <int V>
+template <int V, class St>
 __device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, int x, int y, int z,
                                             const RowOffsets &ro, unsigned nbytes, float &u0, float &u1, float &u2,
                                             double &adr, double &av, double &d2)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    constexpr unsigned ES = St::kBytes;
     LaneOffsets lo;
-    lo.c = 4u * (unsigned)x;
-    lo.xm = 4u * (unsigned)max(x - 1, 0);
-    lo.xp = 4u * (unsigned)min(x + 1, nx - 1);
-    const float vx = bload(b.v, lo.c, ro.c), vy = bload(b.v, lo.c, ro.c + nbytes),
-                vz = bload(b.v, lo.c, ro.c + 2u * nbytes);
+    lo.c = ES * (unsigned)x;
+    lo.xm = ES * (unsigned)max(x - 1, 0);
+    lo.xp = ES * (unsigned)min(x + 1, nx - 1);
+    const float vx = St::load(b.v, lo.c, ro.c), vy = St::load(b.v, lo.c, ro.c + nbytes),
+                vz = St::load(b.v, lo.c, ro.c + 2u * nbytes);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
     // intensity difference: sampled in FP64 here (passive, evolved) or taken
     // from the pre-warp kernel, which forms it the same way; rounded once
     double D64;
     if (V == kPassive || V == kEvolved)
-        D64 = bsample64(b.M, bcell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)bload(b.S, lo.c, ro.c);
+        D64 = bsample64<St>(b.M, bcell_disp<ES>(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)St::load(b.S, lo.c, ro.c);
     else
-        D64 = (double)bload(b.Dd, lo.c, ro.c);
+        D64 = (double)St::load(b.Dd, lo.c, ro.c);
     const float D = (float)D64;
     if (V == kInverseConsistent) {
-        // Eq 6: g = grad Im + grad Is = grad P of the two deformed images
+        // Eq 6: g = grad Im + grad Is = grad P of the two deformed images.
+        // P is FP32 in every storage format (it sits near twice the
+        // background intensity, where 16-bit spacing would quantise grad P).
+        constexpr unsigned K4 = 4u / ES;
+        const LaneOffsets l4{K4 * lo.c, K4 * lo.xm, K4 * lo.xp};
+        const RowOffsets r4{K4 * ro.c, K4 * ro.ym, K4 * ro.yp, K4 * ro.zm, K4 * ro.zp};
         float gx, gy, gz;
-        cdiff(b.P, lo, ro, gx, gy, gz);
+        cdiff<StF32>(b.P, l4, r4, gx, gy, gz);
         dterm(D, gx, gy, gz, a.alpha2, fx, fy, fz);
     } else {
         float sx, sy, sz;
-        cdiff(b.S, lo, ro, sx, sy, sz);
+        cdiff<St>(b.S, lo, ro, sx, sy, sz);
         if (V == kPassive || V == kDouble) dterm(D, sx, sy, sz, a.alpha2, fx, fy, fz);  // Eq 1
         if (V == kActive || V == kDouble) {                                             // Eq 3
             // grad Im = grad (Im - S) + grad S
             float dx, dy, dz, bx, by, bz;
-            cdiff(b.Dd, lo, ro, dx, dy, dz);
+            cdiff<St>(b.Dd, lo, ro, dx, dy, dz);
             dterm(D, dx + sx, dy + sy, dz + sz, a.alpha2, bx, by, bz);
             fx += bx;
             fy += by;
@@ -130,7 +139,7 @@ __device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, i
         }
         if (V == kEvolved) {                                                            // Eq 2
             float mx, my, mz;
-            cdiff(b.M, lo, ro, mx, my, mz);
+            cdiff<St>(b.M, lo, ro, mx, my, mz);
             eterm(D, sx, sy, sz, fast_sqrt(fmaf(mx, mx, fmaf(my, my, mz * mz))), fx, fy, fz);
         }
     }
@@ -144,8 +153,8 @@ __device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, i
 
 // RC >= 0: the smoothing radius is RC, known at compile time (taps from the
 // kernel arguments, LDS reads issued together); RC < 0: taps.radius, taps
-// from LDS.
-template <int V, int TX, int RC>
+// from LDS.  St: storage format of every volume the kernel reads and writes.
+template <int V, int TX, int RC, class St>
 __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
 {
     if (a.stop_at && *a.stop_at < a.n) return;
@@ -161,13 +170,14 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
     const int R = RC >= 0 ? RC : taps.radius;
     const int rows = a.ny * a.nz;
     const unsigned N = (unsigned)a.nx * (unsigned)rows;
-    const unsigned nbytes = 4u * N;
+    constexpr unsigned ES = St::kBytes;
+    const unsigned nbytes = ES * N;
     Bufs b;
     b.S = make_rsrc(a.S, nbytes);
     b.M = make_rsrc(a.M, nbytes);
     b.v = make_rsrc(a.v, 3u * nbytes);
     b.Dd = make_rsrc(a.Dd, nbytes);
-    b.P = make_rsrc(a.P, nbytes);
+    b.P = make_rsrc(a.P, 4u * N);  // FP32 in every format
     b.out = make_rsrc(a.out, 3u * nbytes);
     double s1 = 0.0, s2 = 0.0, sse = 0.0;
 
@@ -177,7 +187,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
         const bool row_ok = r < rows;
         if (row_ok) {
             const int y = r % a.ny, z = r / a.ny;
-            const unsigned rowb = 4u * (unsigned)a.nx;  // bytes per row
+            const unsigned rowb = ES * (unsigned)a.nx;  // bytes per row
             RowOffsets ro;
             ro.c = rowb * (unsigned)r;
             ro.ym = rowb * (unsigned)(max(y - 1, 0) + a.ny * z);
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
                 const int xx = x0 - R + p;  // in [0, nx)
                 float u0, u1, u2;
                 double adr, av, d2;
-                force_point<V>(a, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
+                force_point<V, St>(a, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
                 ul[0][wrow][p] = u0;
                 ul[1][wrow][p] = u1;
                 ul[2][wrow][p] = u2;
@@ -220,7 +230,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
         __syncthreads();
         const int x = x0 + lane;
         if (row_ok && x < a.nx) {
-            const unsigned rowoff = 4u * (unsigned)a.nx * (unsigned)r;
+            const unsigned rowoff = ES * (unsigned)a.nx * (unsigned)r;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float s = 0.0f;
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
                 } else {
                     for (int j = 0; j <= 2 * R; ++j) s = fmaf(wl[j], ul[c][wrow][lane + j], s);
                 }
-                bstore(b.out, s, 4u * (unsigned)x, rowoff + (unsigned)c * nbytes);
+                St::store(b.out, s, ES * (unsigned)x, rowoff + (unsigned)c * nbytes);
             }
         }
         __syncthreads();
@@ -285,26 +295,38 @@ ForceGrid force_grid(Dims d)
     return g;
 }
 
-template <int V, int RC>
+template <int V, int RC, class St>
 void launch_force_vr(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
 {
     const dim3 grid((unsigned)g.blocks), block(256);
-    if (g.tx == 64) go(c, ev, (k_force_x<V, 64, RC>), grid, block, a, taps);
-    else if (g.tx == 128) go(c, ev, (k_force_x<V, 128, RC>), grid, block, a, taps);
-    else go(c, ev, (k_force_x<V, 256, RC>), grid, block, a, taps);
+    if (g.tx == 64) go(c, ev, (k_force_x<V, 64, RC, St>), grid, block, a, taps);
+    else if (g.tx == 128) go(c, ev, (k_force_x<V, 128, RC, St>), grid, block, a, taps);
+    else go(c, ev, (k_force_x<V, 256, RC, St>), grid, block, a, taps);
 }
 
-// Radii with their own kernels: 0 (the force alone), and ceil(3 sigma) for
-// sigma = 1 and 1.5 voxels; others take the runtime-radius kernel.
-template <int V>
-void launch_force_v(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
+// Radii with their own kernels: 0 (the force alone, FP32 only), and
+// ceil(3 sigma) for sigma = 1 and 1.5 voxels; others take the runtime-radius
+// kernel.
+template <int V, class St>
+void launch_force_vs(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
 {
     switch (taps.radius) {
-    case 0: launch_force_vr<V, 0>(c, ev, g, a, taps); break;
-    case 3: launch_force_vr<V, 3>(c, ev, g, a, taps); break;
-    case 5: launch_force_vr<V, 5>(c, ev, g, a, taps); break;
-    default: launch_force_vr<V, -1>(c, ev, g, a, taps); break;
+    case 0:
+        if constexpr (St::kBytes == 4) launch_force_vr<V, 0, St>(c, ev, g, a, taps);
+        else launch_force_vr<V, -1, St>(c, ev, g, a, taps);
+        break;
+    case 3: launch_force_vr<V, 3, St>(c, ev, g, a, taps); break;
+    case 5: launch_force_vr<V, 5, St>(c, ev, g, a, taps); break;
+    default: launch_force_vr<V, -1, St>(c, ev, g, a, taps); break;
     }
+}
+
+template <int V>
+void launch_force_v(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps, int storage)
+{
+    if (storage == kStoreF16) launch_force_vs<V, StF16>(c, ev, g, a, taps);
+    else if (storage == kStoreBF16) launch_force_vs<V, StBF16>(c, ev, g, a, taps);
+    else launch_force_vs<V, StF32>(c, ev, g, a, taps);
 }
 
 }  // namespace
@@ -332,11 +354,11 @@ hipError_t launch_force(Ctx &c, const ForceLaunch &f)
     a.gxt = g.gxt;
     return timed(c, K_FORCE, [&](const Ev &ev) {
         switch (f.variant) {
-        case kPassive: launch_force_v<kPassive>(c, ev, g, a, *f.taps); break;
-        case kEvolved: launch_force_v<kEvolved>(c, ev, g, a, *f.taps); break;
-        case kActive: launch_force_v<kActive>(c, ev, g, a, *f.taps); break;
-        case kDouble: launch_force_v<kDouble>(c, ev, g, a, *f.taps); break;
-        default: launch_force_v<kInverseConsistent>(c, ev, g, a, *f.taps); break;
+        case kPassive: launch_force_v<kPassive>(c, ev, g, a, *f.taps, f.storage); break;
+        case kEvolved: launch_force_v<kEvolved>(c, ev, g, a, *f.taps, f.storage); break;
+        case kActive: launch_force_v<kActive>(c, ev, g, a, *f.taps, f.storage); break;
+        case kDouble: launch_force_v<kDouble>(c, ev, g, a, *f.taps, f.storage); break;
+        default: launch_force_v<kInverseConsistent>(c, ev, g, a, *f.taps, f.storage); break;
         }
     });
 }

@@ -11,37 +11,57 @@ using namespace dev;
 // ------------------------------------------------------------------------
 // Pyramid (Sec 2.3)
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_restrict(const float *__restrict__ in, int nx, int ny, int nz,
-                                                  float *__restrict__ out, int cx, int cy, int cz, int gx, int gy)
+// Si, So: storage formats of the fine input and the coarse output.
+template <class Si, class So>
+__global__ __launch_bounds__(256) void k_restrict(const void *__restrict__ in, int nx, int ny, int nz,
+                                                  void *__restrict__ out, int cx, int cy, int cz, int gx, int gy)
 {
     const Tile t = decode_tile(gx, gy);
     const int i = t.x * kBlockX + threadIdx.x, j = t.y * kBlockY + threadIdx.y, k = t.z;
     if (i >= cx || j >= cy) return;
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(in, Si::kBytes * (unsigned)nx * (unsigned)ny * (unsigned)nz);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(out, So::kBytes * (unsigned)cx * (unsigned)cy * (unsigned)cz);
     // FP64 sum, rounded once: coarse images feed intensity differences
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            const int row = nx * (min(2 * j + b, ny - 1) + ny * min(2 * k + c, nz - 1));
-            s += (double)in[row + min(2 * i, nx - 1)] + (double)in[row + min(2 * i + 1, nx - 1)];
+            const unsigned row = (unsigned)(nx * (min(2 * j + b, ny - 1) + ny * min(2 * k + c, nz - 1)));
+            s += (double)Si::load(rin, Si::kBytes * (row + (unsigned)min(2 * i, nx - 1)), 0) +
+                 (double)Si::load(rin, Si::kBytes * (row + (unsigned)min(2 * i + 1, nx - 1)), 0);
         }
-    out[i + cx * (j + cy * k)] = (float)(0.125 * s);
+    So::store(rout, (float)(0.125 * s), So::kBytes * (unsigned)(i + cx * (j + cy * k)), 0);
 }
 
-__global__ __launch_bounds__(256) void k_prolong(const float *__restrict__ vc, int cx, int cy, int cz,
-                                                 float *__restrict__ vf, int fx, int fy, int fz, int gx, int gy)
+// FP32 trilinear sample, at a Cell of element offsets, of a volume in format St
+// addressed through a buffer resource (soff: byte offset of its plane).
+template <class St>
+__device__ __forceinline__ float sample_st(__amdgpu_buffer_rsrc_t r, const Cell &c, unsigned soff)
+{
+    constexpr unsigned E = St::kBytes;
+    const float c00 = lerp1(St::load(r, E * c.o000, soff), St::load(r, E * c.o100, soff), c.tx);
+    const float c10 = lerp1(St::load(r, E * c.o010, soff), St::load(r, E * c.o110, soff), c.tx);
+    const float c01 = lerp1(St::load(r, E * c.o001, soff), St::load(r, E * c.o101, soff), c.tx);
+    const float c11 = lerp1(St::load(r, E * c.o011, soff), St::load(r, E * c.o111, soff), c.tx);
+    return lerp1(lerp1(c00, c10, c.ty), lerp1(c01, c11, c.ty), c.tz);
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void k_prolong(const void *__restrict__ vc, int cx, int cy, int cz,
+                                                 void *__restrict__ vf, int fx, int fy, int fz, int gx, int gy)
 {
     const Tile t = decode_tile(gx, gy);
     const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
     if (x >= fx || y >= fy) return;
+    constexpr unsigned E = St::kBytes;
+    const unsigned Nc = (unsigned)cx * (unsigned)cy * (unsigned)cz, Nf = (unsigned)fx * (unsigned)fy * (unsigned)fz;
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(vc, 3u * E * Nc), rf = make_rsrc(vf, 3u * E * Nf);
     // fine index f sits at coarse coordinate (f - 0.5) / 2
     const Cell c = make_cell(0.5f * x - 0.25f, 0.5f * y - 0.25f, 0.5f * z - 0.25f, cx, cy, cz);
-    const int Nc = cx * cy * cz, Nf = fx * fy * fz;
-    const int i = x + fx * (y + fy * z);
-    vf[i] = 2.0f * sample(vc, c);
-    vf[Nf + i] = 2.0f * sample(vc + Nc, c);
-    vf[2 * Nf + i] = 2.0f * sample(vc + 2 * Nc, c);
+    const unsigned o = E * (unsigned)(x + fx * (y + fy * z));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) St::store(rf, 2.0f * sample_st<St>(rc, c, (unsigned)k * E * Nc), o, (unsigned)k * E * Nf);
 }
 
 __global__ __launch_bounds__(256) void k_gradient(const float *__restrict__ I, int nx, int ny, int nz,
@@ -76,101 +96,157 @@ __global__ __launch_bounds__(256) void k_warp(const float *__restrict__ I, const
 // Intensity difference for the active and double forces: D = M(x - v) - S(x),
 // sampled and subtracted in FP64, rounded once.  The force kernel takes D and
 // its gradient from here (grad Im = grad D + grad S), so the gather happens
-// once per iteration.  Buffer addressing as in the force kernel.
-__global__ __launch_bounds__(256) void k_warp_diff(const float *__restrict__ M, const float *__restrict__ S,
-                                                   const float *__restrict__ v, int nx, int ny, int nz,
-                                                   float *__restrict__ D, int gx, int gy,
+// once per iteration.  Buffer addressing as in the force kernel; every volume
+// in format St.
+template <class St>
+__global__ __launch_bounds__(256) void k_warp_diff(const void *__restrict__ M, const void *__restrict__ S,
+                                                   const void *__restrict__ v, int nx, int ny, int nz,
+                                                   void *__restrict__ D, int gx, int gy,
                                                    const int *__restrict__ stop_at, int n)
 {
     if (stop_at && *stop_at < n) return;
     const Tile t = decode_tile(gx, gy);
     const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
     if (x >= nx || y >= ny) return;
-    const unsigned nbytes = 4u * (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    constexpr unsigned E = St::kBytes;
+    const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, nbytes), rS = make_rsrc(S, nbytes), rv = make_rsrc(v, 3u * nbytes),
                                  rD = make_rsrc(D, nbytes);
-    const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
-    const float vx = bload(rv, o, 0), vy = bload(rv, o, nbytes), vz = bload(rv, o, 2u * nbytes);
-    const double d = bsample64(rM, bcell_disp(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)bload(rS, o, 0);
-    bstore(rD, (float)d, o, 0);
+    const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
+    const float vx = St::load(rv, o, 0), vy = St::load(rv, o, nbytes), vz = St::load(rv, o, 2u * nbytes);
+    const double d = bsample64<St>(rM, bcell_disp<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)St::load(rS, o, 0);
+    St::store(rD, (float)d, o, 0);
 }
 
 // Inverse-consistent pair (Sec 2.2, after Eq 6): Im = M(x - h), Is = S(x + h),
 // written as D = Im - Is and P = Im + Is (the force needs D and grad P).
-// Both formed in FP64 and rounded once.
-__global__ __launch_bounds__(256) void k_warp_pair(const float *__restrict__ M, const float *__restrict__ S,
-                                                   const float *__restrict__ h, int nx, int ny, int nz,
-                                                   float *__restrict__ D, float *__restrict__ P, int gx, int gy,
+// Both formed in FP64 and rounded once: D to the storage format, P to FP32
+// (P is near twice the background intensity, where 16-bit spacing would
+// quantise the gradient the force divides by).
+template <class St>
+__global__ __launch_bounds__(256) void k_warp_pair(const void *__restrict__ M, const void *__restrict__ S,
+                                                   const void *__restrict__ h, int nx, int ny, int nz,
+                                                   void *__restrict__ D, void *__restrict__ P, int gx, int gy,
                                                    const int *__restrict__ stop_at, int n)
 {
     if (stop_at && *stop_at < n) return;
     const Tile t = decode_tile(gx, gy);
     const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
     if (x >= nx || y >= ny) return;
-    const unsigned nbytes = 4u * (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    constexpr unsigned E = St::kBytes;
+    const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, nbytes), rS = make_rsrc(S, nbytes), rh = make_rsrc(h, 3u * nbytes),
-                                 rD = make_rsrc(D, nbytes), rP = make_rsrc(P, nbytes);
-    const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
-    const float hx = bload(rh, o, 0), hy = bload(rh, o, nbytes), hz = bload(rh, o, 2u * nbytes);
-    const double im = bsample64(rM, bcell_disp(x, y, z, hx, hy, hz, nx, ny, nz));
-    const double is = bsample64(rS, bcell_disp(x, y, z, -hx, -hy, -hz, nx, ny, nz));
-    bstore(rD, (float)(im - is), o, 0);
-    bstore(rP, (float)(im + is), o, 0);
+                                 rD = make_rsrc(D, nbytes), rP = make_rsrc(P, (4u / E) * nbytes);
+    const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
+    const float hx = St::load(rh, o, 0), hy = St::load(rh, o, nbytes), hz = St::load(rh, o, 2u * nbytes);
+    const double im = bsample64<St>(rM, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz));
+    const double is = bsample64<St>(rS, bcell_disp<E>(x, y, z, -hx, -hy, -hz, nx, ny, nz));
+    St::store(rD, (float)(im - is), o, 0);
+    StF32::store(rP, (float)(im + is), (4u / E) * o, 0);
 }
 
 // ------------------------------------------------------------------------
 // Inverse-consistent output composition: w(z) = 2 h(p), p = z - h(p)
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_compose(const float *__restrict__ h, int nx, int ny, int nz, int K,
+// h in format St; the output field is FP32.
+template <class St>
+__global__ __launch_bounds__(256) void k_compose(const void *__restrict__ h, int nx, int ny, int nz, int K,
                                                  float *__restrict__ out, int gx, int gy)
 {
     const Tile t = decode_tile(gx, gy);
     const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
     if (x >= nx || y >= ny) return;
-    const unsigned nbytes = 4u * (unsigned)nx * (unsigned)ny * (unsigned)nz;
-    const __amdgpu_buffer_rsrc_t H = make_rsrc(h, 3u * nbytes);
+    constexpr unsigned E = St::kBytes;
+    const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    const __amdgpu_buffer_rsrc_t H = make_rsrc(h, 3u * E * N);
     // p = (x, y, z) - (hx, hy, hz): the position is kept as the displacement
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-    for (int k = 0; k < K; ++k) bsample3(H, bcell_disp(x, y, z, hx, hy, hz, nx, ny, nz), nbytes, hx, hy, hz);
+    for (int k = 0; k < K; ++k)
+        bsample3<St>(H, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz), E * N, hx, hy, hz);
     float ax, ay, az;
-    bsample3(H, bcell_disp(x, y, z, hx, hy, hz, nx, ny, nz), nbytes, ax, ay, az);
-    const __amdgpu_buffer_rsrc_t O = make_rsrc(out, 3u * nbytes);
+    bsample3<St>(H, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz), E * N, ax, ay, az);
+    const __amdgpu_buffer_rsrc_t O = make_rsrc(out, 12u * N);
     const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
     bstore(O, 2.0f * ax, o, 0u);
-    bstore(O, 2.0f * ay, o, nbytes);
-    bstore(O, 2.0f * az, o, 2u * nbytes);
+    bstore(O, 2.0f * ay, o, 4u * N);
+    bstore(O, 2.0f * az, o, 8u * N);
 }
 
-__global__ __launch_bounds__(256) void k_zero(float *__restrict__ p, int64_t n)
+template <class St>
+__global__ __launch_bounds__(256) void k_zero(void *__restrict__ p, unsigned n)
 {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0f;
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(p, St::kBytes * n);
+    for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) St::store(r, 0.0f, St::kBytes * i, 0);
 }
 
+// Element-wise change of storage format (rounded to nearest even).
+template <class Si, class So>
+__global__ __launch_bounds__(256) void k_convert(const void *__restrict__ in, void *__restrict__ out, unsigned n)
+{
+    const __amdgpu_buffer_rsrc_t ri = make_rsrc(in, Si::kBytes * n), ro = make_rsrc(out, So::kBytes * n);
+    for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
+        So::store(ro, Si::load(ri, Si::kBytes * i, 0), So::kBytes * i, 0);
+}
 
 }  // namespace
 
-hipError_t launch_zero(Ctx &c, float *p, int64_t n)
+namespace {
+unsigned grid_stride_blocks(int64_t n)
 {
     const int64_t want = (n + 255) / 256;
-    const unsigned blocks = (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
-    return timed(c, K_FILL, [&](const Ev &ev) { go(c, ev, k_zero, dim3(blocks), dim3(256), p, n); });
+    return (unsigned)(want < 4096 ? (want > 0 ? want : 1) : 4096);
 }
+}  // namespace
 
-hipError_t launch_restrict(Ctx &c, const float *in, Dims fine, float *out, Dims coarse)
+hipError_t launch_zero(Ctx &c, void *p, int64_t n, int st)
 {
-    const Grid2 g = plane_grid(coarse);
-    return timed(c, K_RESTRICT, [&](const Ev &ev) {
-        go(c, ev, k_restrict, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), in, fine.nx,
-                           fine.ny, fine.nz, out, coarse.nx, coarse.ny, coarse.nz, g.gx, g.gy);
+    const unsigned blocks = grid_stride_blocks(n);
+    return timed(c, K_FILL, [&](const Ev &ev) {
+        with_storage(st, [&](auto t) {
+            using St = typename decltype(t)::type;
+            go(c, ev, k_zero<St>, dim3(blocks), dim3(256), p, (unsigned)n);
+        });
     });
 }
 
-hipError_t launch_prolong(Ctx &c, const float *vc, Dims coarse, float *vf, Dims fine)
+hipError_t launch_convert(Ctx &c, const void *in, int in_st, void *out, int out_st, int64_t n)
+{
+    const unsigned blocks = grid_stride_blocks(n);
+    return timed(c, K_CONVERT, [&](const Ev &ev) {
+        with_storage(in_st, [&](auto ti) {
+            with_storage(out_st, [&](auto to) {
+                using Si = typename decltype(ti)::type;
+                using So = typename decltype(to)::type;
+                go(c, ev, k_convert<Si, So>, dim3(blocks), dim3(256), in, out, (unsigned)n);
+            });
+        });
+    });
+}
+
+hipError_t launch_restrict(Ctx &c, const void *in, int in_st, Dims fine, void *out, int out_st, Dims coarse)
+{
+    const Grid2 g = plane_grid(coarse);
+    return timed(c, K_RESTRICT, [&](const Ev &ev) {
+        with_storage(in_st, [&](auto ti) {
+            with_storage(out_st, [&](auto to) {
+                using Si = typename decltype(ti)::type;
+                using So = typename decltype(to)::type;
+                go(c, ev, k_restrict<Si, So>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), in, fine.nx, fine.ny,
+                   fine.nz, out, coarse.nx, coarse.ny, coarse.nz, g.gx, g.gy);
+            });
+        });
+    });
+}
+
+hipError_t launch_prolong(Ctx &c, const void *vc, Dims coarse, void *vf, Dims fine, int st)
 {
     const Grid2 g = plane_grid(fine);
     return timed(c, K_PROLONG, [&](const Ev &ev) {
-        go(c, ev, k_prolong, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), vc, coarse.nx,
-                           coarse.ny, coarse.nz, vf, fine.nx, fine.ny, fine.nz, g.gx, g.gy);
+        with_storage(st, [&](auto t) {
+            using St = typename decltype(t)::type;
+            go(c, ev, k_prolong<St>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), vc, coarse.nx, coarse.ny,
+               coarse.nz, vf, fine.nx, fine.ny, fine.nz, g.gx, g.gy);
+        });
     });
 }
 
@@ -192,32 +268,41 @@ hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, flo
     });
 }
 
-hipError_t launch_warp_diff(Ctx &c, const float *M, const float *S, const float *v, Dims d, float *D,
+hipError_t launch_warp_diff(Ctx &c, const void *M, const void *S, const void *v, Dims d, void *D, int st,
                             const int *stop_at, int n)
 {
     const Grid2 g = plane_grid(d);
     return timed(c, K_WARP, [&](const Ev &ev) {
-        go(c, ev, k_warp_diff, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, v, d.nx,
-                           d.ny, d.nz, D, g.gx, g.gy, stop_at, n);
+        with_storage(st, [&](auto t) {
+            using St = typename decltype(t)::type;
+            go(c, ev, k_warp_diff<St>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, v, d.nx, d.ny, d.nz, D,
+               g.gx, g.gy, stop_at, n);
+        });
     });
 }
 
-hipError_t launch_warp_pair(Ctx &c, const float *M, const float *S, const float *h, Dims d, float *D, float *P,
+hipError_t launch_warp_pair(Ctx &c, const void *M, const void *S, const void *h, Dims d, void *D, void *P, int st,
                             const int *stop_at, int n)
 {
     const Grid2 g = plane_grid(d);
     return timed(c, K_WARP_PAIR, [&](const Ev &ev) {
-        go(c, ev, k_warp_pair, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, h, d.nx,
-                           d.ny, d.nz, D, P, g.gx, g.gy, stop_at, n);
+        with_storage(st, [&](auto t) {
+            using St = typename decltype(t)::type;
+            go(c, ev, k_warp_pair<St>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, h, d.nx, d.ny, d.nz, D,
+               P, g.gx, g.gy, stop_at, n);
+        });
     });
 }
 
-hipError_t launch_compose(Ctx &c, const float *h, Dims d, int K, float *out)
+hipError_t launch_compose(Ctx &c, const void *h, int h_st, Dims d, int K, float *out)
 {
     const Grid2 g = plane_grid(d);
     return timed(c, K_COMPOSE, [&](const Ev &ev) {
-        go(c, ev, k_compose, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), h, d.nx, d.ny,
-                           d.nz, K, out, g.gx, g.gy);
+        with_storage(h_st, [&](auto t) {
+            using St = typename decltype(t)::type;
+            go(c, ev, k_compose<St>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), h, d.nx, d.ny, d.nz, K, out,
+               g.gx, g.gy);
+        });
     });
 }
 

@@ -63,8 +63,8 @@ constexpr int max_tz()
 // kernel of this iteration left per workgroup (they are complete: that kernel
 // has finished), writes the history entry and takes the stopping decision;
 // the smoothing tiles are workgroups 1 and up.
-template <int R, int TZ>
-__global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in, float *__restrict__ out, int nx,
+template <int R, int TZ, class St>
+__global__ __launch_bounds__(256) void k_smooth_yz(const void *__restrict__ in, void *__restrict__ out, int nx,
                                                    int ny, int nz, GaussTaps taps, int gx, int gy, int gz,
                                                    const int *__restrict__ stop_at, int n, SumsReduce red)
 {
@@ -89,11 +89,12 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
     const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
     const int x = min(tx * kBlockX + lane, nx - 1);  // lanes past the edge repeat the last column
     const int y_base = ty * kTileY, z0 = tz * TZ;
+    constexpr unsigned ES = St::kBytes;
     const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
-    const unsigned rowb = 4u * (unsigned)nx, planeb = rowb * (unsigned)ny;
-    const __amdgpu_buffer_rsrc_t src = make_rsrc(in + (size_t)c * N, 4u * N);
-    const __amdgpu_buffer_rsrc_t dst = make_rsrc(out + (size_t)c * N, 4u * N);
-    const unsigned xb = 4u * (unsigned)x;
+    const unsigned rowb = ES * (unsigned)nx, planeb = rowb * (unsigned)ny;
+    const __amdgpu_buffer_rsrc_t src = make_rsrc(static_cast<const char *>(in) + (size_t)c * ES * N, ES * N);
+    const __amdgpu_buffer_rsrc_t dst = make_rsrc(static_cast<char *>(out) + (size_t)c * ES * N, ES * N);
+    const unsigned xb = ES * (unsigned)x;
     float w[2 * R + 1];
 #pragma unroll
     for (int j = 0; j <= 2 * R; ++j) w[j] = taps.w[j];
@@ -111,10 +112,10 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
         const unsigned rb = rowb * (unsigned)clampi(y_base - R + (two ? row2 : row), ny);
         float wa[TZ + 2 * R], wb[TZ + 2 * R];
 #pragma unroll
-        for (int k = 0; k < TZ + 2 * R; ++k) wa[k] = bload(src, xb, ra + zoff[k]);
+        for (int k = 0; k < TZ + 2 * R; ++k) wa[k] = St::load(src, xb, ra + zoff[k]);
         if (two) {
 #pragma unroll
-            for (int k = 0; k < TZ + 2 * R; ++k) wb[k] = bload(src, xb, rb + zoff[k]);
+            for (int k = 0; k < TZ + 2 * R; ++k) wb[k] = St::load(src, xb, rb + zoff[k]);
         }
 #pragma unroll
         for (int k = 0; k < TZ; ++k) {
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
     const int xo = tx * kBlockX + lane;
     const int y0 = y_base + wave * kRowsPerThread;
     if (xo >= nx || y0 >= ny) return;
-    const unsigned ob = 4u * (unsigned)xo;
+    const unsigned ob = ES * (unsigned)xo;
     for (int k = 0; k < TZ; ++k) {
         if (z0 + k >= nz) break;
         float v[kRowsPerThread + 2 * R];
@@ -151,18 +152,18 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const float *__restrict__ in,
             float s = 0.0f;
 #pragma unroll
             for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], v[q + j], s);
-            if (y0 + q < ny) bstore(dst, s, ob, zb + rowb * (unsigned)(y0 + q));
+            if (y0 + q < ny) St::store(dst, s, ob, zb + rowb * (unsigned)(y0 + q));
         }
     }
 }
 
-template <int R, int TZ>
-void launch_yz_tz(Ctx &c, const Ev &ev, const float *in, float *out, int ncomp, Dims d, const GaussTaps &taps, const int *stop_at,
-                  int n, const SumsReduce &red)
+template <int R, int TZ, class St>
+void launch_yz_tz(Ctx &c, const Ev &ev, const void *in, void *out, int ncomp, Dims d, const GaussTaps &taps,
+                  const int *stop_at, int n, const SumsReduce &red)
 {
     const int gx = ceil_div(d.nx, kBlockX), gy = ceil_div(d.ny, kTileY), gz = ceil_div(d.nz, TZ);
     const int64_t blocks = (int64_t)gx * gy * gz * ncomp + (red.partials ? 1 : 0);
-    go(c, ev, (k_smooth_yz<R, TZ>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), in, out,
+    go(c, ev, (k_smooth_yz<R, TZ, St>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), in, out,
                        d.nx, d.ny, d.nz, taps, gx, gy, gz, stop_at, n, red);
 }
 
@@ -170,32 +171,41 @@ void launch_yz_tz(Ctx &c, const Ev &ev, const float *in, float *out, int ncomp, 
 // 2R halo planes, so deeper chunks cost fewer loads per output).
 constexpr int64_t kYZTargetBlocks = 1024;
 
-template <int R>
-hipError_t launch_yz_r(Ctx &c, const float *in, float *out, int ncomp, Dims d, const GaussTaps &taps,
+template <int R, class St>
+hipError_t launch_yz_r(Ctx &c, const void *in, void *out, int ncomp, Dims d, const GaussTaps &taps,
                        const int *stop_at, int n, const SumsReduce &red)
 {
     const int64_t tiles = (int64_t)ceil_div(d.nx, kBlockX) * ceil_div(d.ny, kTileY) * ncomp;
     const bool deep = max_tz<R>() == 8 && tiles * ceil_div(d.nz, 8) >= kYZTargetBlocks;
     return timed(c, K_SMOOTH_YZ, [&](const Ev &ev) {
-        if (deep) launch_yz_tz<R, max_tz<R>()>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
-        else if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
-        else launch_yz_tz<R, 2>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
+        if (deep) launch_yz_tz<R, max_tz<R>(), St>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
+        else if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4, St>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
+        else launch_yz_tz<R, 2, St>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
     });
 }
 
 }  // namespace
 
-hipError_t launch_smooth_yz(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out,
-                            const int *stop_at, int n, const SumsReduce &red)
+template <class St>
+hipError_t launch_smooth_yz_st(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out,
+                               const int *stop_at, int n, const SumsReduce &red)
 {
     switch (taps.radius) {
 #define DIR_R(r) \
-    case r: return launch_yz_r<r>(c, in, out, ncomp, d, taps, stop_at, n, red);
+    case r: return launch_yz_r<r, St>(c, in, out, ncomp, d, taps, stop_at, n, red);
         DIR_R(0) DIR_R(1) DIR_R(2) DIR_R(3) DIR_R(4) DIR_R(5) DIR_R(6) DIR_R(7) DIR_R(8)
         DIR_R(9) DIR_R(10) DIR_R(11) DIR_R(12) DIR_R(13) DIR_R(14) DIR_R(15) DIR_R(16)
 #undef DIR_R
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_smooth_yz(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out, int st,
+                            const int *stop_at, int n, const SumsReduce &red)
+{
+    if (st == kStoreF16) return launch_smooth_yz_st<StF16>(c, in, ncomp, d, taps, out, stop_at, n, red);
+    if (st == kStoreBF16) return launch_smooth_yz_st<StBF16>(c, in, ncomp, d, taps, out, stop_at, n, red);
+    return launch_smooth_yz_st<StF32>(c, in, ncomp, d, taps, out, stop_at, n, red);
 }
 
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out)

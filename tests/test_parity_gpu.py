@@ -373,7 +373,7 @@ def test_invalid_arguments(B, h):
     assert L.dir_register(h.ptr, ptr(S), ptr(S), 6, 5, 4, None, ctypes.byref(p), None, None) == B.DIR_EINVAL
     assert L.dir_register(h.ptr, ptr(S), ptr(S), 0, 5, 4, None, ctypes.byref(p), ptr(out), None) == B.DIR_EINVAL
     for field, value in (("alpha", 0.0), ("sigma", -1.0), ("levels", 0), ("levels", 9), ("variant", 7),
-                         ("radius", 17), ("eps", -1.0), ("reserved", 1), ("struct_size", 8)):
+                         ("radius", 17), ("eps", -1.0), ("storage", 3), ("storage", -1), ("struct_size", 8)):
         q = B.make_params("passive", [2], sigma=1.0)
         setattr(q, field, value)
         assert L.dir_register(h.ptr, ptr(S), ptr(S), 6, 5, 4, None, ctypes.byref(q), ptr(out), None) == B.DIR_EINVAL
