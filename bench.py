@@ -49,13 +49,19 @@ SETTINGS = [("passive", "passive", 1.0), ("active", "active", 1.0), ("double", "
 METRIC = "voxel-iters/s + HBM GB/s fraction; p50/p99 per-registration latency"
 
 # Algorithmic HBM bytes per voxel of one launch (each operand read or written
-# once; stencil neighbours and gather re-reads are not counted).
-ALGO_BYTES_PER_VOXEL = {
-    "force": 32.0,       # two images 8 + field 12 in + x-smoothed field 12 out
-    "warp": 24.0,        # M 4 (gathered) + S 4 + field 12 + D = Im - S 4
-    "warp_pair": 28.0,   # M 4 + S 4 (both gathered) + h 12 + D 4 + P 4
-    "smooth_yz": 24.0,   # field 12 in + 12 out
-}
+# once; stencil neighbours and gather re-reads are not counted), for stored
+# values of `es` bytes (4: FP32, 2: F16/BF16).
+def algo_bytes_per_voxel(kernel, es=4):
+    return {
+        "force": 8.0 * es,           # two images + field in (3) + x-smoothed field out (3)
+        "warp": 6.0 * es,            # M (gathered) + S + field (3) + D = Im - S
+        "warp_pair": 6.0 * es + 4,   # M + S (both gathered) + h (3) + D; P = Im + Is is FP32
+        "smooth_yz": 6.0 * es,       # field in (3) + out (3)
+    }.get(kernel)
+
+
+ALGO_BYTES_PER_VOXEL = {k: algo_bytes_per_voxel(k) for k in ("force", "warp", "warp_pair", "smooth_yz")}
+STORAGE_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
 
 
 def level_dims(shape, levels):
@@ -117,6 +123,89 @@ def cpu_baseline(S, M):
                       f"coarse to fine ({vi} voxel-iterations, {dt:.1f} s, FP64)", "seconds": dt}
 
 
+# Reduced-precision study: 512x512x160 phantoms (max displacement 20
+# voxels), 4 levels with 100/100/50/25 iterations coarse to fine, passive and
+# inverse-consistent, each registered with FP32, F16 and BF16 storage.
+STUDY_SHAPE = (512, 512, 160)
+STUDY_SEED = 4
+STUDY_MAX_U = 20.0
+STUDY_ITERS = [100, 100, 50, 25]
+STUDY_VARIANTS = ("passive", "inverse_consistent")
+
+
+def storage_study(args):
+    import torch
+    from paper_0909_0928_amd import binding as B
+    from paper_0909_0928_amd import phantom as P
+
+    print(f"[study] building phantom {STUDY_SHAPE}", file=sys.stderr, flush=True)
+    ph = P.make_phantom(STUDY_SHAPE, seed=STUDY_SEED, max_u=STUDY_MAX_U, spacing_mm=SPACING)
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(ph.static.astype(np.float32)).to(dev)
+    M = torch.from_numpy(ph.moving.astype(np.float32)).to(dev)
+    out = torch.empty((3,) + tuple(S.shape), dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(0)
+    body = np.flatnonzero(ph.body.ravel())
+    sample = np.sort(rng.choice(body, size=min(100000, body.size), replace=False))
+    z, y, x = np.unravel_index(sample, ph.static.shape)
+    vt, _ = ph.ground_truth(x.astype(float), y.astype(float), z.astype(float))
+    sample_dev = torch.from_numpy(sample).to(dev)
+    h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))
+    vi = voxel_iters(STUDY_SHAPE, STUDY_ITERS)
+    n0 = STUDY_SHAPE[0] * STUDY_SHAPE[1] * STUDY_SHAPE[2]
+    rows = []
+    for variant in STUDY_VARIANTS:
+        ref = None
+        for st in ("f32", "f16", "bf16"):
+            p = B.make_params(variant, STUDY_ITERS, sigma=SIGMA, radius=RADIUS, storage=st)
+            B.dir_register(h, S, M, p, field_out=out, history=False)           # warm-up
+            times = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                B.dir_register(h, S, M, p, field_out=out, history=False)
+                times.append(time.perf_counter() - t0)
+            t = float(np.median(times))
+            B.dir_timing_enable(h, ["force", "smooth_yz"])
+            B.dir_register(h, S, M, p, field_out=out, history=False)
+            fk = {k: B.dir_timing_read(h, k, level=0) for k in ("force", "smooth_yz")}
+            B.dir_timing_enable(h, ())
+            f = out.view(3, -1)
+            d = f[:, sample_dev].cpu().numpy().astype(np.float64) - vt
+            gt = float(np.sqrt((d ** 2).sum(axis=0)).mean())
+            row = {"variant": variant, "storage": st, "seconds_per_registration": t, "voxel_iter_per_s": vi / t,
+                   "gt_error_vox": gt}
+            es = STORAGE_BYTES[st]
+            for k, (ms, n) in fk.items():
+                us = ms * 1e3 / max(n, 1)
+                gbs = algo_bytes_per_voxel(k, es) * n0 / (us * 1e-6) / 1e9
+                row[k + "_finest"] = {"avg_launch_us": us, "algo_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS}
+            if ref is None:
+                ref = out.clone()
+            else:
+                dd = ((out - ref) ** 2).sum(dim=0)
+                row["rms_vs_f32_vox"] = float(dd.mean().sqrt())
+                row["rms_vs_f32_body_sample_vox"] = float(dd.view(-1)[sample_dev].mean().sqrt())
+                row["gt_error_change_vox"] = gt - rows[-1 if st == "f16" else -2]["gt_error_vox"]
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+        if args.with_oracle:
+            import oracle as O
+            print(f"[study] FP64 oracle, {variant}", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            of, _, _, _ = O.register(ph.static.astype(np.float32).astype(np.float64),
+                                     ph.moving.astype(np.float32).astype(np.float64), O.VARIANTS[variant],
+                                     STUDY_ITERS, sigma=SIGMA, radius=RADIUS)
+            dt = time.perf_counter() - t0
+            g = ref.cpu().numpy().astype(np.float64).reshape(3, -1)
+            orc = {"variant": variant, "oracle_seconds": dt,
+                   "rms_gpu_f32_vs_oracle_vox": float(np.sqrt(((g - of.reshape(3, -1)) ** 2).sum(axis=0).mean()))}
+            print(json.dumps(orc), flush=True)
+    B.dir_destroy(h)
+    print(json.dumps({"study": "storage", "shape_xyz": list(STUDY_SHAPE), "iters_coarse_to_fine": STUDY_ITERS,
+                      "sigma": SIGMA, "radius": RADIUS, "max_u": STUDY_MAX_U, "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +216,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gt", action="store_true", help="skip the ground-truth error pass (profiling runs)")
     ap.add_argument("--roofline-kernel", default=None, help="kernel to time for the roofline (default: largest)")
+    ap.add_argument("--storage", choices=("f32", "f16", "bf16"), default="f32",
+                    help="storage format of images and fields inside the registrations (arithmetic stays FP32)")
+    ap.add_argument("--study-storage", action="store_true",
+                    help="instead: the 512x512x160 reduced-precision study (F32, F16, BF16; passive and IC)")
+    ap.add_argument("--with-oracle", action="store_true", help="study: also run the FP64 oracle on the FP32 inputs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain device copies of known size (counter calibration)")
     args = ap.parse_args()
@@ -136,6 +230,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.study_storage:
+        storage_study(args)
+        return
     if args.copy_probe:
         n = 256 * 1024 * 1024 // 4
         a = torch.ones(n, device="cuda")
@@ -157,7 +254,9 @@ def main():
     S = torch.from_numpy(ph.static.astype(np.float32)).to(dev)
     M = torch.from_numpy(ph.moving.astype(np.float32)).to(dev)
     outs = [torch.empty((3,) + tuple(S.shape), dtype=torch.float32, device=dev) for _ in SETTINGS]
-    params = {name: B.make_params(var, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha) for name, var, alpha in SETTINGS}
+    params = {name: B.make_params(var, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha, storage=args.storage)
+              for name, var, alpha in SETTINGS}
+    es = STORAGE_BYTES[args.storage]
     torch.cuda.synchronize()
     streams = [torch.cuda.Stream(device=dev) for _ in SETTINGS]       # default priority
     handles = [B.dir_create(0, stream=st) for st in streams]
@@ -233,18 +332,20 @@ def main():
     n_act = sum(1 for _, v, _ in SETTINGS if v in ("active", "double"))
     units = launch_units(dominant, SHAPE, ITERS, n_ic, n_act, len(SETTINGS))
     roof = None
-    if units is not None and dominant in ALGO_BYTES_PER_VOXEL and kern_launches:
-        bytes_total = units * ALGO_BYTES_PER_VOXEL[dominant] * args.latency_steps
+    abpv = algo_bytes_per_voxel(dominant, es)
+    if units is not None and abpv is not None and kern_launches:
+        bytes_total = units * abpv * args.latency_steps
         achieved = bytes_total / (kern_ms * 1e-3) / 1e9
-        traffic, traffic_src = measured_traffic(dominant)
+        traffic, traffic_src = measured_traffic(dominant) if args.storage == "f32" else \
+            (None, "the committed traffic records are of FP32 storage")
         roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_us": kern_ms * 1e3 / kern_launches, "launches": kern_launches,
-                "algo_bytes_per_voxel": ALGO_BYTES_PER_VOXEL[dominant],
+                "algo_bytes_per_voxel": abpv,
                 "bytes_per_launch": bytes_total / kern_launches, "traffic_source": traffic_src,
                 "timed_in": f"{args.latency_steps} sequential steps after the timed region"}
         if fine_launches:
-            fine_bytes = SHAPE[0] * SHAPE[1] * SHAPE[2] * ALGO_BYTES_PER_VOXEL[dominant]
+            fine_bytes = SHAPE[0] * SHAPE[1] * SHAPE[2] * abpv
             fine_gbs = fine_bytes * fine_launches / (fine_ms * 1e-3) / 1e9
             roof["finest_level"] = {"shape_xyz": list(SHAPE), "launches": fine_launches,
                                     "avg_launch_us": fine_ms * 1e3 / fine_launches, "bytes_per_launch": fine_bytes,
@@ -275,7 +376,7 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "voxel-iter/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "storage": args.storage, "data": "synthetic",
         "config": {"workload": "256x256x100 synthetic 4DCT phantom pair, 3-level pyramid, 100/50/25 iterations "
                                "coarse to fine, sigma 1.5 (R 5), six force settings per step",
                    "shape_xyz": list(SHAPE), "iters_coarse_to_fine": ITERS, "sigma": SIGMA, "radius": RADIUS,

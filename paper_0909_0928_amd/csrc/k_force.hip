@@ -2,8 +2,9 @@
 // the Gaussian smoothing (Sec 2.5 low-pass filter) and the per-workgroup FP64
 // sums behind the relative norm of Sec 2.4.
 //
-// A workgroup of 256 threads owns an x tile of TX voxels (TX = 64, 128 or
-// 256; 256/TX rows in flight) and walks `rows_per_block` row steps.  For each
+// A workgroup of 256 threads owns an x tile of TX voxels (TX = 64, 128, 256
+// or 512; 256/TX rows in flight when TX < 256, and TX/256 voxels per thread
+// when TX = 512) and walks `rows_per_block` row steps.  For each
 // row it evaluates u = v + dr at the TX tile voxels plus an R-voxel halo on
 // both sides where the halo lies inside the row (past a row end the halo is
 // the end voxel's u, by index clamping, and is copied, not recomputed: a
@@ -158,12 +159,13 @@ template <int V, int TX, int RC, class St>
 __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
 {
     if (a.stop_at && *a.stop_at < a.n) return;
-    constexpr int W = 256 / TX;
+    constexpr int LANES = TX < 256 ? TX : 256;  // threads per row
+    constexpr int W = 256 / LANES;               // rows in flight
     __shared__ float ul[3][W][TX + 2 * kMaxRadius];
     __shared__ float wl[2 * kMaxRadius + 1];  // taps, read as LDS broadcasts
     const int tid = threadIdx.x;
     if (tid <= 2 * kMaxRadius) wl[tid] = taps.w[tid];  // ordered before use by the row barrier
-    const int lane = tid % TX, wrow = tid / TX;
+    const int lane = tid % LANES, wrow = tid / LANES;
     const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
     const int x0 = (lid % a.gxt) * TX;
     const int rb = lid / a.gxt;
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
             // the row: a halo slot beyond a row end holds the end voxel's u
             // (clamped index), so the end lanes copy theirs there instead.
             const int p_lo = max(R - x0, 0), p_hi = min(TX + 2 * R, a.nx - x0 + R);
-            for (int p = p_lo + lane; p < p_hi; p += TX) {
+            for (int p = p_lo + lane; p < p_hi; p += LANES) {
                 const int xx = x0 - R + p;  // in [0, nx)
                 float u0, u1, u2;
                 double adr, av, d2;
@@ -228,20 +230,22 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
             }
         }
         __syncthreads();
-        const int x = x0 + lane;
-        if (row_ok && x < a.nx) {
-            const unsigned rowoff = ES * (unsigned)a.nx * (unsigned)r;
+        const unsigned rowoff = ES * (unsigned)a.nx * (unsigned)r;
+#pragma unroll
+        for (int xl = lane; xl < TX; xl += LANES) {
+            const int x = x0 + xl;
+            if (!row_ok || x >= a.nx) break;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float s = 0.0f;
                 if constexpr (RC >= 0) {
                     float u[2 * RC + 1];
 #pragma unroll
-                    for (int j = 0; j <= 2 * RC; ++j) u[j] = ul[c][wrow][lane + j];
+                    for (int j = 0; j <= 2 * RC; ++j) u[j] = ul[c][wrow][xl + j];
 #pragma unroll
                     for (int j = 0; j <= 2 * RC; ++j) s = fmaf(taps.w[j], u[j], s);
                 } else {
-                    for (int j = 0; j <= 2 * R; ++j) s = fmaf(wl[j], ul[c][wrow][lane + j], s);
+                    for (int j = 0; j <= 2 * R; ++j) s = fmaf(wl[j], ul[c][wrow][xl + j], s);
                 }
                 St::store(b.out, s, ES * (unsigned)x, rowoff + (unsigned)c * nbytes);
             }
@@ -284,8 +288,9 @@ constexpr int64_t kTargetForceBlocks = 8192;
 ForceGrid force_grid(Dims d)
 {
     ForceGrid g;
-    g.tx = d.nx <= 64 ? 64 : (d.nx <= 128 ? 128 : 256);
-    const int w = 256 / g.tx;
+    // the narrowest tile spanning the row (no interior halo), up to 512
+    g.tx = d.nx <= 64 ? 64 : (d.nx <= 128 ? 128 : (d.nx <= 256 ? 256 : 512));
+    const int w = g.tx < 256 ? 256 / g.tx : 1;
     g.gxt = ceil_div(d.nx, g.tx);
     const int64_t steps = ((int64_t)d.ny * d.nz + w - 1) / w;  // row steps of the whole volume
     const int64_t per_tile = (kTargetForceBlocks + g.gxt - 1) / g.gxt;
@@ -301,7 +306,8 @@ void launch_force_vr(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &
     const dim3 grid((unsigned)g.blocks), block(256);
     if (g.tx == 64) go(c, ev, (k_force_x<V, 64, RC, St>), grid, block, a, taps);
     else if (g.tx == 128) go(c, ev, (k_force_x<V, 128, RC, St>), grid, block, a, taps);
-    else go(c, ev, (k_force_x<V, 256, RC, St>), grid, block, a, taps);
+    else if (g.tx == 256) go(c, ev, (k_force_x<V, 256, RC, St>), grid, block, a, taps);
+    else go(c, ev, (k_force_x<V, 512, RC, St>), grid, block, a, taps);
 }
 
 // Radii with their own kernels: 0 (the force alone, FP32 only), and

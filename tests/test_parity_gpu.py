@@ -138,7 +138,7 @@ def test_force(B, h, shape3, variant, alpha):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
 
-STEP_SHAPES = [(11, 13, 17), (9, 33, 65), (20, 40, 72), (7, 30, 129), (2, 3, 300), (1, 2, 257), (3, 4, 530)]
+STEP_SHAPES = [(11, 13, 17), (9, 33, 65), (20, 40, 72), (7, 30, 129), (2, 3, 300), (1, 2, 257), (3, 4, 530), (1, 3, 1100)]
 
 
 @pytest.mark.parametrize("shape3", STEP_SHAPES)
