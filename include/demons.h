@@ -236,6 +236,43 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
 int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, int32_t nz, int32_t K,
                     float *d_out);
 
+/* Workspace (device bytes) a handle allocates for a registration with these
+ * sizes and parameters; host-only, no device needed.  DIR_EINVAL for
+ * parameters dir_register would reject. */
+int32_t dir_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const dir_params *params, uint64_t *bytes);
+
+/* Request pool (serving).  A pool runs submitted registrations on `slots`
+ * handles of its own, each with its own stream, so registrations that arrive
+ * while others run overlap with them on the device.  Requests are admitted in
+ * arrival order when a slot is free and the workspace all slots then hold
+ * stays within max_bytes (0: no limit); a slot keeps its workspace between
+ * requests (resident pyramids and fields) and free slots give it back when a
+ * request would not fit otherwise.  The pool has no thread of its own: every
+ * pool call first collects finished registrations without blocking and admits
+ * queued ones.  Results are bitwise those of dir_register on the same inputs.
+ * Not thread-safe.
+ *
+ * dir_pool_submit: queue a registration (arguments as dir_register; the
+ *   device buffers must stay valid until its result is taken) and return its
+ *   ticket (> 0).  DIR_ENOMEM if it needs more than max_bytes by itself.
+ * dir_pool_poll: *done = 1 and the registration's status if it finished (its
+ *   result is then taken: stats, if not NULL, receives it without history),
+ *   else *done = 0 and DIR_OK.  DIR_EINVAL for an unknown or taken ticket.
+ * dir_pool_wait: block until the ticket finishes; its status.
+ * dir_pool_stats: workspace held now, the peak held after any admission, the
+ *   peak number of registrations running at once, requests queued now. */
+typedef struct dir_pool dir_pool;
+int32_t dir_pool_create(dir_pool **out, int32_t device, int32_t slots, uint64_t max_bytes);
+int32_t dir_pool_destroy(dir_pool *p);
+int32_t dir_pool_submit(dir_pool *p, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                        int32_t nz, const double *spacing_mm, const dir_params *params, float *d_field_out,
+                        int64_t *ticket);
+int32_t dir_pool_progress(dir_pool *p);
+int32_t dir_pool_poll(dir_pool *p, int64_t ticket, dir_stats *stats, int32_t *done);
+int32_t dir_pool_wait(dir_pool *p, int64_t ticket, dir_stats *stats);
+int32_t dir_pool_stats(const dir_pool *p, uint64_t *held_bytes_now, uint64_t *peak_bytes, int32_t *peak_running,
+                       int32_t *queued_now);
+
 /* Per-kernel device timing with HIP events on the handle's stream.
  * Kernels are numbered 0 .. dir_timing_count()-1; dir_timing_name(k) gives
  * the kernel's name (NULL if k is out of range).

@@ -82,6 +82,16 @@ def lib():
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.dir_wait.argtypes = [vp, vp]
         L.dir_set_graphs.argtypes = [vp, i32]
+        u64, i64 = ctypes.c_uint64, ctypes.c_int64
+        L.dir_workspace_bytes.argtypes = [i32, i32, i32, vp, ctypes.POINTER(u64)]
+        L.dir_pool_create.argtypes = [ctypes.POINTER(vp), i32, i32, u64]
+        L.dir_pool_destroy.argtypes = [vp]
+        L.dir_pool_submit.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, ctypes.POINTER(i64)]
+        L.dir_pool_progress.argtypes = [vp]
+        L.dir_pool_poll.argtypes = [vp, i64, vp, ctypes.POINTER(i32)]
+        L.dir_pool_wait.argtypes = [vp, i64, vp]
+        L.dir_pool_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32)]
         L.dir_compose.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.dir_timing_count.restype = i32
         L.dir_timing_name.restype = ctypes.c_char_p
@@ -92,6 +102,8 @@ def lib():
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
                      "dir_register_async", "dir_wait", "dir_set_graphs", "dir_step_stored",
+                     "dir_workspace_bytes", "dir_pool_create", "dir_pool_destroy", "dir_pool_submit",
+                     "dir_pool_progress", "dir_pool_poll", "dir_pool_wait", "dir_pool_stats",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
             getattr(L, name).restype = i32
         _lib = L
@@ -425,3 +437,82 @@ def dir_timing_read(h, kernel, level=None):
         _check(lib().dir_timing_read_level(h.ptr, k, int(level), ctypes.byref(ms), ctypes.byref(n)),
                "dir_timing_read_level")
     return ms.value, n.value
+
+
+def dir_workspace_bytes(shape_zyx, params):
+    """Device bytes a handle allocates for a registration of this shape [nz, ny, nx]."""
+    nz, ny, nx = shape_zyx
+    b = ctypes.c_uint64()
+    _check(lib().dir_workspace_bytes(int(nx), int(ny), int(nz), ctypes.byref(params), ctypes.byref(b)),
+           "dir_workspace_bytes")
+    return b.value
+
+
+class Pool:
+    """dir_pool: registrations of any size admitted by workspace budget onto
+    `slots` streams.  submit() keeps the request's tensors alive until its
+    result is taken by poll() or wait()."""
+
+    def __init__(self, slots=4, max_bytes=0, device=0):
+        self.ptr = ctypes.c_void_p()
+        _check(lib().dir_pool_create(ctypes.byref(self.ptr), int(device), int(slots), ctypes.c_uint64(max_bytes)),
+               "dir_pool_create")
+        self.device = device
+        self._live = {}
+
+    def submit(self, static, moving, params, field_out=None, spacing_mm=None):
+        field_out, sp = _register_args(static, moving, params, field_out, spacing_mm)
+        nx, ny, nz = _dims(static)
+        t = ctypes.c_int64()
+        _check(lib().dir_pool_submit(self.ptr, _ptr(static), _ptr(moving), nx, ny, nz, sp, ctypes.byref(params),
+                                     _ptr(field_out), ctypes.byref(t)), "dir_pool_submit")
+        self._live[t.value] = (static, moving, field_out, params)
+        return t.value
+
+    def _stats(self):
+        st = dir_stats()
+        st.struct_size = ctypes.sizeof(dir_stats)
+        return st
+
+    def poll(self, ticket):
+        """None while running or queued, else (field, stats dict)."""
+        st = self._stats()
+        done = ctypes.c_int32()
+        rc = lib().dir_pool_poll(self.ptr, int(ticket), ctypes.byref(st), ctypes.byref(done))
+        if not done.value:
+            _check(rc, "dir_pool_poll")
+            return None
+        live = self._live.pop(ticket, None)
+        if rc != DIR_OK:
+            raise DemonsError(rc, "dir_pool_poll")
+        return live[2], _stats_dict(rc, st, None)
+
+    def wait(self, ticket):
+        st = self._stats()
+        rc = lib().dir_pool_wait(self.ptr, int(ticket), ctypes.byref(st))
+        live = self._live.pop(ticket, None)
+        if rc != DIR_OK:
+            raise DemonsError(rc, "dir_pool_wait")
+        return live[2], _stats_dict(rc, st, None)
+
+    def progress(self):
+        _check(lib().dir_pool_progress(self.ptr), "dir_pool_progress")
+
+    def stats(self):
+        held, peak = ctypes.c_uint64(), ctypes.c_uint64()
+        run, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().dir_pool_stats(self.ptr, ctypes.byref(held), ctypes.byref(peak), ctypes.byref(run),
+                                    ctypes.byref(q)), "dir_pool_stats")
+        return {"held_bytes": held.value, "peak_bytes": peak.value, "peak_running": run.value, "queued": q.value}
+
+    def close(self):
+        if self.ptr:
+            lib().dir_pool_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

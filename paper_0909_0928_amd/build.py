@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdemons.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["k_pyramid.hip", "k_force.hip", "k_smooth.hip", "abi.hip"]
+SOURCES = ["k_pyramid.hip", "k_force.hip", "k_smooth.hip", "abi.hip", "pool.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -6,6 +6,7 @@
 
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "demons.h"
@@ -645,31 +646,127 @@ struct RegPlan {
     int64_t hist_off[DIR_MAX_LEVELS];
 };
 
+// Parameter checks of a registration that need no pointers.
+int check_register_params(int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
+{
+    if (!p || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    if (p->struct_size != (int32_t)sizeof(dir_params)) return DIR_EINVAL;
+    if (p->storage < kStoreF32 || p->storage > kStoreBF16) return DIR_EINVAL;
+    if (p->variant < kPassive || p->variant > kInverseConsistent) return DIR_EINVAL;
+    if (!(p->alpha > 0.0) || !isfinite(p->alpha) || !(p->sigma > 0.0) || !isfinite(p->sigma)) return DIR_EINVAL;
+    if (!(p->eps >= 0.0) || !isfinite(p->eps)) return DIR_EINVAL;
+    if (p->levels < 1 || p->levels > DIR_MAX_LEVELS) return DIR_EINVAL;
+    for (int l = 0; l < p->levels; ++l)
+        if (p->iters[l] < 0) return DIR_EINVAL;
+    const int R = resolve_radius(p->sigma, p->radius);
+    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+    return DIR_OK;
+}
+
+// Bytes of every workspace buffer a registration needs (parameters checked).
+struct RegSizes {
+    size_t pyr, img0, field, img_a, img_b, partials, history, state;
+    size_t total() const { return 2 * pyr + 2 * img0 + 2 * field + img_a + img_b + partials + history + state; }
+};
+
+RegSizes register_sizes(int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
+{
+    RegSizes z;
+    const int L = p->levels;
+    int64_t total_iters = 0;
+    for (int l = 0; l < L; ++l) total_iters += p->iters[l];
+    Dims d{nx, ny, nz};
+    const size_t n0 = (size_t)d.n();
+    const size_t es = storage_bytes(p->storage);  // bytes per stored value
+    size_t pyr = 0, nb = 0;
+    for (int k = 0; k < L; ++k) {
+        if (k > 0) {
+            d = coarser(d);
+            pyr += (size_t)d.n();
+        }
+        nb = std::max(nb, (size_t)force_blocks(d));
+    }
+    const bool pre = p->variant == kActive || p->variant == kDouble || p->variant == kInverseConsistent;
+    z.pyr = L > 1 ? es * pyr : 0;                     // S and M, levels 1..
+    z.img0 = p->storage != kStoreF32 ? es * n0 : 0;   // S and M, finest level, 16-bit copies
+    z.field = es * 3 * n0;                            // v and the x-smoothed u
+    z.img_a = pre ? es * n0 : 0;                      // D
+    z.img_b = p->variant == kInverseConsistent ? sizeof(float) * n0 : 0;  // P, FP32
+    z.partials = sizeof(double) * 3 * nb;
+    z.history = sizeof(double) * 4 * (size_t)(total_iters > 0 ? total_iters : 1);
+    z.state = sizeof(LevelState) * DIR_MAX_LEVELS;
+    return z;
+}
+
+}  // namespace
+
+namespace dir {
+
+size_t workspace_now(const dir_handle *h)
+{
+    size_t b = h->pyr_s.bytes + h->pyr_m.bytes + h->img_a.bytes + h->img_b.bytes + h->img0_s.bytes +
+               h->img0_m.bytes + h->partials.bytes + h->history.bytes + h->state.bytes;
+    for (const auto &f : h->field) b += f.bytes;
+    return b;
+}
+
+size_t workspace_after(const dir_handle *h, int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
+{
+    const RegSizes z = register_sizes(nx, ny, nz, p);
+    auto mx = [](size_t a, size_t b) { return a > b ? a : b; };
+    return mx(h->pyr_s.bytes, z.pyr) + mx(h->pyr_m.bytes, z.pyr) + mx(h->img0_s.bytes, z.img0) +
+           mx(h->img0_m.bytes, z.img0) + mx(h->field[0].bytes, z.field) + mx(h->field[1].bytes, z.field) +
+           h->field[2].bytes + mx(h->img_a.bytes, z.img_a) + mx(h->img_b.bytes, z.img_b) +
+           mx(h->partials.bytes, z.partials) + mx(h->history.bytes, z.history) + mx(h->state.bytes, z.state);
+}
+
+void workspace_release(dir_handle *h)
+{
+    h->pyr_s.release();
+    h->pyr_m.release();
+    for (auto &f : h->field) f.release();
+    h->img_a.release();
+    h->img_b.release();
+    h->img0_s.release();
+    h->img0_m.release();
+    h->partials.release();
+    h->history.release();
+    h->state.release();
+    if (h->graph_exec) {
+        hipGraphExecDestroy(h->graph_exec);
+        h->graph_exec = nullptr;
+    }
+}
+
+}  // namespace dir
+
+extern "C" int32_t dir_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const dir_params *params, uint64_t *bytes)
+{
+    if (!bytes) return DIR_EINVAL;
+    const int rc = check_register_params(nx, ny, nz, params);
+    if (rc != DIR_OK) return rc;
+    *bytes = (uint64_t)register_sizes(nx, ny, nz, params).total();
+    return DIR_OK;
+}
+
+namespace {
+
 // Validate the arguments of a registration and size the workspace for it.
 int plan_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny, int32_t nz,
                   const double *spacing_mm, const dir_params *p, float *d_field_out, RegPlan &pl)
 {
-    int rc = DIR_OK;
     // ---- validation ----
-    if (!d_static || !d_moving || !p || !d_field_out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
-    if (p->struct_size != (int32_t)sizeof(dir_params)) return DIR_EINVAL;
-    if (p->storage < kStoreF32 || p->storage > kStoreBF16) return DIR_EINVAL;
+    if (!d_static || !d_moving || !d_field_out) return DIR_EINVAL;
+    int rc = check_register_params(nx, ny, nz, p);
+    if (rc != DIR_OK) return rc;
     if (spacing_mm)
         for (int k = 0; k < 3; ++k)
             if (!(spacing_mm[k] > 0.0) || !isfinite(spacing_mm[k])) return DIR_EINVAL;
     const int variant = p->variant;
-    if (variant < kPassive || variant > kInverseConsistent) return DIR_EINVAL;
-    if (!(p->alpha > 0.0) || !isfinite(p->alpha) || !(p->sigma > 0.0) || !isfinite(p->sigma)) return DIR_EINVAL;
-    if (!(p->eps >= 0.0) || !isfinite(p->eps)) return DIR_EINVAL;
     const int L = p->levels;
-    if (L < 1 || L > DIR_MAX_LEVELS) return DIR_EINVAL;
     int64_t total_iters = 0;
-    for (int l = 0; l < L; ++l) {
-        if (p->iters[l] < 0) return DIR_EINVAL;
-        total_iters += p->iters[l];
-    }
+    for (int l = 0; l < L; ++l) total_iters += p->iters[l];
     const int R = resolve_radius(p->sigma, p->radius);
-    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
     const int K = p->compose_iters < 0 ? DIR_DEFAULT_COMPOSE_ITERS : p->compose_iters;
     const GaussTaps taps = make_taps(p->sigma, R);
     const float alpha2 = (float)(p->alpha * p->alpha);
@@ -683,28 +780,23 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     // ---- workspace ----
     Dims dims[DIR_MAX_LEVELS];
     dims[0] = Dims{nx, ny, nz};
-    size_t pyr = 0;
-    for (int k = 1; k < L; ++k) {
-        dims[k] = coarser(dims[k - 1]);
-        pyr += (size_t)dims[k].n();
+    for (int k = 1; k < L; ++k) dims[k] = coarser(dims[k - 1]);
+    const RegSizes z = register_sizes(nx, ny, nz, p);
+    if (z.pyr) {
+        DIR_TRY(h->pyr_s.ensure(z.pyr));
+        DIR_TRY(h->pyr_m.ensure(z.pyr));
     }
-    const size_t n0 = (size_t)dims[0].n();
-    const size_t es = storage_bytes(p->storage);  // bytes per stored value
-    if (L > 1) {
-        DIR_TRY(h->pyr_s.ensure(es * pyr));
-        DIR_TRY(h->pyr_m.ensure(es * pyr));
+    if (z.img0) {
+        DIR_TRY(h->img0_s.ensure(z.img0));
+        DIR_TRY(h->img0_m.ensure(z.img0));
     }
-    if (p->storage != kStoreF32) {
-        DIR_TRY(h->img0_s.ensure(es * n0));
-        DIR_TRY(h->img0_m.ensure(es * n0));
-    }
-    for (auto &f : h->field) DIR_TRY(f.ensure(es * 3 * n0));
-    for (int k = 0; k < L; ++k) {  // sum slots: the largest level count
-        rc = ensure_force_workspace(h, dims[k], variant, p->storage);
-        if (rc != DIR_OK) return rc;
-    }
-    DIR_TRY(h->history.ensure(sizeof(double) * 4 * (size_t)(total_iters > 0 ? total_iters : 1)));
-    DIR_TRY(h->state.ensure(sizeof(LevelState) * DIR_MAX_LEVELS));
+    DIR_TRY(h->field[0].ensure(z.field));
+    DIR_TRY(h->field[1].ensure(z.field));
+    if (z.img_a) DIR_TRY(h->img_a.ensure(z.img_a));
+    if (z.img_b) DIR_TRY(h->img_b.ensure(z.img_b));
+    DIR_TRY(h->partials.ensure(z.partials));
+    DIR_TRY(h->history.ensure(z.history));
+    DIR_TRY(h->state.ensure(z.state));
 
     pl.S = d_static;
     pl.M = d_moving;

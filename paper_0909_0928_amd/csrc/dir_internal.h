@@ -150,3 +150,13 @@ hipError_t launch_zero(Ctx &c, void *p, int64_t n, int st);
 hipError_t launch_convert(Ctx &c, const void *in, int in_st, void *out, int out_st, int64_t n);
 
 }  // namespace dir
+
+// Workspace accounting of a handle (abi.hip), used by the request pool.
+#include "demons.h"
+namespace dir {
+size_t workspace_now(const dir_handle *h);
+// Bytes the handle holds after a registration with these parameters
+// (each buffer grows to the larger of its current and needed size).
+size_t workspace_after(const dir_handle *h, int32_t nx, int32_t ny, int32_t nz, const dir_params *p);
+void workspace_release(dir_handle *h);  // free the workspace (no registration may be in flight)
+}  // namespace dir

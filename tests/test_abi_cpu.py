@@ -70,3 +70,25 @@ def test_struct_layouts_match_the_header(tmp_path):
     sizes = [int(s) for s in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert sizes == [ctypes.sizeof(B.dir_params), ctypes.sizeof(B.dir_stats), B.dir_params.iters.offset,
                      B.dir_params.eps.offset, B.dir_stats.history.offset, B.dir_stats.history_len.offset]
+
+
+def test_workspace_bytes_accounting():
+    """dir_workspace_bytes follows the buffers a registration allocates."""
+    from paper_0909_0928_amd import binding as B
+    shape = (32, 64, 64)
+    n = 32 * 64 * 64
+    one = lambda v, st: B.dir_workspace_bytes(shape, B.make_params(v, [50], sigma=1.0, storage=st))
+    # 16-bit storage: two fields of 3N values at 2 B instead of 4, plus 2 B copies of S and M
+    assert one("passive", "f32") - one("passive", "f16") == 2 * 3 * n * 2 - 2 * 2 * n
+    assert one("passive", "bf16") == one("passive", "f16")
+    # active keeps D (storage format); IC keeps D and P (FP32)
+    assert one("active", "f32") - one("passive", "f32") == 4 * n
+    assert one("inverse_consistent", "f32") - one("passive", "f32") == 8 * n
+    assert one("inverse_consistent", "f16") - one("passive", "f16") == 2 * n + 4 * n
+    # pyramid levels: S and M at every coarser level (ceil halving)
+    two = B.dir_workspace_bytes(shape, B.make_params("passive", [25, 25], sigma=1.0))
+    assert two - one("passive", "f32") == 2 * 4 * (16 * 32 * 32)
+    bad = B.make_params("passive", [5], sigma=1.0)
+    bad.sigma = -1.0
+    with pytest.raises(B.DemonsError):
+        B.dir_workspace_bytes(shape, bad)
