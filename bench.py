@@ -206,6 +206,146 @@ def storage_study(args):
                       "sigma": SIGMA, "radius": RADIUS, "max_u": STUDY_MAX_U, "rows": rows}))
 
 
+def _phantom_job(job):
+    """(shape xyz, seed, max_u) -> FP32 static and moving (worker process)."""
+    from paper_0909_0928_amd import phantom as P
+    shape, seed, max_u = job
+    ph = P.make_phantom(shape, seed=seed, max_u=max_u, spacing_mm=SPACING)
+    return ph.static.astype(np.float32), ph.moving.astype(np.float32)
+
+
+def _phantoms(jobs):
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(len(jobs), 16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_phantom_job, jobs))
+
+
+def batch32(args):
+    """32 independent inverse-consistent pairs of uneven sizes (x, y uniform in
+    128..256, z in 64..128; seeds 1000 + i), 3 levels, 100/50/25 iterations:
+    all submitted at once to a request pool, against one after another."""
+    import torch
+    from paper_0909_0928_amd import binding as B
+    rng = np.random.default_rng(1000)
+    shapes = [(int(rng.integers(128, 257)), int(rng.integers(128, 257)), int(rng.integers(64, 129)))
+              for _ in range(32)]
+    print(f"[batch] building 32 phantoms", file=sys.stderr, flush=True)
+    pairs = _phantoms([(sh, 1000 + i, MAX_U) for i, sh in enumerate(shapes)])
+    dev = torch.device("cuda:0")
+    S = [torch.from_numpy(a).to(dev) for a, _ in pairs]
+    M = [torch.from_numpy(b).to(dev) for _, b in pairs]
+    outs = [torch.empty((3,) + tuple(x.shape), dtype=torch.float32, device=dev) for x in S]
+    params = B.make_params("inverse_consistent", ITERS, sigma=SIGMA, radius=RADIUS, storage=args.storage)
+    vi = sum(voxel_iters(sh, ITERS) for sh in shapes)
+    res = {"workload": "32 inverse-consistent pairs, x,y in 128..256, z in 64..128, 3 levels 100/50/25, sigma 1.5",
+           "storage": args.storage, "voxel_iters": vi}
+    with B.Pool(slots=args.slots, max_bytes=0) as pool:
+        def run_pool():
+            ts = [pool.submit(a, b, params, field_out=o) for a, b, o in zip(S, M, outs)]
+            for t in ts:
+                pool.wait(t)
+        run_pool()                                   # warm-up: workspaces grow to their sizes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_pool()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res.update({"pool_slots": args.slots, "pool_seconds": dt, "pool_voxel_iter_per_s": vi / dt,
+                    "pool_peak_running": pool.stats()["peak_running"]})
+    h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))
+    for a, b, o in zip(S, M, outs):
+        B.dir_register(h, a, b, params, field_out=o, history=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b, o in zip(S, M, outs):
+        B.dir_register(h, a, b, params, field_out=o, history=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    B.dir_destroy(h)
+    res.update({"sequential_seconds": dt, "sequential_voxel_iter_per_s": vi / dt, "speedup": dt / res["pool_seconds"]})
+    print(json.dumps(res))
+
+
+SERVE_SIZES = [((128, 128, 64), 0.3), ((256, 256, 100), 0.4), ((384, 384, 128), 0.2), ((512, 512, 160), 0.1)]
+
+
+def serve(args):
+    """Poisson arrivals (rate args.rate per second, arrival seed 5) of requests
+    with sizes drawn from SERVE_SIZES and the six settings uniformly, served by
+    a request pool; latency = completion seen by the loop - arrival."""
+    import torch
+    from paper_0909_0928_amd import binding as B
+    print(f"[serve] building {len(SERVE_SIZES)} phantom pairs", file=sys.stderr, flush=True)
+    pairs = _phantoms([(sh, 5000 + i, MAX_U) for i, (sh, _) in enumerate(SERVE_SIZES)])
+    dev = torch.device("cuda:0")
+    S = [torch.from_numpy(a).to(dev) for a, _ in pairs]
+    M = [torch.from_numpy(b).to(dev) for _, b in pairs]
+    rng = np.random.default_rng(5)
+    n = args.requests
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, size=n))
+    size_idx = rng.choice(len(SERVE_SIZES), size=n, p=[pr for _, pr in SERVE_SIZES])
+    setting_idx = rng.integers(0, len(SETTINGS), size=n)
+    params = [[B.make_params(var, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha, storage=args.storage)
+               for _, var, alpha in SETTINGS] for _ in SERVE_SIZES]
+    budget = int(args.budget_gib * 2 ** 30)
+    lat = np.zeros(n)
+    done_at = np.zeros(n)
+    checked = []
+    with B.Pool(slots=args.slots, max_bytes=budget) as pool:
+        # warm-up: every size and setting once, so workspaces exist
+        for k in range(len(SERVE_SIZES)):
+            for j in range(len(SETTINGS)):
+                pool.wait(pool.submit(S[k], M[k], params[k][j]))
+        torch.cuda.synchronize()
+        print(f"[serve] {n} requests at {args.rate}/s", file=sys.stderr, flush=True)
+        inflight = {}
+        nxt = 0
+        t0 = time.perf_counter()
+        while nxt < n or inflight:
+            now = time.perf_counter() - t0
+            while nxt < n and arrivals[nxt] <= now:
+                k, j = size_idx[nxt], setting_idx[nxt]
+                inflight[pool.submit(S[k], M[k], params[k][j])] = nxt
+                nxt += 1
+            for t in list(inflight):
+                r = pool.poll(t)
+                if r is not None:
+                    i = inflight.pop(t)
+                    done_at[i] = time.perf_counter() - t0
+                    lat[i] = done_at[i] - arrivals[i]
+                    if len(checked) < 12 and i % 50 == 0:
+                        checked.append((i, r[0].clone()))
+            if nxt < n and not inflight:
+                time.sleep(max(0.0, min(arrivals[nxt] - (time.perf_counter() - t0), 0.002)))
+            else:
+                time.sleep(0.0002)
+            if nxt and nxt % 100 == 0 and not inflight:
+                print(f"[serve] {nxt} submitted", file=sys.stderr, flush=True)
+        elapsed = time.perf_counter() - t0
+        pst = pool.stats()
+    # each checked result equals the same registration run alone
+    h = B.dir_create(0)
+    same = True
+    for i, f in checked:
+        k, j = size_idx[i], setting_idx[i]
+        g, _ = B.dir_register(h, S[k], M[k], params[k][j])
+        same = same and bool(torch.equal(f, g))
+    B.dir_destroy(h)
+    vi = sum(voxel_iters(SERVE_SIZES[k][0], ITERS) for k in size_idx)
+    per_size = {f"{sh[0]}x{sh[1]}x{sh[2]}": float(np.median(lat[size_idx == k]) * 1e3)
+                for k, (sh, _) in enumerate(SERVE_SIZES) if np.any(size_idx == k)}
+    print(json.dumps({"workload": f"Poisson arrivals at {args.rate}/s, {n} requests, sizes 128x128x64 / 256x256x100 / "
+                                  f"384x384x128 / 512x512x160 with p 0.3/0.4/0.2/0.1, six settings uniformly, "
+                                  f"3 levels 100/50/25",
+                      "storage": args.storage, "slots": args.slots, "budget_bytes": budget,
+                      "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                     "p99": float(np.percentile(lat, 99) * 1e3),
+                                     "max": float(lat.max() * 1e3), "per_size_p50": per_size},
+                      "seconds": elapsed, "voxel_iter_per_s": vi / elapsed, "offered_voxel_iters": vi,
+                      "pool": pst, "results_equal_alone": same, "checked": len(checked)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +361,13 @@ def main():
     ap.add_argument("--study-storage", action="store_true",
                     help="instead: the 512x512x160 reduced-precision study (F32, F16, BF16; passive and IC)")
     ap.add_argument("--with-oracle", action="store_true", help="study: also run the FP64 oracle on the FP32 inputs")
+    ap.add_argument("--batch32", action="store_true",
+                    help="instead: 32 uneven inverse-consistent pairs through a request pool vs sequentially")
+    ap.add_argument("--serve", action="store_true", help="instead: Poisson-arrival serving through a request pool")
+    ap.add_argument("--rate", type=float, default=4.0, help="serve: arrivals per second")
+    ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")
+    ap.add_argument("--slots", type=int, default=8, help="batch32/serve: pool slots (streams)")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: pool workspace budget in GiB")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain device copies of known size (counter calibration)")
     args = ap.parse_args()
@@ -232,6 +379,12 @@ def main():
     import torch
     if args.study_storage:
         storage_study(args)
+        return
+    if args.batch32:
+        batch32(args)
+        return
+    if args.serve:
+        serve(args)
         return
     if args.copy_probe:
         n = 256 * 1024 * 1024 // 4
