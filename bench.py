@@ -206,6 +206,82 @@ def storage_study(args):
                       "sigma": SIGMA, "radius": RADIUS, "max_u": STUDY_MAX_U, "rows": rows}))
 
 
+def _study_pair(torch, B, P):
+    ph = P.make_phantom(SHAPE, seed=SEED, max_u=MAX_U, spacing_mm=SPACING)
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(ph.static.astype(np.float32)).to(dev)
+    M = torch.from_numpy(ph.moving.astype(np.float32)).to(dev)
+    rng = np.random.default_rng(0)
+    body = np.flatnonzero(ph.body.ravel())
+    sample = np.sort(rng.choice(body, size=min(100000, body.size), replace=False))
+    z, y, x = np.unravel_index(sample, ph.static.shape)
+    vt, _ = ph.ground_truth(x.astype(float), y.astype(float), z.astype(float))
+    sdev = torch.from_numpy(sample).to(dev)
+
+    def gt(field):
+        d = field.view(3, -1)[:, sdev].cpu().numpy().astype(np.float64) - vt
+        e = np.sqrt((d ** 2).sum(axis=0))
+        mm = np.sqrt((d[0] * SPACING[0]) ** 2 + (d[1] * SPACING[1]) ** 2 + (d[2] * SPACING[2]) ** 2)
+        return {"mean_vox": float(e.mean()), "p95_vox": float(np.percentile(e, 95)), "mean_mm": float(mm.mean())}
+
+    return S, M, gt
+
+
+def convergence_study(args):
+    """Analogue of the paper's convergence figure (Sec 3.2): passive force on
+    the 256x256x100 pair, 100 and 50 iterations on the coarse levels and up
+    to 200 at full resolution.  Reports the relative norm l(n) and the MSE per
+    full-resolution iteration (the registration's history), where the
+    stopping rule with eps = 1e-4 stops the level, and the correlation
+    coefficient and ground-truth error after every 10 full-resolution
+    iterations."""
+    import torch
+    from paper_0909_0928_amd import binding as B
+    from paper_0909_0928_amd import phantom as P
+    S, M, gt = _study_pair(torch, B, P)
+    h = B.dir_create(0, stream=torch.cuda.Stream())
+    cap = 200
+    f, st = B.dir_register(h, S, M, B.make_params("passive", [100, 50, cap], sigma=SIGMA, radius=RADIUS))
+    fine = st["history"][150:]
+    f_eps, st_eps = B.dir_register(h, S, M, B.make_params("passive", [100, 50, cap], sigma=SIGMA, radius=RADIUS,
+                                                          eps=1e-4))
+    checkpoints = []
+    for n in range(0, cap + 1, 10):
+        f, _ = B.dir_register(h, S, M, B.make_params("passive", [100, 50, n], sigma=SIGMA, radius=RADIUS))
+        mse, cc = B.dir_similarity(h, S, M, f)
+        checkpoints.append({"fine_iters": n, "cc": cc, "mse": mse, "gt": gt(f)})
+        print(json.dumps(checkpoints[-1]), file=sys.stderr, flush=True)
+    mse0, cc0 = B.dir_similarity(h, S, M, None)
+    B.dir_destroy(h)
+    print(json.dumps({"study": "convergence", "workload": "256x256x100 pair, passive, 100/50/<=200 iterations",
+                      "undeformed": {"mse": mse0, "cc": cc0},
+                      "stopping_rule_eps_1e-4": {"iters_run": st_eps["iters_run"],
+                                                 "relnorm_final": st_eps["relnorm_final"]},
+                      "fine_history": [{"n": i, "sum_dr": e[0], "sum_v": e[1], "mse": e[2], "l": e[3]}
+                                       for i, e in enumerate(fine)],
+                      "checkpoints": checkpoints}))
+
+
+def alpha_study(args):
+    """Analogue of the paper's study of the normalisation factor (Sec 3.2):
+    ground-truth error of the 256x256x100 pair registered with alpha from 0.1
+    to 5 for the alpha-normalised passive force and Eq 5 (double force)."""
+    import torch
+    from paper_0909_0928_amd import binding as B
+    from paper_0909_0928_amd import phantom as P
+    S, M, gt = _study_pair(torch, B, P)
+    h = B.dir_create(0, stream=torch.cuda.Stream())
+    rows = []
+    for variant in ("passive", "double"):
+        for alpha in (0.1, 0.2, 0.4, 0.7, 1.0, 1.5, 2.0, 3.0, 5.0):
+            f, st = B.dir_register(h, S, M, B.make_params(variant, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha))
+            mse, cc = B.dir_similarity(h, S, M, f)
+            rows.append({"variant": variant, "alpha": alpha, "gt": gt(f), "cc": cc, "mse": mse})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    B.dir_destroy(h)
+    print(json.dumps({"study": "alpha", "workload": "256x256x100 pair, 3 levels 100/50/25", "rows": rows}))
+
+
 def _phantom_job(job):
     """(shape xyz, seed, max_u) -> FP32 static and moving (worker process)."""
     from paper_0909_0928_amd import phantom as P
@@ -361,6 +437,10 @@ def main():
     ap.add_argument("--study-storage", action="store_true",
                     help="instead: the 512x512x160 reduced-precision study (F32, F16, BF16; passive and IC)")
     ap.add_argument("--with-oracle", action="store_true", help="study: also run the FP64 oracle on the FP32 inputs")
+    ap.add_argument("--study-convergence", action="store_true",
+                    help="instead: relative norm, MSE, CC and ground-truth error against iterations (passive)")
+    ap.add_argument("--study-alpha", action="store_true",
+                    help="instead: ground-truth error against the normalisation factor alpha")
     ap.add_argument("--batch32", action="store_true",
                     help="instead: 32 uneven inverse-consistent pairs through a request pool vs sequentially")
     ap.add_argument("--serve", action="store_true", help="instead: Poisson-arrival serving through a request pool")
@@ -382,6 +462,12 @@ def main():
         return
     if args.batch32:
         batch32(args)
+        return
+    if args.study_convergence:
+        convergence_study(args)
+        return
+    if args.study_alpha:
+        alpha_study(args)
         return
     if args.serve:
         serve(args)

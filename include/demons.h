@@ -273,6 +273,15 @@ int32_t dir_pool_wait(dir_pool *p, int64_t ticket, dir_stats *stats);
 int32_t dir_pool_stats(const dir_pool *p, uint64_t *held_bytes_now, uint64_t *peak_bytes, int32_t *peak_running,
                        int32_t *queued_now);
 
+/* How well a field registers the pair, the two measures the paper follows
+ * over the iterations (Sec 3.2): *mse, the mean of (Im - S)^2, and *cc, the
+ * Pearson correlation coefficient of Im and S over all voxels, with
+ * Im(x) = M(x - v(x)) sampled in FP64 and every sum in FP64 (NaN when either
+ * image is constant).  d_field: 3 planes, or NULL for the undeformed M.
+ * Either output may be NULL.  Blocks. */
+int32_t dir_similarity(dir_handle *h, const float *d_static, const float *d_moving, const float *d_field, int32_t nx,
+                       int32_t ny, int32_t nz, double *mse, double *cc);
+
 /* Per-kernel device timing with HIP events on the handle's stream.
  * Kernels are numbered 0 .. dir_timing_count()-1; dir_timing_name(k) gives
  * the kernel's name (NULL if k is out of range).

@@ -82,6 +82,7 @@ def lib():
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.dir_wait.argtypes = [vp, vp]
         L.dir_set_graphs.argtypes = [vp, i32]
+        L.dir_similarity.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
         u64, i64 = ctypes.c_uint64, ctypes.c_int64
         L.dir_workspace_bytes.argtypes = [i32, i32, i32, vp, ctypes.POINTER(u64)]
         L.dir_pool_create.argtypes = [ctypes.POINTER(vp), i32, i32, u64]
@@ -101,7 +102,7 @@ def lib():
         L.dir_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
-                     "dir_register_async", "dir_wait", "dir_set_graphs", "dir_step_stored",
+                     "dir_register_async", "dir_wait", "dir_set_graphs", "dir_step_stored", "dir_similarity",
                      "dir_workspace_bytes", "dir_pool_create", "dir_pool_destroy", "dir_pool_submit",
                      "dir_pool_progress", "dir_pool_poll", "dir_pool_wait", "dir_pool_stats",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
@@ -401,6 +402,18 @@ def dir_step_stored(h, storage, variant, alpha, static, moving, field, sigma, ra
     _check(lib().dir_step_stored(h.ptr, st, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
                                  *_dims(static), float(sigma), int(radius), _ptr(out), sums), "dir_step_stored")
     return out, tuple(sums)
+
+
+def dir_similarity(h, static, moving, field=None):
+    """(mse, cc) of static and moving deformed by field (None: undeformed)."""
+    _dev_f32(static, "static", 3)
+    _dev_f32(moving, "moving", 3)
+    if field is not None:
+        _dev_f32(field, "field", 4)
+    mse, cc = ctypes.c_double(), ctypes.c_double()
+    _check(lib().dir_similarity(h.ptr, _ptr(static), _ptr(moving), _ptr(field) if field is not None else None,
+                                *_dims(static), ctypes.byref(mse), ctypes.byref(cc)), "dir_similarity")
+    return mse.value, cc.value
 
 
 def dir_compose(h, half, K=-1, out=None):

@@ -20,7 +20,7 @@ thread_local std::string g_last_error;
 
 const char *const kKernelNames[K_COUNT] = {
     "force", "warp", "warp_pair", "smooth_yz", "smooth_x", "finalize", "level_reset",
-    "restrict", "prolong", "gradient", "compose", "fill", "convert",
+    "restrict", "prolong", "gradient", "compose", "fill", "convert", "similarity",
 };
 
 // Device buffer that only grows.
@@ -611,6 +611,31 @@ int32_t dir_step(dir_handle *h, int32_t variant, double alpha, const float *d_st
     if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
     const GaussTaps taps = make_taps(sigma, R);
     return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, &taps, d_field_out, sums);
+}
+
+int32_t dir_similarity(dir_handle *h, const float *d_static, const float *d_moving, const float *d_field, int32_t nx,
+                       int32_t ny, int32_t nz, double *mse, double *cc)
+{
+    int rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    if (!d_static || !d_moving || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
+    const Dims d{nx, ny, nz};
+    DIR_TRY(h->partials.ensure(sizeof(double) * 6 * (size_t)similarity_blocks(d)));
+    DIR_TRY(h->history.ensure(sizeof(double) * 6));
+    Ctx c{h->stream, &h->timer};
+    DIR_TRY(launch_similarity(c, d_moving, d_static, d_field, d, h->partials.as<double>(), h->history.as<double>()));
+    rc = finish(h);
+    if (rc != DIR_OK) return rc;
+    double e[6];
+    rc = copy_to_host(h, e, h->history.p, sizeof e);
+    if (rc != DIR_OK) return rc;
+    const double n = (double)d.n();
+    if (mse) *mse = e[5] / n;
+    if (cc) {
+        const double cov = n * e[4] - e[0] * e[1], vs = n * e[2] - e[0] * e[0], vm = n * e[3] - e[1] * e[1];
+        *cc = (vs > 0.0 && vm > 0.0) ? cov / sqrt(vs * vm) : __builtin_nan("");
+    }
+    return DIR_OK;
 }
 
 int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double alpha, const float *d_static,

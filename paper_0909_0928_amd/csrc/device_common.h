@@ -28,36 +28,39 @@ __device__ __forceinline__ int clampi(int i, int n) { return min(max(i, 0), n - 
 //
 // The sample position is x - v with x an integer grid index.  Forming x - v
 // in FP32 would round it to the ulp of x (7.6e-6 voxel at x = 100); instead v
-// is split into floor(v) (exact) and r = v - floor(v) (exact for |v| < 2^23):
-// the cell index is integer arithmetic, w0 = r is exact, and t = 1 - r is
-// exact in FP64 (one rounding of at most 2^-25 in FP32).  v is first limited
-// to +-2^20 (NaN becomes -2^20), which keeps every index inside the grid.
+// is split into floor(v) (exact) and the fraction r = v - floor(v), formed in
+// FP64, where it is exact for every FP32 v (in FP32 it is not: for -1/2 < v
+// < 0, r = 1 + v lies in a coarser binade than v).  The cell index is then
+// integer arithmetic and the weight w0 = r is exact; the FP32 t = 1 - r is
+// rounded once.  v is first limited to +-2^20 (NaN becomes -2^20), which
+// keeps every index inside the grid.
 struct Axis {
     int i0, i1;
-    float t, w0;
+    float t;
+    double w0;
 };
 
 __device__ __forceinline__ Axis axis_disp(int x, float v, int n)
 {
     v = fminf(fmaxf(v, -1048576.0f), 1048576.0f);
     const float fv = floorf(v);
-    const float r = v - fv;
+    const double r = (double)v - (double)fv;  // exact
     int i = x - (int)fv;  // p = x - v = i - r
     Axis a;
     a.t = 0.0f;
-    a.w0 = 1.0f;
-    if (r > 0.0f) {
+    a.w0 = 1.0;
+    if (r > 0.0) {
         i -= 1;
-        a.t = 1.0f - r;
+        a.t = (float)(1.0 - r);
         a.w0 = r;
     }
     if (i < 0 || i > n - 1) {  // outside: clamp onto the border sample
         i = i < 0 ? 0 : n - 1;
         a.t = 0.0f;
-        a.w0 = 1.0f;
+        a.w0 = 1.0;
     } else if (i == n - 1) {   // p in (n-1, n) would need the next cell: clamp
         a.t = 0.0f;
-        a.w0 = 1.0f;
+        a.w0 = 1.0;
     }
     a.i0 = i;
     a.i1 = min(i + 1, n - 1);
@@ -72,14 +75,14 @@ __device__ __forceinline__ Axis axis_coord(float p, int n)
     a.i0 = min((int)p, n - 1);  // p >= 0, so truncation is floor
     a.i1 = min(a.i0 + 1, n - 1);
     a.t = p - (float)a.i0;      // exact: p carries few fraction bits
-    a.w0 = 1.0f - a.t;
+    a.w0 = 1.0 - (double)a.t;
     return a;
 }
 
 struct Cell {
     int o000, o100, o010, o110, o001, o101, o011, o111;
     float tx, ty, tz;     // FP32 fractional positions
-    float wx, wy, wz;     // exact weights of the lower index
+    double wx, wy, wz;    // exact weights of the lower index
 };
 
 __device__ __forceinline__ Cell make_cell_axes(const Axis &ax, const Axis &ay, const Axis &az, int nx, int ny)
@@ -227,31 +230,31 @@ struct StBF16 {  // bfloat16: the upper half of a binary32
 struct BCell {
     unsigned o;
     unsigned dx, dy, dz;
-    float wx, wy, wz;
+    double wx, wy, wz;
 };
 
 struct AxisB {
     int i;
     bool step;
-    float w0;
+    double w0;
 };
 
 __device__ __forceinline__ AxisB axis_b(int x, float v, int n)
 {
     v = fminf(fmaxf(v, -1048576.0f), 1048576.0f);  // NaN -> -2^20; keeps indices in range
     const float fv = floorf(v);
-    const float r = v - fv;                          // exact
+    const double r = (double)v - (double)fv;         // exact (see axis_disp)
     int i = x - (int)fv;                             // p = x - v = i - r
     AxisB a;
-    a.w0 = 1.0f;
-    if (r > 0.0f) {
+    a.w0 = 1.0;
+    if (r > 0.0) {
         i -= 1;
         a.w0 = r;
     }
     a.step = i >= 0 && i <= n - 2;
     if (!a.step) {  // clamped onto the border sample (or the last sample exactly)
         i = min(max(i, 0), n - 1);
-        a.w0 = 1.0f;
+        a.w0 = 1.0;
     }
     a.i = i;
     return a;
@@ -296,18 +299,19 @@ __device__ __forceinline__ void bsample3(__amdgpu_buffer_rsrc_t I, const BCell &
                                          float &s1, float &s2)
 {
     const unsigned o = c.o, oy = o + c.dy, oz = o + c.dz, oyz = oz + c.dy;
+    const float wx = (float)c.wx, wy = (float)c.wy, wz = (float)c.wz;
     float r[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const unsigned so = (unsigned)k * plane;
         const float b00 = St::load(I, o + c.dx, so), b10 = St::load(I, oy + c.dx, so);
         const float b01 = St::load(I, oz + c.dx, so), b11 = St::load(I, oyz + c.dx, so);
-        const float c00 = fmaf(c.wx, St::load(I, o, so) - b00, b00);
-        const float c10 = fmaf(c.wx, St::load(I, oy, so) - b10, b10);
-        const float c01 = fmaf(c.wx, St::load(I, oz, so) - b01, b01);
-        const float c11 = fmaf(c.wx, St::load(I, oyz, so) - b11, b11);
-        const float d0 = fmaf(c.wy, c00 - c10, c10), d1 = fmaf(c.wy, c01 - c11, c11);
-        r[k] = fmaf(c.wz, d0 - d1, d1);
+        const float c00 = fmaf(wx, St::load(I, o, so) - b00, b00);
+        const float c10 = fmaf(wx, St::load(I, oy, so) - b10, b10);
+        const float c01 = fmaf(wx, St::load(I, oz, so) - b01, b01);
+        const float c11 = fmaf(wx, St::load(I, oyz, so) - b11, b11);
+        const float d0 = fmaf(wy, c00 - c10, c10), d1 = fmaf(wy, c01 - c11, c11);
+        r[k] = fmaf(wz, d0 - d1, d1);
     }
     s0 = r[0];
     s1 = r[1];
@@ -402,6 +406,29 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, int 
     }
 }
 
+
+// Fixed-order sum of K doubles over a 256-thread workgroup (result in
+// thread 0): xor shuffles within each wavefront, then the four wavefront
+// sums in order.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], int tid)
+{
+    __shared__ double red[K][kBlockX * kBlockY / 64];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k][wave] = v[k];
+    __syncthreads();
+    if (tid == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            v[k] = red[k][0];
+            for (int w = 1; w < kBlockX * kBlockY / 64; ++w) v[k] += red[k][w];
+        }
+}
 
 // Reduction of the force kernel's per-workgroup sums (slots s1[nb], s2[nb],
 // sse[nb]) by one 256-thread workgroup: strided partial sums per thread, then

@@ -36,6 +36,7 @@ enum KernelId {
     K_COMPOSE,
     K_FILL,
     K_CONVERT,       // storage-format conversion (reduced-precision registrations)
+    K_SIMILARITY,    // intensity error and correlation coefficient (dir_similarity)
     K_COUNT
 };
 
@@ -148,6 +149,10 @@ hipError_t launch_level_reset(Ctx &c, LevelState *st);
 hipError_t launch_compose(Ctx &c, const void *h, int h_st, Dims d, int K, float *out);
 hipError_t launch_zero(Ctx &c, void *p, int64_t n, int st);
 hipError_t launch_convert(Ctx &c, const void *in, int in_st, void *out, int out_st, int64_t n);
+int64_t similarity_blocks(Dims d);
+// Six FP64 sums (S, Im, S^2, Im^2, S Im, (Im - S)^2) into out[0..5]; v may be NULL.
+hipError_t launch_similarity(Ctx &c, const float *M, const float *S, const float *v, Dims d, double *partials,
+                             double *out);
 
 }  // namespace dir
 

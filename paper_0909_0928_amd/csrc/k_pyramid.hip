@@ -172,6 +172,57 @@ __global__ __launch_bounds__(256) void k_compose(const void *__restrict__ h, int
     bstore(O, 2.0f * az, o, 8u * N);
 }
 
+// Similarity of S and the deformed M (Sec 3.2 follows registrations by the
+// correlation coefficient and the intensity error): per workgroup the FP64
+// sums of S, Im, S^2, Im^2, S Im and (Im - S)^2, Im = M(x - v) sampled in FP64;
+// the slots (kSimSums arrays of nb) are added up in order by k_similarity_sum.
+constexpr int kSimSums = 6;
+
+__global__ __launch_bounds__(256) void k_similarity(const float *__restrict__ M, const float *__restrict__ S,
+                                                    const float *__restrict__ v, int nx, int ny, int nz,
+                                                    double *__restrict__ partials, int gx, int gy)
+{
+    const Tile t = decode_tile(gx, gy);
+    const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
+    double acc[kSimSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (x < nx && y < ny) {
+        const unsigned nbytes = 4u * (unsigned)nx * (unsigned)ny * (unsigned)nz;
+        const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, nbytes), rS = make_rsrc(S, nbytes);
+        const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
+        float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+        if (v) {
+            const __amdgpu_buffer_rsrc_t rv = make_rsrc(v, 3u * nbytes);
+            vx = bload(rv, o, 0);
+            vy = bload(rv, o, nbytes);
+            vz = bload(rv, o, 2u * nbytes);
+        }
+        const double im = bsample64(rM, bcell_disp(x, y, z, vx, vy, vz, nx, ny, nz));
+        const double s = (double)bload(rS, o, 0);
+        acc[0] = s;
+        acc[1] = im;
+        acc[2] = s * s;
+        acc[3] = im * im;
+        acc[4] = s * im;
+        acc[5] = (im - s) * (im - s);
+    }
+    const int tid = threadIdx.x + kBlockX * threadIdx.y;
+    block_sum(acc, tid);
+    if (tid == 0)
+        for (int k = 0; k < kSimSums; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = acc[k];
+}
+
+__global__ __launch_bounds__(256) void k_similarity_sum(const double *__restrict__ partials, int nb,
+                                                        double *__restrict__ out)
+{
+    const int tid = threadIdx.x;
+    double acc[kSimSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = tid; b < nb; b += 256)
+        for (int k = 0; k < kSimSums; ++k) acc[k] += partials[(size_t)k * nb + b];
+    block_sum(acc, tid);
+    if (tid == 0)
+        for (int k = 0; k < kSimSums; ++k) out[k] = acc[k];
+}
+
 template <class St>
 __global__ __launch_bounds__(256) void k_zero(void *__restrict__ p, unsigned n)
 {
@@ -291,6 +342,22 @@ hipError_t launch_warp_pair(Ctx &c, const void *M, const void *S, const void *h,
             go(c, ev, k_warp_pair<St>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, h, d.nx, d.ny, d.nz, D,
                P, g.gx, g.gy, stop_at, n);
         });
+    });
+}
+
+int64_t similarity_blocks(Dims d) { return plane_grid(d).blocks; }
+
+hipError_t launch_similarity(Ctx &c, const float *M, const float *S, const float *v, Dims d, double *partials,
+                             double *out)
+{
+    const Grid2 g = plane_grid(d);
+    hipError_t e = timed(c, K_SIMILARITY, [&](const Ev &ev) {
+        go(c, ev, k_similarity, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, v, d.nx, d.ny, d.nz,
+           partials, g.gx, g.gy);
+    });
+    if (e != hipSuccess) return e;
+    return timed(c, K_SIMILARITY, [&](const Ev &ev) {
+        go(c, ev, k_similarity_sum, dim3(1), dim3(256), (const double *)partials, (int)g.blocks, out);
     });
 }
 

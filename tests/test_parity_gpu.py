@@ -115,6 +115,21 @@ def test_prolong(B, h, coarse, fine):
     assert rel(got, O.prolong(vc, fine)) < REL_TOL
 
 
+@pytest.mark.parametrize("shape3", [(11, 13, 17), (9, 33, 65), (3, 4, 530)])
+@pytest.mark.parametrize("with_field", [True, False])
+def test_similarity(B, h, shape3, with_field):
+    """MSE and correlation coefficient of S and M(x - v): the definitions on the
+    oracle's FP64 deformed image."""
+    S, M = _img(shape3, 60), f32(_img(shape3, 61) + 0.5 * _img(shape3, 60)).astype(np.float64)
+    v = _fld(shape3, 62, amp=3.0) if with_field else None
+    mse, cc = B.dir_similarity(h, dev(S), dev(M), dev(v) if with_field else None)
+    Im = O.warp(M, v) if with_field else M
+    assert abs(mse - ((Im - S) ** 2).mean()) <= 1e-9 * ((Im - S) ** 2).mean()
+    assert abs(cc - np.corrcoef(Im.ravel(), S.ravel())[0, 1]) <= 1e-9
+    same_mse, same_cc = B.dir_similarity(h, dev(S), dev(S), None)
+    assert same_mse == 0.0 and abs(same_cc - 1.0) <= 1e-12
+
+
 def _pair(shape3, seed, amp=2.0):
     """Phantom-like static/moving images and a moderate field, FP32-exact."""
     nz, ny, nx = shape3
