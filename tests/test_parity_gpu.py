@@ -184,6 +184,24 @@ def test_step_widest_radius(B, h, shape3, variant):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
 
+@pytest.mark.parametrize("variant", ALL)
+@pytest.mark.parametrize("shape3", [(12, 30, 41), (5, 9, 300)])
+def test_register_equals_iterated_step(B, h, variant, shape3):
+    """A one-level registration is bitwise the iteration of dir_step from a zero
+    field (and, for IC, its composition): the same kernels, launch
+    configurations and reduction order inside and outside a registration."""
+    S, M, _ = _pair(shape3, 70)
+    alpha = 0.4 if variant == "double" else 1.0
+    iters = 6
+    f, _ = B.dir_register(h, dev(S), dev(M), B.make_params(variant, [iters], sigma=1.5, radius=5, alpha=alpha))
+    v = torch.zeros((3,) + tuple(S.shape), dtype=torch.float32, device="cuda")
+    for _ in range(iters):
+        v, _ = B.dir_step(h, variant, alpha, dev(S), dev(M), v, 1.5, 5)
+    if variant == "inverse_consistent":
+        v = B.dir_compose(h, v)
+    assert torch.equal(f, v)
+
+
 @pytest.mark.parametrize("shape3", [(11, 13, 17), (9, 33, 65)])
 @pytest.mark.parametrize("K", [0, 1, 10])
 def test_compose(B, h, shape3, K):
@@ -352,9 +370,9 @@ def test_timing_per_level_and_unchanged_results(B, h):
     finally:
         B.dir_timing_enable(h, ())
     assert torch.equal(f0, f1)
-    for k in ("force", "smooth_yz", "warp"):
+    for k, counts in (("force", (10, 4, 6)), ("smooth_yz", (10, 4, 6)), ("warp", (10, 4, 6))):
         (ms, n), (ms0, n0), (ms1, n1) = reads[k]
-        assert (n, n0, n1) == (10, 4, 6), k
+        assert (n, n0, n1) == counts, k
         assert ms > 0 and ms0 > 0 and ms1 > 0 and abs(ms - ms0 - ms1) <= 1e-9 * max(ms, 1.0), k
     assert reads["restrict"][0][1] == 2 and reads["restrict"][2][1] == 2   # S and M into level 1
     assert reads["compose"][0] == (0.0, 0)                                   # not enabled
