@@ -92,3 +92,15 @@ def test_workspace_bytes_accounting():
     bad.sigma = -1.0
     with pytest.raises(B.DemonsError):
         B.dir_workspace_bytes(shape, bad)
+
+
+def test_size_limit_and_empty_volumes():
+    """Buffers are addressed with 32-bit byte ranges: a 3-component FP32 field
+    must stay below 4 GiB, so nx*ny*nz <= 357,913,941; empty volumes are
+    rejected."""
+    from paper_0909_0928_amd import binding as B
+    p = B.make_params("passive", [1], sigma=1.0)
+    assert B.dir_workspace_bytes((1, 1, 357913941), p) > 12 * 357913941
+    for shape in ((1, 1, 357913942), (1024, 1024, 342), (0, 4, 4), (4, 0, 4), (4, 4, 0), (4, -1, 4)):
+        with pytest.raises(B.DemonsError):
+            B.dir_workspace_bytes(shape, p)
