@@ -170,6 +170,14 @@ class Handle:
     def __exit__(self, *exc):
         dir_destroy(self)
 
+    def __del__(self):
+        try:
+            if self.ptr:
+                lib().dir_destroy(self.ptr)
+                self.ptr = ctypes.c_void_p()
+        except Exception:
+            pass
+
     @property
     def _as_param_(self):
         return self.ptr
@@ -529,3 +537,9 @@ class Pool:
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
