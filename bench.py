@@ -476,10 +476,16 @@ def main():
         n = 256 * 1024 * 1024 // 4
         a = torch.ones(n, device="cuda")
         b = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.copy_(a)
+        e0.record()
         for _ in range(5):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
+        rate = 2 * n * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 6,
+                          "copy_GBps": round(rate, 1)}))
         return
 
     from paper_0909_0928_amd import binding as B
