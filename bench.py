@@ -3,23 +3,25 @@
 
 Workload: a seeded synthetic 4DCT-shaped pair of 256x256x100 voxels
 (1.1 x 1.1 x 2.5 mm, max displacement 15 voxels), 3-level pyramid with
-100/50/25 iterations coarse to fine, Gaussian sigma 1.5 voxels (R = 5), and
+100/50/25 iterations coarse to fine, Gaussian sigma 1.5 voxels (R 5), and
 the six force settings: passive, active, double force, alpha-normalised
-passive (alpha = 0.4), inverse-consistent, and double force with alpha = 0.4.
-One step registers the pair once with each of the six; the six are enqueued
-with dir_register_async on six handles, each with its own stream, so they
-overlap on the device, and the step ends when all six are collected.
+passive (alpha 0.4), inverse-consistent, and double force with alpha 0.4.
+One step registers the pair once with each of the six, as one lockstep batch
+(dir_register_batch): every coarse-level iteration of the six runs as one
+pre-warp, one force and one smoothing launch, and the finest level runs
+registration by registration.
 
 Prints one JSON line:
   - value: voxel-iterations per second over the timed steps (no timing
     events inside them);
-  - latency_ms: per-registration latency with each registration run alone
-    (blocking dir_register, one after another), and the step (batch) latency;
+  - streams: the rate of the same steps with the six registrations enqueued
+    with dir_register_async on six handles, each with its own stream;
   - sequential: the rate of the same steps run one registration at a time;
+  - latency_ms: per-registration latency with each registration run alone
+    (blocking dir_register, one after another), and the step latency;
   - roofline: the kernel that takes the most device time, its algorithmic
     bytes per launch over its average launch time, from a separate pass of
-    sequential steps in which its launches carry dispatch-stamped HIP events
-    (each launch then runs alone on the device, as in a kernel trace);
+    batch steps in which its launches carry dispatch-stamped HIP events;
   - cpu_baseline: the FP64 CPU oracle on a bounded sample of the workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -80,12 +82,16 @@ def voxel_iters(shape, iters):
     return total
 
 
-def launch_units(kernel, shape, iters, n_ic, n_active_like, n_settings):
-    """Voxels processed by all launches of `kernel` in one step (for bytes)."""
+def launch_units(kernel, shape, iters, n_ic, n_active_like, n_settings, level=None):
+    """Voxels processed by all launches of `kernel` in one step (for bytes);
+    `level` (0 = finest) restricts them to one pyramid level."""
     dims = level_dims(shape, len(iters))
     per_reg = 0
     for k, it in enumerate(iters):
-        nx, ny, nz = dims[len(iters) - 1 - k]
+        lv = len(iters) - 1 - k
+        if level is not None and lv != level:
+            continue
+        nx, ny, nz = dims[lv]
         per_reg += nx * ny * nz * it
     if kernel in ("force", "smooth_yz"):
         return per_reg * n_settings
@@ -93,6 +99,8 @@ def launch_units(kernel, shape, iters, n_ic, n_active_like, n_settings):
         return per_reg * n_active_like
     if kernel == "warp_pair":
         return per_reg * n_ic
+    if kernel == "warp_mixed":
+        return None   # 24 or 28 bytes per voxel by registration
     return None
 
 
@@ -450,6 +458,9 @@ def main():
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: pool workspace budget in GiB")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain device copies of known size (counter calibration)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="batch steps and the roofline pass only (no stream or sequential comparison, no "
+                         "ground truth, no CPU baseline), so a kernel trace holds the launches the roofline times")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: independent registrations shard by pair, "
@@ -503,13 +514,20 @@ def main():
               for name, var, alpha in SETTINGS}
     es = STORAGE_BYTES[args.storage]
     torch.cuda.synchronize()
-    streams = [torch.cuda.Stream(device=dev) for _ in SETTINGS]       # default priority
+    plist = [params[name] for name, _, _ in SETTINGS]
+    hb = B.dir_create(0, stream=torch.cuda.Stream(device=dev))          # the batch steps (default priority)
+    streams = [torch.cuda.Stream(device=dev) for _ in SETTINGS]
     handles = [B.dir_create(0, stream=st) for st in streams]
     h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))           # sequential passes
     vi_reg = voxel_iters(SHAPE, ITERS)
+    compare = not args.profile_run
 
     def step():
-        """The six registrations, overlapped on the device."""
+        """The six registrations as one lockstep batch."""
+        B.dir_register_batch(hb, [S] * len(SETTINGS), [M] * len(SETTINGS), plist, field_outs=outs, history=False)
+
+    def step_streams():
+        """The six registrations overlapped on six streams."""
         for hh, (name, _, _), o in zip(handles, SETTINGS, outs):
             B.dir_register_async(hh, S, M, params[name], field_out=o, history=False)
         for hh in handles:
@@ -522,55 +540,69 @@ def main():
             if lat is not None:
                 lat.append((name, (time.perf_counter() - t0) * 1e3))
 
+    def timed_steps(fn, k):
+        ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            ts = time.perf_counter()
+            fn()
+            ms.append((time.perf_counter() - ts) * 1e3)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ms
+
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
-        step_sequential()
+        if compare:
+            step_streams()
+            step_sequential()
     torch.cuda.synchronize()
 
     # timed region: no timing events
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    step_ms = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        step()
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed, step_ms = timed_steps(step, args.steps)
     total_vi = vi_reg * len(SETTINGS) * args.steps
     value = total_vi / elapsed
 
-    # the same steps one registration at a time: per-registration latency
-    print(f"[bench] sequential {args.latency_steps} steps", file=sys.stderr, flush=True)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.latency_steps):
-        step_sequential(lat)
-    torch.cuda.synchronize()
-    seq_elapsed = time.perf_counter() - t0
-    lats = np.array([l for _, l in lat])
-    per_var = {name: float(np.median([l for n, l in lat if n == name])) for name, _, _ in SETTINGS}
+    streams_res = seq_res = None
+    lats, per_var = np.array([np.nan]), {}
+    if compare:
+        print(f"[bench] streams {args.steps} steps", file=sys.stderr, flush=True)
+        st_elapsed, _ = timed_steps(step_streams, args.steps)
+        streams_res = {"value": total_vi / st_elapsed, "ms_per_step": st_elapsed * 1e3 / args.steps,
+                       "steps": args.steps}
+        # the same steps one registration at a time: per-registration latency
+        print(f"[bench] sequential {args.latency_steps} steps", file=sys.stderr, flush=True)
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.latency_steps):
+            step_sequential(lat)
+        torch.cuda.synchronize()
+        seq_elapsed = time.perf_counter() - t0
+        lats = np.array([l for _, l in lat])
+        per_var = {name: float(np.median([l for n, l in lat if n == name])) for name, _, _ in SETTINGS}
+        seq_res = {"value": vi_reg * len(SETTINGS) * args.latency_steps / seq_elapsed,
+                   "ms_per_step": seq_elapsed * 1e3 / args.latency_steps, "steps": args.latency_steps}
 
-    # which kernel takes the most device time (one sequential step, all kernels timed)
+    # which kernel takes the most device time (one batch step, all kernels timed)
     names = B.dir_timing_names()
-    B.dir_timing_enable(h, names)
-    step_sequential()
-    per_kernel = {k: B.dir_timing_read(h, k) for k in names}
-    B.dir_timing_enable(h, ())
+    B.dir_timing_enable(hb, names)
+    step()
+    per_kernel = {k: B.dir_timing_read(hb, k) for k in names}
+    B.dir_timing_enable(hb, ())
     dominant = args.roofline_kernel or max(per_kernel, key=lambda k: per_kernel[k][0])
     print(f"[bench] per-kernel ms in one step: "
           + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in per_kernel.items() if v[1]), file=sys.stderr, flush=True)
 
     # roofline pass: events on the dominant kernel only
-    B.dir_timing_enable(h, [dominant])
+    B.dir_timing_enable(hb, [dominant])
     for _ in range(args.latency_steps):
-        step_sequential()
-    kern_ms, kern_launches = B.dir_timing_read(h, dominant)
-    fine_ms, fine_launches = B.dir_timing_read(h, dominant, level=0)
-    B.dir_timing_enable(h, ())
+        step()
+    kern_ms, kern_launches = B.dir_timing_read(hb, dominant)
+    levels = {lv: B.dir_timing_read(hb, dominant, level=lv) for lv in range(len(ITERS))}
+    B.dir_timing_enable(hb, ())
 
     # roofline of the dominant kernel: algorithmic bytes over its measured time
     n_ic = sum(1 for _, v, _ in SETTINGS if v == "inverse_consistent")
@@ -588,13 +620,19 @@ def main():
                 "avg_launch_us": kern_ms * 1e3 / kern_launches, "launches": kern_launches,
                 "algo_bytes_per_voxel": abpv,
                 "bytes_per_launch": bytes_total / kern_launches, "traffic_source": traffic_src,
-                "timed_in": f"{args.latency_steps} sequential steps after the timed region"}
-        if fine_launches:
-            fine_bytes = SHAPE[0] * SHAPE[1] * SHAPE[2] * abpv
-            fine_gbs = fine_bytes * fine_launches / (fine_ms * 1e-3) / 1e9
-            roof["finest_level"] = {"shape_xyz": list(SHAPE), "launches": fine_launches,
-                                    "avg_launch_us": fine_ms * 1e3 / fine_launches, "bytes_per_launch": fine_bytes,
-                                    "achieved": fine_gbs, "frac": fine_gbs / HBM_PEAK_GBS}
+                "timed_in": f"{args.latency_steps} batch steps after the timed region"}
+        per_level = []
+        for lv, (ms_l, n_l) in levels.items():
+            if not n_l:
+                continue
+            b_l = launch_units(dominant, SHAPE, ITERS, n_ic, n_act, len(SETTINGS), level=lv) * abpv * \
+                args.latency_steps
+            gbs = b_l / (ms_l * 1e-3) / 1e9
+            per_level.append({"level": lv, "shape_xyz": list(level_dims(SHAPE, len(ITERS))[lv]), "launches": n_l,
+                              "avg_launch_us": ms_l * 1e3 / n_l, "bytes_per_launch": b_l / n_l,
+                              "achieved": gbs, "frac": gbs / HBM_PEAK_GBS})
+        roof["per_level"] = per_level
+        roof["finest_level"] = next((e for e in per_level if e["level"] == 0), None)
 
     # ground-truth error of each setting on a body sample
     rng = np.random.default_rng(0)
@@ -603,18 +641,19 @@ def main():
     z, y, x = np.unravel_index(sample, ph.static.shape)
     vt, _ = ph.ground_truth(x.astype(float), y.astype(float), z.astype(float))
     gt = {}
-    for name, _, _ in ([] if args.no_gt else SETTINGS):
+    for name, _, _ in ([] if (args.no_gt or not compare) else SETTINGS):
         B.dir_register(h, S, M, params[name], field_out=outs[0], history=False)
         f = outs[0].view(3, -1)[:, torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
         d = f - vt
         mm = np.sqrt((d[0] * SPACING[0]) ** 2 + (d[1] * SPACING[1]) ** 2 + (d[2] * SPACING[2]) ** 2)
         gt[name] = {"mean_vox": float(np.sqrt((d ** 2).sum(axis=0)).mean()), "mean_mm": float(mm.mean())}
     B.dir_destroy(h)
+    B.dir_destroy(hb)
     for hh in handles:
         B.dir_destroy(hh)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and compare:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(S64, M64)
 
@@ -623,14 +662,16 @@ def main():
         "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "storage": args.storage, "data": "synthetic",
         "config": {"workload": "256x256x100 synthetic 4DCT phantom pair, 3-level pyramid, 100/50/25 iterations "
-                               "coarse to fine, sigma 1.5 (R 5), six force settings per step",
+                               "coarse to fine, sigma 1.5 (R 5), six force settings per step as one "
+                               "lockstep batch",
                    "shape_xyz": list(SHAPE), "iters_coarse_to_fine": ITERS, "sigma": SIGMA, "radius": RADIUS,
                    "settings": [s[0] for s in SETTINGS], "voxel_iters_per_step": vi_reg * len(SETTINGS)},
-        "latency_ms": {"p50": float(np.percentile(lats, 50)), "p99": float(np.percentile(lats, 99)),
+        "latency_ms": {"p50": float(np.percentile(lats, 50)) if compare else None,
+                       "p99": float(np.percentile(lats, 99)) if compare else None,
                        "per_setting_p50": per_var, "alone": True,
                        "step_p50": float(np.percentile(step_ms, 50)), "step_p99": float(np.percentile(step_ms, 99))},
-        "sequential": {"value": vi_reg * len(SETTINGS) * args.latency_steps / seq_elapsed,
-                       "ms_per_step": seq_elapsed * 1e3 / args.latency_steps, "steps": args.latency_steps},
+        "streams": streams_res,
+        "sequential": seq_res,
         "roofline": roof,
         "cpu_baseline": cpu,
         "gt_error": gt,

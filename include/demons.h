@@ -47,6 +47,7 @@ extern "C" {
 #define DIR_ABI_VERSION 1
 #define DIR_MAX_LEVELS 8
 #define DIR_MAX_RADIUS 16
+#define DIR_MAX_BATCH 8           /* registrations per dir_register_batch call */
 #define DIR_DEFAULT_COMPOSE_ITERS 10
 
 typedef enum {
@@ -240,6 +241,32 @@ int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, 
  * sizes and parameters; host-only, no device needed.  DIR_EINVAL for
  * parameters dir_register would reject. */
 int32_t dir_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const dir_params *params, uint64_t *bytes);
+
+/* Lockstep batch (the iteration of Sec 2.4 and the pyramid of Sec 2.3, run
+ * for several pairs at once): `count` (1..DIR_MAX_BATCH) registrations of
+ * volumes of one size, given as host arrays of device pointers d_static[r],
+ * d_moving[r] and d_field_out[r] and a host array params[r].  The
+ * registrations must agree in levels, iterations per level, sigma, radius
+ * and storage; variant, alpha, eps and compose_iters may differ.
+ *
+ * On a pyramid level whose images and fields, over all `count`
+ * registrations, fit the device's 256 MB last-level cache (about 8 stored
+ * values per voxel each), every iteration of all of them runs as one
+ * pre-warp launch (for the variants that have one), one force launch and one
+ * smoothing launch: the short, latency-bound launches of coarse levels then
+ * carry `count` times the work.  A larger level streams from HBM either way
+ * and runs registration by registration, so that each kernel finds the field
+ * the previous one wrote still in that cache.
+ *
+ * Each field, its iteration counts and its history are bitwise those
+ * dir_register computes alone.  Output fields must be distinct and must not
+ * overlap any input.  stats: NULL or an array of `count` (each with
+ * struct_size set); DIR_ENUMERIC if any registration's sums turn non-finite.
+ * The workspace holds `count` registrations' worth.  Blocks until complete. */
+int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_static,
+                           const float *const *d_moving, int32_t nx, int32_t ny, int32_t nz,
+                           const double *spacing_mm, const dir_params *params, float *const *d_field_out,
+                           dir_stats *stats);
 
 /* Request pool (serving).  A pool runs submitted registrations on `slots`
  * handles of its own, each with its own stream, so registrations that arrive

@@ -20,6 +20,7 @@ DIR_OK, DIR_EINVAL, DIR_ENOMEM, DIR_EDEVICE, DIR_ENUMERIC, DIR_EBUSY = 0, -1, -2
 DIR_PASSIVE, DIR_EVOLVED_PASSIVE, DIR_ACTIVE, DIR_DOUBLE, DIR_INVERSE_CONSISTENT = 0, 1, 2, 3, 4
 DIR_MAX_LEVELS = 8
 DIR_MAX_RADIUS = 16
+DIR_MAX_BATCH = 8
 DIR_STORE_F32, DIR_STORE_F16, DIR_STORE_BF16 = 0, 1, 2
 STORAGE = {"f32": DIR_STORE_F32, "f16": DIR_STORE_F16, "bf16": DIR_STORE_BF16}
 VARIANTS = {"passive": DIR_PASSIVE, "evolved": DIR_EVOLVED_PASSIVE, "active": DIR_ACTIVE, "double": DIR_DOUBLE,
@@ -80,6 +81,7 @@ def lib():
         L.dir_step.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_step_stored.argtypes = [vp, i32, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
+        L.dir_register_batch.argtypes = [vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.dir_wait.argtypes = [vp, vp]
         L.dir_set_graphs.argtypes = [vp, i32]
         L.dir_similarity.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
@@ -102,7 +104,7 @@ def lib():
         L.dir_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
-                     "dir_register_async", "dir_wait", "dir_set_graphs", "dir_step_stored", "dir_similarity",
+                     "dir_register_async", "dir_register_batch", "dir_wait", "dir_set_graphs", "dir_step_stored", "dir_similarity",
                      "dir_workspace_bytes", "dir_pool_create", "dir_pool_destroy", "dir_pool_submit",
                      "dir_pool_progress", "dir_pool_poll", "dir_pool_wait", "dir_pool_stats",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
@@ -285,6 +287,41 @@ def dir_register(h, static, moving, params, field_out=None, spacing_mm=None, his
     if rc != DIR_OK:
         raise DemonsError(rc, "dir_register")
     return field_out, stats
+
+
+def dir_register_batch(h, statics, movings, params, field_outs=None, spacing_mm=None, history=True):
+    """Lockstep batch of len(statics) registrations of one volume size (at
+    most DIR_MAX_BATCH); `params` is a list of dir_params that agree in
+    levels, iterations, sigma, radius and storage.  Returns a list of
+    (field, stats dict), each field bitwise the one dir_register computes."""
+    count = len(statics)
+    if not 1 <= count <= DIR_MAX_BATCH or len(movings) != count or len(params) != count:
+        raise ValueError(f"1..{DIR_MAX_BATCH} registrations, with one moving image and one dir_params each")
+    if field_outs is None:
+        field_outs = [None] * count
+    outs, sp = [], None
+    for k in range(count):
+        if statics[k].shape != statics[0].shape:
+            raise ValueError("every registration of a batch has the same volume size")
+        o, sp = _register_args(statics[k], movings[k], params[k], field_outs[k], spacing_mm)
+        outs.append(o)
+    nx, ny, nz = _dims(statics[0])
+    if h.stream is not None and h.stream != torch.cuda.current_stream(h.device):
+        h.stream.wait_stream(torch.cuda.current_stream(h.device))
+    ptrs = lambda ts: (ctypes.c_void_p * count)(*[t.data_ptr() for t in ts])
+    parr = (dir_params * count)(*params)
+    sts, bufs = [], []
+    for p in params:
+        st, buf = _new_stats(p, history)
+        sts.append(st)
+        bufs.append(buf)
+    sarr = (dir_stats * count)(*sts)
+    rc = lib().dir_register_batch(h.ptr, count, ptrs(statics), ptrs(movings), nx, ny, nz, sp, parr, ptrs(outs),
+                                  sarr)
+    res = [(outs[k], _stats_dict(rc, sarr[k], bufs[k])) for k in range(count)]
+    if rc != DIR_OK:
+        raise DemonsError(rc, "dir_register_batch")
+    return res
 
 
 def dir_register_async(h, static, moving, params, field_out=None, spacing_mm=None, history=True):

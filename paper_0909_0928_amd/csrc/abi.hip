@@ -20,7 +20,7 @@ thread_local std::string g_last_error;
 
 const char *const kKernelNames[K_COUNT] = {
     "force", "warp", "warp_pair", "smooth_yz", "smooth_x", "finalize", "level_reset",
-    "restrict", "prolong", "gradient", "compose", "fill", "convert", "similarity",
+    "restrict", "prolong", "gradient", "compose", "fill", "convert", "similarity", "warp_mixed",
 };
 
 // Device buffer that only grows.
@@ -63,15 +63,19 @@ struct GraphKey {
     dir_params params;
     int32_t nx, ny, nz, pad;
 };
+static_assert(kMaxBatch == DIR_MAX_BATCH, "batch limit of the ABI and of the kernels");
 static_assert(sizeof(GraphKey) == 15 * sizeof(void *) + sizeof(dir_params) + 16, "GraphKey has padding");
 
 // A registration enqueued by dir_register_async (or dir_register) whose
 // statistics have not been collected yet.
 struct InFlight {
     bool active = false;
+    int count = 1;                  // registrations (a lockstep batch: more than 1)
     int levels = 0;
     int64_t total_iters = 0;
     int64_t hist_off[DIR_MAX_LEVELS] = {};
+    size_t hist_stride = 0;         // bytes between registrations' histories
+    size_t state_stride = 0;        // bytes between registrations' level states
 };
 
 struct dir_handle {
@@ -479,44 +483,84 @@ GaussTaps identity_taps()
     return t;
 }
 
-// The force half of one iteration: pre-warp where the variant needs
-// deformed-image gradients, then the force kernel (u = v + dr, x pass of the
-// smoothing with `taps`, per-workgroup sums).
-hipError_t force_half(dir_handle *h, Ctx &c, int variant, int storage, float alpha2, const void *S, const void *M,
-                      const void *v, Dims d, const GaussTaps &taps, void *out, const int *stop_at, int n)
+// One iteration's force half for `count` registrations of one size (arrays
+// indexed by registration).
+struct ForceHalf {
+    int count = 1;
+    int storage;
+    int variant[kMaxBatch];
+    float alpha2[kMaxBatch];
+    const void *S[kMaxBatch], *M[kMaxBatch], *v[kMaxBatch];
+    void *D[kMaxBatch], *P[kMaxBatch];  // pre-warp outputs (workspace)
+    void *out[kMaxBatch];
+    double *partials[kMaxBatch];
+    const int *stop_at[kMaxBatch];
+};
+
+// The force half of one iteration: one pre-warp launch for the registrations
+// whose variant needs deformed-image gradients, then one force launch (u =
+// v + dr, x pass of the smoothing with `taps`, per-workgroup sums).
+hipError_t force_half(Ctx &c, const ForceHalf &b, Dims d, const GaussTaps &taps, int n)
 {
-    void *D = h->img_a.p, *P = h->img_b.p;
-    hipError_t e = hipSuccess;
-    if (variant == kActive || variant == kDouble) e = launch_warp_diff(c, M, S, v, d, D, storage, stop_at, n);
-    else if (variant == kInverseConsistent) e = launch_warp_pair(c, M, S, v, d, D, P, storage, stop_at, n);
-    if (e != hipSuccess) return e;
+    PrewarpLaunch w;
+    w.count = 0;
+    w.storage = b.storage;
+    w.d = d;
+    w.n = n;
+    unsigned kinds = 0;
+    for (int r = 0; r < b.count; ++r) {
+        const int v = b.variant[r];
+        if (v != kActive && v != kDouble && v != kInverseConsistent) continue;
+        const int kind = v == kInverseConsistent ? kPrewarpPair : kPrewarpDiff;
+        const int q = w.count++;
+        w.kinds[q] = kind;
+        kinds |= 1u << kind;
+        w.M[q] = b.M[r];
+        w.S[q] = b.S[r];
+        w.v[q] = b.v[r];
+        w.D[q] = b.D[r];
+        w.P[q] = b.P[r];
+        w.stop_at[q] = b.stop_at[r];
+    }
+    if (w.count) {
+        w.kind = kinds == (1u << kPrewarpDiff) ? kPrewarpDiff
+                                               : (kinds == (1u << kPrewarpPair) ? kPrewarpPair : kPrewarpMixed);
+        const hipError_t e = launch_prewarp(c, w);
+        if (e != hipSuccess) return e;
+    }
     ForceLaunch f;
-    f.variant = variant;
-    f.storage = storage;
-    f.alpha2 = alpha2;
-    f.S = S;
-    f.M = M;
-    f.v = v;
-    f.D = D;
-    f.P = P;
+    f.count = b.count;
+    f.variant = b.variant[0];
+    for (int r = 0; r < b.count; ++r) {
+        if (b.variant[r] != b.variant[0]) f.variant = kMixedVariants;
+        f.variants[r] = b.variant[r];
+        f.alpha2[r] = b.alpha2[r];
+        f.S[r] = b.S[r];
+        f.M[r] = b.M[r];
+        f.v[r] = b.v[r];
+        f.D[r] = b.D[r];
+        f.P[r] = b.P[r];
+        f.out[r] = b.out[r];
+        f.partials[r] = b.partials[r];
+        f.stop_at[r] = b.stop_at[r];
+    }
+    f.storage = b.storage;
     f.d = d;
     f.taps = &taps;
-    f.out = out;
-    f.partials = h->partials.as<double>();
-    f.stop_at = stop_at;
     f.n = n;
     return launch_force(c, f);
 }
 
-// Reduction descriptor for the sums of the force kernel at level size d.
-SumsReduce sums_reduce(dir_handle *h, Dims d, double *hist, LevelState *st, double eps)
+// Reduction descriptor of one registration's sums at level size d.
+SumsReduce sums_reduce_one(double *partials, Dims d, double *hist, LevelState *st, double eps)
 {
     SumsReduce r;
-    r.partials = h->partials.as<double>();
+    r.count = 1;
+    r.partials[0] = partials;
     r.nb = (int)force_blocks(d);
-    r.hist = hist;
-    r.st = st;
-    r.eps = eps;
+    r.hist[0] = hist;
+    r.st[0] = st;
+    r.eps[0] = eps;
     r.inv_n = 1.0 / (double)d.n();
     return r;
 }
@@ -563,15 +607,27 @@ int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, co
     }
     LevelState *st = h->state.as<LevelState>();
     DIR_TRY(launch_level_reset(c, st));
-    SumsReduce red = sums_reduce(h, d, h->history.as<double>(), st, 0.0);
+    SumsReduce red = sums_reduce_one(h->partials.as<double>(), d, h->history.as<double>(), st, 0.0);
     red.inv_n = 1.0;  // report the plain sum of D^2
+    ForceHalf fh;
+    fh.storage = storage;
+    fh.variant[0] = variant;
+    fh.alpha2[0] = (float)(alpha * alpha);
+    fh.S[0] = Sx;
+    fh.M[0] = Mx;
+    fh.v[0] = vx;
+    fh.D[0] = h->img_a.p;
+    fh.P[0] = h->img_b.p;
+    fh.partials[0] = h->partials.as<double>();
+    fh.stop_at[0] = nullptr;
     if (taps) {
-        DIR_TRY(force_half(h, c, variant, storage, (float)(alpha * alpha), Sx, Mx, vx, d, *taps, h->field[2].p,
-                           nullptr, 0));
+        fh.out[0] = h->field[2].p;
+        DIR_TRY(force_half(c, fh, d, *taps, 0));
         DIR_TRY(launch_smooth_yz(c, h->field[2].p, 3, d, *taps, fout, storage, nullptr, 0, red));
     } else {
         const GaussTaps id = identity_taps();
-        DIR_TRY(force_half(h, c, variant, storage, (float)(alpha * alpha), Sx, Mx, vx, d, id, fout, nullptr, 0));
+        fh.out[0] = fout;
+        DIR_TRY(force_half(c, fh, d, id, 0));
         DIR_TRY(launch_finalize(c, red, 0));
     }
     if (conv) DIR_TRY(launch_convert(c, fout, storage, out, kStoreF32, 3 * (int64_t)n));
@@ -656,19 +712,29 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
 
 namespace {
 
-// Everything one registration needs to enqueue its kernels: validated
-// arguments, level sizes and the history layout.
+// Everything one registration, or a lockstep batch of registrations of one
+// size, needs to enqueue its kernels: validated arguments (arrays indexed by
+// registration), level sizes, the history layout and the workspace strides
+// between registrations.
+struct RegSizes {
+    size_t pyr, img0, field, img_a, img_b, partials, history, state;
+    size_t total() const { return 2 * pyr + 2 * img0 + 2 * field + img_a + img_b + partials + history + state; }
+};
+
 struct RegPlan {
-    const float *S, *M;
-    float *out;
-    int variant, storage, L, K;
-    float alpha2;
-    double eps;
+    int count = 1;
+    const float *S[kMaxBatch], *M[kMaxBatch];
+    float *out[kMaxBatch];
+    int variant[kMaxBatch], K[kMaxBatch];
+    float alpha2[kMaxBatch];
+    double eps[kMaxBatch];
+    int storage, L;
     GaussTaps taps;
     Dims dims[DIR_MAX_LEVELS];
     int iters[DIR_MAX_LEVELS];
     int64_t total_iters;
     int64_t hist_off[DIR_MAX_LEVELS];
+    RegSizes stride;  // bytes between registrations in each workspace buffer
 };
 
 // Parameter checks of a registration that need no pointers.
@@ -689,11 +755,6 @@ int check_register_params(int32_t nx, int32_t ny, int32_t nz, const dir_params *
 }
 
 // Bytes of every workspace buffer a registration needs (parameters checked).
-struct RegSizes {
-    size_t pyr, img0, field, img_a, img_b, partials, history, state;
-    size_t total() const { return 2 * pyr + 2 * img0 + 2 * field + img_a + img_b + partials + history + state; }
-};
-
 RegSizes register_sizes(int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
 {
     RegSizes z;
@@ -776,36 +837,64 @@ extern "C" int32_t dir_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const
 
 namespace {
 
+// Fill the per-registration entries r of a plan from p (validated).
+void plan_entry(RegPlan &pl, int r, const float *S, const float *M, float *out, const dir_params *p)
+{
+    pl.S[r] = S;
+    pl.M[r] = M;
+    pl.out[r] = out;
+    pl.variant[r] = p->variant;
+    pl.K[r] = p->compose_iters < 0 ? DIR_DEFAULT_COMPOSE_ITERS : p->compose_iters;
+    pl.alpha2[r] = (float)(p->alpha * p->alpha);
+    pl.eps[r] = p->eps;
+}
+
+// The parts of a plan every registration of a batch shares (from p).
+void plan_shared(RegPlan &pl, int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
+{
+    pl.storage = p->storage;
+    pl.L = p->levels;
+    pl.taps = make_taps(p->sigma, resolve_radius(p->sigma, p->radius));
+    pl.dims[0] = Dims{nx, ny, nz};
+    for (int k = 1; k < pl.L; ++k) pl.dims[k] = coarser(pl.dims[k - 1]);
+    int64_t off = 0;
+    for (int k = 0; k < pl.L; ++k) {
+        pl.iters[k] = p->iters[k];  // coarsest first
+        pl.hist_off[k] = off;
+        off += p->iters[k];
+    }
+    pl.total_iters = off;
+}
+
+// The output field must not overlap either input.
+bool disjoint_io(const float *S, const float *M, const float *out, size_t n)
+{
+    const char *out_b = reinterpret_cast<const char *>(out);
+    for (const float *in : {S, M}) {
+        const char *b = reinterpret_cast<const char *>(in);
+        if (b < out_b + 3 * sizeof(float) * n && out_b < b + sizeof(float) * n) return false;
+    }
+    return true;
+}
+
+bool spacing_ok(const double *spacing_mm)
+{
+    if (spacing_mm)
+        for (int k = 0; k < 3; ++k)
+            if (!(spacing_mm[k] > 0.0) || !isfinite(spacing_mm[k])) return false;
+    return true;
+}
+
 // Validate the arguments of a registration and size the workspace for it.
 int plan_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny, int32_t nz,
                   const double *spacing_mm, const dir_params *p, float *d_field_out, RegPlan &pl)
 {
-    // ---- validation ----
     if (!d_static || !d_moving || !d_field_out) return DIR_EINVAL;
     int rc = check_register_params(nx, ny, nz, p);
     if (rc != DIR_OK) return rc;
-    if (spacing_mm)
-        for (int k = 0; k < 3; ++k)
-            if (!(spacing_mm[k] > 0.0) || !isfinite(spacing_mm[k])) return DIR_EINVAL;
-    const int variant = p->variant;
-    const int L = p->levels;
-    int64_t total_iters = 0;
-    for (int l = 0; l < L; ++l) total_iters += p->iters[l];
-    const int R = resolve_radius(p->sigma, p->radius);
-    const int K = p->compose_iters < 0 ? DIR_DEFAULT_COMPOSE_ITERS : p->compose_iters;
-    const GaussTaps taps = make_taps(p->sigma, R);
-    const float alpha2 = (float)(p->alpha * p->alpha);
-    const char *out_b = reinterpret_cast<const char *>(d_field_out);
-    const size_t out_bytes = sizeof(float) * 3 * (size_t)((int64_t)nx * ny * nz);
-    for (const float *in : {d_static, d_moving}) {
-        const char *b = reinterpret_cast<const char *>(in);
-        if (b < out_b + out_bytes && out_b < b + sizeof(float) * (size_t)((int64_t)nx * ny * nz)) return DIR_EINVAL;
-    }
+    if (!spacing_ok(spacing_mm)) return DIR_EINVAL;
+    if (!disjoint_io(d_static, d_moving, d_field_out, (size_t)((int64_t)nx * ny * nz))) return DIR_EINVAL;
 
-    // ---- workspace ----
-    Dims dims[DIR_MAX_LEVELS];
-    dims[0] = Dims{nx, ny, nz};
-    for (int k = 1; k < L; ++k) dims[k] = coarser(dims[k - 1]);
     const RegSizes z = register_sizes(nx, ny, nz, p);
     if (z.pyr) {
         DIR_TRY(h->pyr_s.ensure(z.pyr));
@@ -823,38 +912,142 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     DIR_TRY(h->history.ensure(z.history));
     DIR_TRY(h->state.ensure(z.state));
 
-    pl.S = d_static;
-    pl.M = d_moving;
-    pl.out = d_field_out;
-    pl.variant = variant;
-    pl.storage = p->storage;
-    pl.L = L;
-    pl.K = K;
-    pl.alpha2 = alpha2;
-    pl.eps = p->eps;
-    pl.taps = taps;
-    pl.total_iters = total_iters;
-    int64_t off = 0;
-    for (int k = 0; k < L; ++k) {
-        pl.dims[k] = dims[k];
-        pl.iters[k] = p->iters[k];  // coarsest first
-        pl.hist_off[k] = off;
-        off += p->iters[k];
-    }
+    pl.count = 1;
+    plan_shared(pl, nx, ny, nz, p);
+    plan_entry(pl, 0, d_static, d_moving, d_field_out, p);
+    pl.stride = z;
     return DIR_OK;
 }
 
-// Enqueue the kernels of a planned registration on the handle's stream.  With
-// `poll`, a level run under the stopping rule (eps > 0) reads its stop flag
-// every 10 iterations and enqueues no further iterations once the rule has
-// fired; without it every iteration is enqueued and the kernels of
-// iterations after the stop return at once.
+// Round a per-registration byte count up to a 256-byte boundary.
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Validate a lockstep batch and size the workspace for it: `count`
+// registrations of one volume size whose parameters agree in everything the
+// iteration schedule and the smoothing depend on (levels, iterations per
+// level, sigma, radius, storage); variant, alpha, eps and the composition
+// steps may differ.
+int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float *const *M, int32_t nx, int32_t ny,
+               int32_t nz, const double *spacing_mm, const dir_params *p, float *const *out, RegPlan &pl)
+{
+    if (count < 1 || count > DIR_MAX_BATCH || !S || !M || !p || !out) return DIR_EINVAL;
+    if (!spacing_ok(spacing_mm)) return DIR_EINVAL;
+    const size_t n = (size_t)((int64_t)nx * ny * nz);
+    RegSizes z{};
+    for (int r = 0; r < count; ++r) {
+        if (!S[r] || !M[r] || !out[r]) return DIR_EINVAL;
+        const int rc = check_register_params(nx, ny, nz, &p[r]);
+        if (rc != DIR_OK) return rc;
+        if (p[r].levels != p[0].levels || p[r].sigma != p[0].sigma || p[r].storage != p[0].storage ||
+            resolve_radius(p[r].sigma, p[r].radius) != resolve_radius(p[0].sigma, p[0].radius))
+            return DIR_EINVAL;
+        for (int l = 0; l < p[0].levels; ++l)
+            if (p[r].iters[l] != p[0].iters[l]) return DIR_EINVAL;
+        if (!disjoint_io(S[r], M[r], out[r], n)) return DIR_EINVAL;
+        const char *o = reinterpret_cast<const char *>(out[r]);
+        for (int q = 0; q < r; ++q) {  // every registration writes a field of its own
+            const char *oq = reinterpret_cast<const char *>(out[q]);
+            if (o < oq + 3 * sizeof(float) * n && oq < o + 3 * sizeof(float) * n) return DIR_EINVAL;
+            if (!disjoint_io(S[q], M[q], out[r], n) || !disjoint_io(S[r], M[r], out[q], n)) return DIR_EINVAL;
+        }
+        const RegSizes zr = register_sizes(nx, ny, nz, &p[r]);
+        z.pyr = std::max(z.pyr, align256(zr.pyr));
+        z.img0 = std::max(z.img0, align256(zr.img0));
+        z.field = std::max(z.field, align256(zr.field));
+        z.img_a = std::max(z.img_a, align256(zr.img_a));
+        z.img_b = std::max(z.img_b, align256(zr.img_b));
+        z.partials = std::max(z.partials, align256(zr.partials));
+        z.history = std::max(z.history, align256(zr.history));
+        z.state = std::max(z.state, align256(zr.state));
+    }
+    const size_t c = (size_t)count;
+    if (z.pyr) {
+        DIR_TRY(h->pyr_s.ensure(c * z.pyr));
+        DIR_TRY(h->pyr_m.ensure(c * z.pyr));
+    }
+    if (z.img0) {
+        DIR_TRY(h->img0_s.ensure(c * z.img0));
+        DIR_TRY(h->img0_m.ensure(c * z.img0));
+    }
+    DIR_TRY(h->field[0].ensure(c * z.field));
+    DIR_TRY(h->field[1].ensure(c * z.field));
+    if (z.img_a) DIR_TRY(h->img_a.ensure(c * z.img_a));
+    if (z.img_b) DIR_TRY(h->img_b.ensure(c * z.img_b));
+    DIR_TRY(h->partials.ensure(c * z.partials));
+    DIR_TRY(h->history.ensure(c * z.history));
+    DIR_TRY(h->state.ensure(c * z.state));
+
+    pl.count = count;
+    plan_shared(pl, nx, ny, nz, &p[0]);
+    for (int r = 0; r < count; ++r) plan_entry(pl, r, S[r], M[r], out[r], &p[r]);
+    pl.stride = z;
+    return DIR_OK;
+}
+
+// Address of registration r's part of a workspace buffer.
+template <class T = void>
+T *part(const DevBuf &b, size_t stride, int r)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(b.p) + stride * (size_t)r);
+}
+
+// A batch runs a level in lockstep while the images and fields its
+// registrations stream through every iteration (about 8 stored values per
+// voxel: S, M, v and u with 3 components each) fit the 256 MB last-level
+// cache of an MI355X.  A larger level streams from HBM either way, and then
+// runs registration by registration: consecutive kernels of one registration
+// find the field the previous one wrote still in that cache, which a lockstep
+// launch carrying every registration's data would have evicted.
+constexpr size_t kLockstepBytes = size_t(256) << 20;
+
+bool lockstep_level(int count, Dims d, size_t es)
+{
+    return count == 1 || (size_t)count * 8 * es * (size_t)d.n() <= kLockstepBytes;
+}
+
+// Registration r of a batch's iteration descriptors, as a batch of one.
+ForceHalf one_of(const ForceHalf &b, int r)
+{
+    ForceHalf o;
+    o.count = 1;
+    o.storage = b.storage;
+    o.variant[0] = b.variant[r];
+    o.alpha2[0] = b.alpha2[r];
+    o.S[0] = b.S[r];
+    o.M[0] = b.M[r];
+    o.v[0] = b.v[r];
+    o.D[0] = b.D[r];
+    o.P[0] = b.P[r];
+    o.out[0] = b.out[r];
+    o.partials[0] = b.partials[r];
+    o.stop_at[0] = b.stop_at[r];
+    return o;
+}
+
+SumsReduce one_of(const SumsReduce &b, int r)
+{
+    SumsReduce o = b;
+    o.count = 1;
+    o.partials[0] = b.partials[r];
+    o.hist[0] = b.hist[r];
+    o.st[0] = b.st[r];
+    o.eps[0] = b.eps[r];
+    return o;
+}
+
+// Enqueue the kernels of a planned registration (or lockstep batch) on the
+// handle's stream.  With `poll` (single registrations only), a level run
+// under the stopping rule (eps > 0) reads its stop flag every 10 iterations
+// and enqueues no further iterations once the rule has fired; otherwise every
+// iteration is enqueued and the kernels of iterations after a registration's
+// stop return at once.  A batch runs each iteration of all its registrations
+// as one pre-warp, one force and one smoothing launch.
 int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
 {
-    const int L = pl.L, variant = pl.variant, K = pl.K, st_fmt = pl.storage;
+    const int L = pl.L, st_fmt = pl.storage, B = pl.count;
     const Dims *dims = pl.dims;
     const GaussTaps &taps = pl.taps;
-    const float alpha2 = pl.alpha2;
+    const RegSizes &zs = pl.stride;
     const size_t es = storage_bytes(st_fmt);
     const bool f32 = st_fmt == kStoreF32;
     Ctx c{h->stream, &h->timer};
@@ -862,73 +1055,121 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
     // ---- image pyramids in the storage format (Sec 2.3) ----
     // Level 1 is restricted from the caller's FP32 images; with 16-bit
     // storage the finest level itself is a converted copy.
-    const void *Sk[DIR_MAX_LEVELS], *Mk[DIR_MAX_LEVELS];
-    Sk[0] = pl.S;
-    Mk[0] = pl.M;
-    {
+    const void *Sk[kMaxBatch][DIR_MAX_LEVELS], *Mk[kMaxBatch][DIR_MAX_LEVELS];
+    for (int r = 0; r < B; ++r) {
+        Sk[r][0] = pl.S[r];
+        Mk[r][0] = pl.M[r];
         size_t off = 0;
         for (int k = 1; k < L; ++k) {
-            char *s = static_cast<char *>(h->pyr_s.p) + es * off, *m = static_cast<char *>(h->pyr_m.p) + es * off;
+            char *s = part<char>(h->pyr_s, zs.pyr, r) + es * off, *m = part<char>(h->pyr_m, zs.pyr, r) + es * off;
             const int in_fmt = k == 1 ? kStoreF32 : st_fmt;
             h->timer.level = k;
-            DIR_TRY(launch_restrict(c, Sk[k - 1], in_fmt, dims[k - 1], s, st_fmt, dims[k]));
-            DIR_TRY(launch_restrict(c, Mk[k - 1], in_fmt, dims[k - 1], m, st_fmt, dims[k]));
-            Sk[k] = s;
-            Mk[k] = m;
+            DIR_TRY(launch_restrict(c, Sk[r][k - 1], in_fmt, dims[k - 1], s, st_fmt, dims[k]));
+            DIR_TRY(launch_restrict(c, Mk[r][k - 1], in_fmt, dims[k - 1], m, st_fmt, dims[k]));
+            Sk[r][k] = s;
+            Mk[r][k] = m;
             off += (size_t)dims[k].n();
         }
-    }
-    if (!f32) {
-        h->timer.level = 0;
-        DIR_TRY(launch_convert(c, pl.S, kStoreF32, h->img0_s.p, st_fmt, dims[0].n()));
-        DIR_TRY(launch_convert(c, pl.M, kStoreF32, h->img0_m.p, st_fmt, dims[0].n()));
-        Sk[0] = h->img0_s.p;
-        Mk[0] = h->img0_m.p;
+        if (!f32) {
+            h->timer.level = 0;
+            void *s0 = part(h->img0_s, zs.img0, r), *m0 = part(h->img0_m, zs.img0, r);
+            DIR_TRY(launch_convert(c, pl.S[r], kStoreF32, s0, st_fmt, dims[0].n()));
+            DIR_TRY(launch_convert(c, pl.M[r], kStoreF32, m0, st_fmt, dims[0].n()));
+            Sk[r][0] = s0;
+            Mk[r][0] = m0;
+        }
     }
 
     // ---- levels, coarse to fine (Sec 2.3) ----
-    // With FP32 storage the finest level's field lives in d_field_out itself,
-    // except for the inverse-consistent variant, whose half field is composed
-    // into it; 16-bit fields are converted into it at the end.
-    void *const fa = h->field[0].p, *const fb = h->field[1].p;
-    void *const final_v = (variant == kInverseConsistent || !f32) ? nullptr : static_cast<void *>(pl.out);
-    void *v = (L == 1 && final_v) ? final_v : fa;
-    LevelState *states = h->state.as<LevelState>();
-    double *hist = h->history.as<double>();
+    // With FP32 storage the finest level's field lives in the output field
+    // itself, except for the inverse-consistent variant, whose half field is
+    // composed into it; 16-bit fields are converted into it at the end.
+    void *fa[kMaxBatch], *fb[kMaxBatch], *final_v[kMaxBatch], *v[kMaxBatch], *xs[kMaxBatch];
+    LevelState *states[kMaxBatch];
+    double *hist[kMaxBatch];
+    ForceHalf fh;
+    fh.count = B;
+    fh.storage = st_fmt;
     h->timer.level = L - 1;
-    DIR_TRY(launch_zero(c, v, 3 * dims[L - 1].n(), st_fmt));
+    for (int r = 0; r < B; ++r) {
+        fa[r] = part(h->field[0], zs.field, r);
+        fb[r] = part(h->field[1], zs.field, r);
+        final_v[r] = (pl.variant[r] == kInverseConsistent || !f32) ? nullptr : static_cast<void *>(pl.out[r]);
+        v[r] = (L == 1 && final_v[r]) ? final_v[r] : fa[r];
+        states[r] = part<LevelState>(h->state, zs.state, r);
+        hist[r] = part<double>(h->history, zs.history, r);
+        fh.variant[r] = pl.variant[r];
+        fh.alpha2[r] = pl.alpha2[r];
+        fh.D[r] = part(h->img_a, zs.img_a, r);
+        fh.P[r] = part(h->img_b, zs.img_b, r);
+        fh.partials[r] = part<double>(h->partials, zs.partials, r);
+        DIR_TRY(launch_zero(c, v[r], 3 * dims[L - 1].n(), st_fmt));
+    }
     for (int k = L - 1; k >= 0; --k) {
         const int li = L - 1 - k;
         const Dims d = dims[k];
         h->timer.level = k;
-        if (k < L - 1) {
-            void *dst = (k == 0 && final_v) ? final_v : (v == fa ? fb : fa);
-            DIR_TRY(launch_prolong(c, v, dims[k + 1], dst, d, st_fmt));
-            v = dst;
+        SumsReduce red;
+        red.count = B;
+        red.nb = (int)force_blocks(d);
+        red.inv_n = 1.0 / (double)d.n();
+        for (int r = 0; r < B; ++r) {
+            if (k < L - 1) {
+                void *dst = (k == 0 && final_v[r]) ? final_v[r] : (v[r] == fa[r] ? fb[r] : fa[r]);
+                DIR_TRY(launch_prolong(c, v[r], dims[k + 1], dst, d, st_fmt));
+                v[r] = dst;
+            }
+            xs[r] = v[r] == fa[r] ? fb[r] : fa[r];  // x-smoothed u of this level
+            LevelState *st = states[r] + li;
+            DIR_TRY(launch_level_reset(c, st));
+            red.partials[r] = fh.partials[r];
+            red.hist[r] = hist[r] + 4 * pl.hist_off[li];
+            red.st[r] = st;
+            red.eps[r] = pl.eps[r];
+            // Without the stopping rule the flag never changes, so the
+            // kernels are not given it (each would otherwise read it first).
+            fh.stop_at[r] = pl.eps[r] > 0.0 ? &st->stop_at : nullptr;
+            fh.S[r] = Sk[r][k];
+            fh.M[r] = Mk[r][k];
+            fh.v[r] = v[r];
+            fh.out[r] = xs[r];
         }
-        void *const xs = v == fa ? fb : fa;  // x-smoothed u of this level
-        LevelState *st = states + li;
-        DIR_TRY(launch_level_reset(c, st));
         const int iters = pl.iters[li];
-        const SumsReduce red = sums_reduce(h, d, hist + 4 * pl.hist_off[li], st, pl.eps);
-        for (int n = 0; n < iters; ++n) {
-            // v -> xs = x-smoothed (v + dr) -> v = y,z-smoothed xs; the
-            // smoothing kernel also reduces the sums of this iteration
-            DIR_TRY(force_half(h, c, variant, st_fmt, alpha2, Sk[k], Mk[k], v, d, taps, xs, &st->stop_at, n));
-            DIR_TRY(launch_smooth_yz(c, xs, 3, d, taps, v, st_fmt, &st->stop_at, n, red));
-            if (poll && pl.eps > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
-                int stop_at = kNeverStopped;
-                DIR_TRY(hipMemcpyAsync(&stop_at, &st->stop_at, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-                DIR_TRY(hipStreamSynchronize(h->stream));
-                if (stop_at != kNeverStopped) break;
+        // The iterations of this level for the registrations of `f` and `rd`
+        // (fields xsv, vv), all in lockstep.
+        auto run_level = [&](const ForceHalf &f, const SumsReduce &rd, void *const *xsv, void *const *vv) -> int {
+            for (int n = 0; n < iters; ++n) {
+                // v -> xs = x-smoothed (v + dr) -> v = y,z-smoothed xs; the
+                // smoothing kernel also reduces the sums of this iteration
+                DIR_TRY(force_half(c, f, d, taps, n));
+                DIR_TRY(launch_smooth_yz(c, f.count, xsv, 3, d, taps, vv, st_fmt, f.stop_at, n, rd));
+                if (poll && B == 1 && pl.eps[0] > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
+                    int stop_at = kNeverStopped;
+                    DIR_TRY(hipMemcpyAsync(&stop_at, &states[0][li].stop_at, sizeof(int), hipMemcpyDeviceToHost,
+                                           h->stream));
+                    DIR_TRY(hipStreamSynchronize(h->stream));
+                    if (stop_at != kNeverStopped) break;
+                }
+            }
+            return DIR_OK;
+        };
+        if (lockstep_level(B, d, es)) {
+            const int rc = run_level(fh, red, xs, v);
+            if (rc != DIR_OK) return rc;
+        } else {
+            for (int r = 0; r < B; ++r) {
+                const int rc = run_level(one_of(fh, r), one_of(red, r), &xs[r], &v[r]);
+                if (rc != DIR_OK) return rc;
             }
         }
     }
 
     // ---- output (FP32) ----
     h->timer.level = 0;
-    if (variant == kInverseConsistent) DIR_TRY(launch_compose(c, v, st_fmt, dims[0], K, pl.out));
-    else if (!f32) DIR_TRY(launch_convert(c, v, st_fmt, pl.out, kStoreF32, 3 * dims[0].n()));
+    for (int r = 0; r < B; ++r) {
+        if (pl.variant[r] == kInverseConsistent) DIR_TRY(launch_compose(c, v[r], st_fmt, dims[0], pl.K[r], pl.out[r]));
+        else if (!f32) DIR_TRY(launch_convert(c, v[r], st_fmt, pl.out[r], kStoreF32, 3 * dims[0].n()));
+    }
     return DIR_OK;
 }
 
@@ -936,9 +1177,9 @@ GraphKey graph_key(dir_handle *h, const RegPlan &pl, const dir_params *p)
 {
     GraphKey k;
     memset(&k, 0, sizeof k);
-    k.S = pl.S;
-    k.M = pl.M;
-    k.out = pl.out;
+    k.S = pl.S[0];
+    k.M = pl.M[0];
+    k.out = pl.out[0];
     k.nx = pl.dims[0].nx;
     k.ny = pl.dims[0].ny;
     k.nz = pl.dims[0].nz;
@@ -973,13 +1214,26 @@ int capture_register(dir_handle *h, const RegPlan &pl, hipGraphExec_t *exec)
 // into a HIP graph and the graph is replayed while the arguments and the
 // workspace stay the same; otherwise (or on the null stream, which cannot be
 // captured) they are enqueued one by one.
+// Record an enqueued plan as the handle's registration in flight.
+void note_inflight(dir_handle *h, const RegPlan &pl)
+{
+    InFlight &f = h->inflight;
+    f.active = true;
+    f.count = pl.count;
+    f.levels = pl.L;
+    f.total_iters = pl.total_iters;
+    for (int li = 0; li < pl.L; ++li) f.hist_off[li] = pl.hist_off[li];
+    f.hist_stride = pl.stride.history;
+    f.state_stride = pl.stride.state;
+}
+
 int submit_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
                     int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out, bool poll)
 {
     RegPlan pl;
     int rc = plan_register(h, d_static, d_moving, nx, ny, nz, spacing_mm, p, d_field_out, pl);
     if (rc != DIR_OK) return rc;
-    const bool graph = h->graphs && h->stream != nullptr && h->timer.mask == 0 && !(poll && pl.eps > 0.0);
+    const bool graph = h->graphs && h->stream != nullptr && h->timer.mask == 0 && !(poll && pl.eps[0] > 0.0);
     if (graph) {
         const GraphKey key = graph_key(h, pl, p);
         if (!h->graph_exec || memcmp(&key, &h->graph_key, sizeof key) != 0) {
@@ -999,42 +1253,19 @@ int submit_register(dir_handle *h, const float *d_static, const float *d_moving,
         rc = enqueue_register(h, pl, poll);
         if (rc != DIR_OK) return rc;
     }
-    InFlight &f = h->inflight;
-    f.active = true;
-    f.levels = pl.L;
-    f.total_iters = pl.total_iters;
-    for (int li = 0; li < pl.L; ++li) f.hist_off[li] = pl.hist_off[li];
+    note_inflight(h, pl);
     return DIR_OK;
 }
 
-// Wait for the in-flight registration and fill `stats` (may be NULL).
-int collect_register(dir_handle *h, dir_stats *stats)
+// Fill one registration's statistics from its level states and history.
+bool fill_stats(const InFlight &f, const LevelState *hs, const double *hh, dir_stats *stats)
 {
-    InFlight f = h->inflight;
-    h->inflight.active = false;
-    const int L = f.levels;
-    const int64_t total_iters = f.total_iters;
-    const int64_t *hist_off = f.hist_off;
-    LevelState *states = h->state.as<LevelState>();
-    double *hist = h->history.as<double>();
-    int rc = finish(h);
-    if (rc != DIR_OK) return rc;
-
-    // ---- statistics and the numeric check ----
-    LevelState hs[DIR_MAX_LEVELS];
-    rc = copy_to_host(h, hs, states, sizeof(LevelState) * L);
-    if (rc != DIR_OK) return rc;
-    std::vector<double> hh((size_t)4 * (size_t)(total_iters > 0 ? total_iters : 1));
-    if (total_iters > 0) {
-        rc = copy_to_host(h, hh.data(), hist, sizeof(double) * 4 * total_iters);
-        if (rc != DIR_OK) return rc;
-    }
     bool finite = true;
     int64_t packed = 0;
     double last_mse = 0.0, last_l = __builtin_nan("");
-    for (int li = 0; li < L; ++li) {
+    for (int li = 0; li < f.levels; ++li) {
         for (int n = 0; n < hs[li].iters_run; ++n) {
-            const double *e = &hh[(size_t)4 * (hist_off[li] + n)];
+            const double *e = &hh[(size_t)4 * (f.hist_off[li] + n)];
             if (!isfinite(e[0]) || !isfinite(e[1]) || !isfinite(e[2])) finite = false;
             if (stats && stats->history && packed < stats->history_capacity)
                 memcpy(stats->history + 4 * packed, e, sizeof(double) * 4);
@@ -1044,17 +1275,41 @@ int collect_register(dir_handle *h, dir_stats *stats)
         }
     }
     if (stats) {
-        stats->levels = L;
-        for (int li = 0; li < DIR_MAX_LEVELS; ++li) stats->iters_run[li] = li < L ? hs[li].iters_run : 0;
+        stats->levels = f.levels;
+        for (int li = 0; li < DIR_MAX_LEVELS; ++li) stats->iters_run[li] = li < f.levels ? hs[li].iters_run : 0;
         stats->mse_final = last_mse;
         stats->relnorm_final = last_l;
         stats->history_len = (int32_t)(stats->history ? (packed < stats->history_capacity ? packed
                                                                                          : stats->history_capacity)
                                                       : 0);
     }
-    return finite ? DIR_OK : DIR_ENUMERIC;
+    return finite;
 }
 
+// Wait for the registration (or batch) in flight and fill stats[0 .. count-1]
+// (may be NULL).  DIR_ENUMERIC if any registration's sums are not finite.
+int collect_register(dir_handle *h, dir_stats *stats)
+{
+    const InFlight f = h->inflight;
+    h->inflight.active = false;
+    int rc = finish(h);
+    if (rc != DIR_OK) return rc;
+    bool finite = true;
+    std::vector<double> hh((size_t)4 * (size_t)(f.total_iters > 0 ? f.total_iters : 1));
+    for (int r = 0; r < f.count; ++r) {
+        LevelState hs[DIR_MAX_LEVELS];
+        rc = copy_to_host(h, hs, static_cast<char *>(h->state.p) + f.state_stride * (size_t)r,
+                          sizeof(LevelState) * f.levels);
+        if (rc != DIR_OK) return rc;
+        if (f.total_iters > 0) {
+            rc = copy_to_host(h, hh.data(), static_cast<char *>(h->history.p) + f.hist_stride * (size_t)r,
+                              sizeof(double) * 4 * f.total_iters);
+            if (rc != DIR_OK) return rc;
+        }
+        if (!fill_stats(f, hs, hh.data(), stats ? &stats[r] : nullptr)) finite = false;
+    }
+    return finite ? DIR_OK : DIR_ENUMERIC;
+}
 
 }  // namespace
 
@@ -1086,6 +1341,26 @@ int32_t dir_wait(dir_handle *h, dir_stats *stats)
     if (rc != DIR_OK) return rc;
     if (!h->inflight.active) return DIR_EINVAL;
     if (stats && stats->struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
+    return collect_register(h, stats);
+}
+
+int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_static,
+                           const float *const *d_moving, int32_t nx, int32_t ny, int32_t nz,
+                           const double *spacing_mm, const dir_params *params, float *const *d_field_out,
+                           dir_stats *stats)
+{
+    int rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    if (count < 1 || count > DIR_MAX_BATCH) return DIR_EINVAL;
+    if (stats)
+        for (int r = 0; r < count; ++r)
+            if (stats[r].struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
+    RegPlan pl;
+    rc = plan_batch(h, count, d_static, d_moving, nx, ny, nz, spacing_mm, params, d_field_out, pl);
+    if (rc != DIR_OK) return rc;
+    rc = enqueue_register(h, pl, false);
+    if (rc != DIR_OK) return rc;
+    note_inflight(h, pl);
     return collect_register(h, stats);
 }
 

@@ -13,8 +13,14 @@ constexpr int kMaxRadius = 16;
 constexpr int kBlockX = 64;   // one wavefront along x
 constexpr int kBlockY = 4;    // four wavefronts per workgroup
 
-// Variant codes, numerically equal to dir_variant.
-enum Variant { kPassive = 0, kEvolved = 1, kActive = 2, kDouble = 3, kInverseConsistent = 4 };
+// Variant codes, numerically equal to dir_variant; kMixedVariants selects
+// per-registration variants in a lockstep batch.
+enum Variant { kMixedVariants = -1, kPassive = 0, kEvolved = 1, kActive = 2, kDouble = 3, kInverseConsistent = 4 };
+
+// Registrations one launch of the per-iteration kernels can carry: a lockstep
+// batch of registrations of one volume size runs every iteration of all of
+// them as one pre-warp, one force and one smoothing launch.
+constexpr int kMaxBatch = 8;
 
 // Storage formats of images and fields inside a registration, numerically
 // equal to dir_storage: FP32, IEEE half, bfloat16.
@@ -37,6 +43,7 @@ enum KernelId {
     K_FILL,
     K_CONVERT,       // storage-format conversion (reduced-precision registrations)
     K_SIMILARITY,    // intensity error and correlation coefficient (dir_similarity)
+    K_WARP_MIXED,    // pre-warp of a batch that mixes the two kinds above
     K_COUNT
 };
 
@@ -61,13 +68,15 @@ struct LevelState {
 
 // Where the per-iteration FP64 sums of the force kernel are reduced: the
 // kernel that runs next (the y/z smoothing, or the standalone finalize)
-// dedicates one workgroup to it.
+// dedicates one workgroup per registration to it.
 struct SumsReduce {
-    const double *partials;  // 3 * nb doubles, or NULL: nothing to reduce
-    int nb;
-    double *hist;            // level history; entry n at hist[4n]
-    LevelState *st;
-    double eps, inv_n;
+    int count = 0;                         // registrations; 0: nothing to reduce
+    const double *partials[kMaxBatch];     // 3 * nb doubles each
+    double *hist[kMaxBatch];               // level history; entry n at hist[4n]
+    LevelState *st[kMaxBatch];
+    double eps[kMaxBatch];
+    int nb;                                // force workgroups per registration
+    double inv_n;
 };
 
 // Per-kernel HIP-event timing.  A timed launch goes through
@@ -112,20 +121,41 @@ struct Ctx {
 // Number of workgroups (and FP64 sum slots) of the force kernel for a level.
 int64_t force_blocks(Dims d);
 
-// One force-kernel launch: u = v + dr (Eqs 1-6), its x-smoothing with `taps`
-// (identity taps give u), and the per-workgroup FP64 sums.  Every volume is
-// in format `storage`.
+// One force-kernel launch for `count` registrations of size d: u = v + dr
+// (Eqs 1-6), its x-smoothing with `taps` (identity taps give u), and the
+// per-workgroup FP64 sums.  Every volume is in format `storage`.  Arrays are
+// indexed by registration.
 struct ForceLaunch {
-    int variant;
+    int count = 1;
+    int variant;                     // every registration's, or kMixedVariants
+    int variants[kMaxBatch];         // per registration, with kMixedVariants
     int storage;
-    float alpha2;
-    const void *S, *M, *v;
-    const void *D, *P;    // from the pre-warp: D (active, double, IC), P = Im + Is (IC)
+    float alpha2[kMaxBatch];
+    const void *S[kMaxBatch], *M[kMaxBatch], *v[kMaxBatch];
+    const void *D[kMaxBatch], *P[kMaxBatch];  // from the pre-warp: D (active, double, IC), P = Im + Is (IC)
     Dims d;
     const GaussTaps *taps;
-    void *out;
-    double *partials;     // 3 * force_blocks(d) doubles
-    const int *stop_at;   // skip when *stop_at < n (NULL: never)
+    void *out[kMaxBatch];
+    double *partials[kMaxBatch];     // 3 * force_blocks(d) doubles each
+    const int *stop_at[kMaxBatch];   // skip when *stop_at < n (NULL: never)
+    int n;
+};
+
+// Pre-warp kinds: D = M(x - v) - S (active, double) or the inverse-consistent
+// pair D = Im - Is, P = Im + Is.
+enum PrewarpKind { kPrewarpMixed = -1, kPrewarpDiff = 0, kPrewarpPair = 1 };
+
+// One pre-warp launch for `count` registrations of size d (arrays indexed by
+// registration; P only for the pair kind).
+struct PrewarpLaunch {
+    int count = 1;
+    int kind;                        // every registration's, or kPrewarpMixed
+    int kinds[kMaxBatch];            // per registration, with kPrewarpMixed
+    int storage;
+    const void *M[kMaxBatch], *S[kMaxBatch], *v[kMaxBatch];
+    void *D[kMaxBatch], *P[kMaxBatch];
+    const int *stop_at[kMaxBatch];
+    Dims d;
     int n;
 };
 
@@ -136,14 +166,18 @@ hipError_t launch_restrict(Ctx &c, const void *in, int in_st, Dims fine, void *o
 hipError_t launch_prolong(Ctx &c, const void *vc, Dims coarse, void *vf, Dims fine, int st);
 hipError_t launch_gradient(Ctx &c, const float *img, Dims d, float *grad);
 hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, float *out, const int *stop_at, int n);
-hipError_t launch_warp_diff(Ctx &c, const void *M, const void *S, const void *v, Dims d, void *D, int st,
-                            const int *stop_at, int n);
-hipError_t launch_warp_pair(Ctx &c, const void *M, const void *S, const void *h, Dims d, void *D, void *P, int st,
-                            const int *stop_at, int n);
+hipError_t launch_prewarp(Ctx &c, const PrewarpLaunch &w);
 hipError_t launch_force(Ctx &c, const ForceLaunch &f);
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out);
-hipError_t launch_smooth_yz(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out, int st,
-                            const int *stop_at, int n, const SumsReduce &red);
+// y and z passes for `count` registrations of size d (arrays indexed by
+// registration); red.count is 0 or `count`.
+hipError_t launch_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, Dims d, const GaussTaps &taps,
+                            void *const *out, int st, const int *const *stop_at, int n, const SumsReduce &red);
+inline hipError_t launch_smooth_yz(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out,
+                                   int st, const int *stop_at, int n, const SumsReduce &red)
+{
+    return launch_smooth_yz(c, 1, &in, ncomp, d, taps, &out, st, &stop_at, n, red);
+}
 hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n);
 hipError_t launch_level_reset(Ctx &c, LevelState *st);
 hipError_t launch_compose(Ctx &c, const void *h, int h_st, Dims d, int K, float *out);

@@ -16,6 +16,8 @@
 // kernel that runs next (no cross-workgroup fences inside this kernel: on a
 // multi-XCD device an agent-scope release per workgroup costs an L2
 // write-back each).
+#include <string.h>
+
 #include "device_common.h"
 
 namespace dir {
@@ -24,18 +26,23 @@ namespace {
 using namespace dev;
 
 // Volumes are in the storage format of the kernel instance (StF32, StF16 or
-// StBF16); the pointers are untyped.
+// StBF16); the pointers are untyped.  One launch serves `count` registrations
+// of one size (a lockstep batch; 1 outside batches): per-registration
+// arguments are arrays indexed by registration, and the grid holds `blocks`
+// workgroups per registration.
 struct ForceArgs {
-    const void *S, *M, *v;
-    const void *Dd, *P;   // pre-warped D (active, double, IC) and P = Im + Is (IC, always FP32)
+    const void *S[kMaxBatch], *M[kMaxBatch], *v[kMaxBatch];
+    const void *Dd[kMaxBatch], *P[kMaxBatch];  // pre-warped D (active, double, IC) and P = Im + Is (IC, always FP32)
+    void *out[kMaxBatch];           // x-smoothed u (u itself with identity taps)
+    double *partials[kMaxBatch];    // 3 * blocks doubles each: s1[], s2[], sse[]
+    const int *stop_at[kMaxBatch];  // skip when *stop_at < n (NULL: never)
+    float alpha2[kMaxBatch];
+    int variant[kMaxBatch];         // read by the mixed-variant instance only
     int nx, ny, nz;
-    float alpha2;
-    void *out;            // x-smoothed u (u itself with identity taps)
-    double *partials;     // 3 * gridDim.x doubles: s1[], s2[], sse[]
-    const int *stop_at;   // skip when *stop_at < n (NULL: never)
-    int n;                // iteration index within the level
+    int n;                          // iteration index within the level
     int rows_per_block;
-    int gxt;              // x tiles
+    int gxt;                        // x tiles
+    int blocks;                     // workgroups per registration
 };
 
 // Byte offsets of one wave-uniform row (y, z) and of its stencil neighbour
@@ -94,7 +101,7 @@ struct Bufs {
 
 // u = v + dr at voxel (x, y, z) and its contributions |dr|, |v|, D^2.
 template <int V, class St>
-__device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, int x, int y, int z,
+__device__ __forceinline__ void force_point(const ForceArgs &a, float alpha2, const Bufs &b, int x, int y, int z,
                                             const RowOffsets &ro, unsigned nbytes, float &u0, float &u1, float &u2,
                                             double &adr, double &av, double &d2)
 {
@@ -124,16 +131,16 @@ __device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, i
         const RowOffsets r4{K4 * ro.c, K4 * ro.ym, K4 * ro.yp, K4 * ro.zm, K4 * ro.zp};
         float gx, gy, gz;
         cdiff<StF32>(b.P, l4, r4, gx, gy, gz);
-        dterm(D, gx, gy, gz, a.alpha2, fx, fy, fz);
+        dterm(D, gx, gy, gz, alpha2, fx, fy, fz);
     } else {
         float sx, sy, sz;
         cdiff<St>(b.S, lo, ro, sx, sy, sz);
-        if (V == kPassive || V == kDouble) dterm(D, sx, sy, sz, a.alpha2, fx, fy, fz);  // Eq 1
+        if (V == kPassive || V == kDouble) dterm(D, sx, sy, sz, alpha2, fx, fy, fz);  // Eq 1
         if (V == kActive || V == kDouble) {                                             // Eq 3
             // grad Im = grad (Im - S) + grad S
             float dx, dy, dz, bx, by, bz;
             cdiff<St>(b.Dd, lo, ro, dx, dy, dz);
-            dterm(D, dx + sx, dy + sy, dz + sz, a.alpha2, bx, by, bz);
+            dterm(D, dx + sx, dy + sy, dz + sz, alpha2, bx, by, bz);
             fx += bx;
             fy += by;
             fz += bz;
@@ -152,21 +159,26 @@ __device__ __forceinline__ void force_point(const ForceArgs &a, const Bufs &b, i
     d2 = D64 * D64;
 }
 
+// Rows in flight per workgroup and the LDS row buffer of a TX-wide tile.
+template <int TX>
+struct ForceTile {
+    static constexpr int LANES = TX < 256 ? TX : 256;  // threads per row
+    static constexpr int W = 256 / LANES;               // rows in flight
+    using Rows = float[3][W][TX + 2 * kMaxRadius];
+};
+
+// The rows of registration `reg` that its logical workgroup `lid` owns.
 // RC >= 0: the smoothing radius is RC, known at compile time (taps from the
 // kernel arguments, LDS reads issued together); RC < 0: taps.radius, taps
 // from LDS.  St: storage format of every volume the kernel reads and writes.
 template <int V, int TX, int RC, class St>
-__global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
+__device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &taps, int reg, int lid,
+                                           typename ForceTile<TX>::Rows &ul, const float *wl)
 {
-    if (a.stop_at && *a.stop_at < a.n) return;
-    constexpr int LANES = TX < 256 ? TX : 256;  // threads per row
-    constexpr int W = 256 / LANES;               // rows in flight
-    __shared__ float ul[3][W][TX + 2 * kMaxRadius];
-    __shared__ float wl[2 * kMaxRadius + 1];  // taps, read as LDS broadcasts
+    constexpr int LANES = ForceTile<TX>::LANES;
+    constexpr int W = ForceTile<TX>::W;
     const int tid = threadIdx.x;
-    if (tid <= 2 * kMaxRadius) wl[tid] = taps.w[tid];  // ordered before use by the row barrier
     const int lane = tid % LANES, wrow = tid / LANES;
-    const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
     const int x0 = (lid % a.gxt) * TX;
     const int rb = lid / a.gxt;
     const int R = RC >= 0 ? RC : taps.radius;
@@ -174,13 +186,14 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
     const unsigned N = (unsigned)a.nx * (unsigned)rows;
     constexpr unsigned ES = St::kBytes;
     const unsigned nbytes = ES * N;
+    const float alpha2 = a.alpha2[reg];
     Bufs b;
-    b.S = make_rsrc(a.S, nbytes);
-    b.M = make_rsrc(a.M, nbytes);
-    b.v = make_rsrc(a.v, 3u * nbytes);
-    b.Dd = make_rsrc(a.Dd, nbytes);
-    b.P = make_rsrc(a.P, 4u * N);  // FP32 in every format
-    b.out = make_rsrc(a.out, 3u * nbytes);
+    b.S = make_rsrc(a.S[reg], nbytes);
+    b.M = make_rsrc(a.M[reg], nbytes);
+    b.v = make_rsrc(a.v[reg], 3u * nbytes);
+    b.Dd = make_rsrc(a.Dd[reg], nbytes);
+    b.P = make_rsrc(a.P[reg], 4u * N);  // FP32 in every format
+    b.out = make_rsrc(a.out[reg], 3u * nbytes);
     double s1 = 0.0, s2 = 0.0, sse = 0.0;
 
     for (int it = 0; it < a.rows_per_block; ++it) {
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
                 const int xx = x0 - R + p;  // in [0, nx)
                 float u0, u1, u2;
                 double adr, av, d2;
-                force_point<V, St>(a, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
+                force_point<V, St>(a, alpha2, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
                 ul[0][wrow][p] = u0;
                 ul[1][wrow][p] = u1;
                 ul[2][wrow][p] = u2;
@@ -256,16 +269,45 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
     // ---- sums: fixed-order workgroup reduction into this workgroup's slots ----
     block_sum3(s1, s2, sse, tid);
     if (tid == 0) {
-        const int nb = gridDim.x;
-        a.partials[blockIdx.x] = s1;
-        a.partials[nb + blockIdx.x] = s2;
-        a.partials[2 * nb + blockIdx.x] = sse;
+        const int nb = a.blocks;
+        double *p = a.partials[reg];
+        p[lid] = s1;
+        p[nb + lid] = s2;
+        p[2 * nb + lid] = sse;
     }
 }
 
+// One workgroup of a force launch.  Logical workgroup ids (XCD-contiguous)
+// run registration by registration; V = kMixedVariants takes each
+// registration's variant from the arguments (a uniform branch per workgroup).
+template <int V, int TX, int RC, class St>
+__global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
+{
+    __shared__ typename ForceTile<TX>::Rows ul;
+    __shared__ float wl[2 * kMaxRadius + 1];  // taps, read as LDS broadcasts
+    const int g = xcd_logical_id(blockIdx.x, gridDim.x);
+    const int reg = g / a.blocks, lid = g - reg * a.blocks;  // wave-uniform
+    if (a.stop_at[reg] && *a.stop_at[reg] < a.n) return;
+    if (threadIdx.x <= 2 * kMaxRadius) wl[threadIdx.x] = taps.w[threadIdx.x];  // ordered before use by the row barrier
+    if constexpr (V != kMixedVariants) {
+        force_rows<V, TX, RC, St>(a, taps, reg, lid, ul, wl);
+    } else {
+        switch (a.variant[reg]) {
+        case kPassive: force_rows<kPassive, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
+        case kEvolved: force_rows<kEvolved, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
+        case kActive: force_rows<kActive, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
+        case kDouble: force_rows<kDouble, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
+        default: force_rows<kInverseConsistent, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
+        }
+    }
+}
+
+
+// Workgroup r reduces the sums of registration r.
 __global__ __launch_bounds__(256) void k_finalize(SumsReduce red, int n)
 {
-    reduce_sums(red.partials, red.nb, red.hist, n, red.st, red.eps, red.inv_n, threadIdx.x);
+    const int r = blockIdx.x;
+    reduce_sums(red.partials[r], red.nb, red.hist[r], n, red.st[r], red.eps[r], red.inv_n, threadIdx.x);
 }
 
 __global__ void k_level_reset(LevelState *st)
@@ -349,37 +391,48 @@ int64_t force_blocks(Dims d) { return force_grid(d).blocks; }
 
 hipError_t launch_force(Ctx &c, const ForceLaunch &f)
 {
+    if (f.count < 1 || f.count > kMaxBatch) return hipErrorInvalidValue;
     const ForceGrid g = force_grid(f.d);
     ForceArgs a;
-    a.S = f.S;
-    a.M = f.M;
-    a.v = f.v;
-    a.Dd = f.D;
-    a.P = f.P;
+    memset(&a, 0, sizeof a);
+    for (int r = 0; r < f.count; ++r) {
+        a.S[r] = f.S[r];
+        a.M[r] = f.M[r];
+        a.v[r] = f.v[r];
+        a.Dd[r] = f.D[r];
+        a.P[r] = f.P[r];
+        a.out[r] = f.out[r];
+        a.partials[r] = f.partials[r];
+        a.stop_at[r] = f.stop_at[r];
+        a.alpha2[r] = f.alpha2[r];
+        a.variant[r] = f.variant == kMixedVariants ? f.variants[r] : f.variant;
+    }
     a.nx = f.d.nx;
     a.ny = f.d.ny;
     a.nz = f.d.nz;
-    a.alpha2 = f.alpha2;
-    a.out = f.out;
-    a.partials = f.partials;
-    a.stop_at = f.stop_at;
     a.n = f.n;
     a.rows_per_block = g.rows_per_block;
     a.gxt = g.gxt;
+    a.blocks = (int)g.blocks;
+    ForceGrid gl = g;
+    gl.blocks = g.blocks * f.count;  // the launch: every registration's workgroups
     return timed(c, K_FORCE, [&](const Ev &ev) {
         switch (f.variant) {
-        case kPassive: launch_force_v<kPassive>(c, ev, g, a, *f.taps, f.storage); break;
-        case kEvolved: launch_force_v<kEvolved>(c, ev, g, a, *f.taps, f.storage); break;
-        case kActive: launch_force_v<kActive>(c, ev, g, a, *f.taps, f.storage); break;
-        case kDouble: launch_force_v<kDouble>(c, ev, g, a, *f.taps, f.storage); break;
-        default: launch_force_v<kInverseConsistent>(c, ev, g, a, *f.taps, f.storage); break;
+        case kPassive: launch_force_v<kPassive>(c, ev, gl, a, *f.taps, f.storage); break;
+        case kEvolved: launch_force_v<kEvolved>(c, ev, gl, a, *f.taps, f.storage); break;
+        case kActive: launch_force_v<kActive>(c, ev, gl, a, *f.taps, f.storage); break;
+        case kDouble: launch_force_v<kDouble>(c, ev, gl, a, *f.taps, f.storage); break;
+        case kInverseConsistent: launch_force_v<kInverseConsistent>(c, ev, gl, a, *f.taps, f.storage); break;
+        default: launch_force_v<kMixedVariants>(c, ev, gl, a, *f.taps, f.storage); break;
         }
     });
 }
 
 hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n)
 {
-    return timed(c, K_FINALIZE, [&](const Ev &ev) { go(c, ev, k_finalize, dim3(1), dim3(256), red, n); });
+    if (red.count < 1 || red.count > kMaxBatch) return hipErrorInvalidValue;
+    return timed(c, K_FINALIZE,
+                 [&](const Ev &ev) { go(c, ev, k_finalize, dim3((unsigned)red.count), dim3(256), red, n); });
 }
 
 hipError_t launch_level_reset(Ctx &c, LevelState *st)

@@ -1,6 +1,8 @@
 // gfx950 kernels for the image pyramid (Sec 2.3), deformed images (Sec 2.5
 // interpolation kernel), plain gradients (Sec 2.5 gradient kernel) and the
 // inverse-consistent output composition.
+#include <string.h>
+
 #include "device_common.h"
 
 namespace dir {
@@ -93,25 +95,33 @@ __global__ __launch_bounds__(256) void k_warp(const float *__restrict__ I, const
     out[i] = (float)sample64(I, make_cell_disp(x, y, z, v[i], v[N + i], v[2 * N + i], nx, ny, nz));
 }
 
+// Pre-warp of one iteration for `count` registrations of one size (a
+// lockstep batch; 1 outside batches): per-registration arguments are arrays
+// indexed by registration, and the grid holds `per` 64 x 4 workgroups (one
+// per x tile, y tile and z plane) per registration.
+struct PrewarpArgs {
+    const void *M[kMaxBatch], *S[kMaxBatch], *v[kMaxBatch];
+    void *D[kMaxBatch], *P[kMaxBatch];
+    const int *stop_at[kMaxBatch];  // skip when *stop_at < n (NULL: never)
+    int kind[kMaxBatch];            // read by the mixed instance only
+    int nx, ny, nz, gx, gy;
+    int n;
+    int per;
+};
+
 // Intensity difference for the active and double forces: D = M(x - v) - S(x),
 // sampled and subtracted in FP64, rounded once.  The force kernel takes D and
 // its gradient from here (grad Im = grad D + grad S), so the gather happens
 // once per iteration.  Buffer addressing as in the force kernel; every volume
 // in format St.
 template <class St>
-__global__ __launch_bounds__(256) void k_warp_diff(const void *__restrict__ M, const void *__restrict__ S,
-                                                   const void *__restrict__ v, int nx, int ny, int nz,
-                                                   void *__restrict__ D, int gx, int gy,
-                                                   const int *__restrict__ stop_at, int n)
+__device__ __forceinline__ void warp_diff_at(const PrewarpArgs &a, int r, int x, int y, int z)
 {
-    if (stop_at && *stop_at < n) return;
-    const Tile t = decode_tile(gx, gy);
-    const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
-    if (x >= nx || y >= ny) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
     constexpr unsigned E = St::kBytes;
     const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
-    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, nbytes), rS = make_rsrc(S, nbytes), rv = make_rsrc(v, 3u * nbytes),
-                                 rD = make_rsrc(D, nbytes);
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes), rS = make_rsrc(a.S[r], nbytes),
+                                 rv = make_rsrc(a.v[r], 3u * nbytes), rD = make_rsrc(a.D[r], nbytes);
     const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
     const float vx = St::load(rv, o, 0), vy = St::load(rv, o, nbytes), vz = St::load(rv, o, 2u * nbytes);
     const double d = bsample64<St>(rM, bcell_disp<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)St::load(rS, o, 0);
@@ -124,25 +134,60 @@ __global__ __launch_bounds__(256) void k_warp_diff(const void *__restrict__ M, c
 // (P is near twice the background intensity, where 16-bit spacing would
 // quantise the gradient the force divides by).
 template <class St>
-__global__ __launch_bounds__(256) void k_warp_pair(const void *__restrict__ M, const void *__restrict__ S,
-                                                   const void *__restrict__ h, int nx, int ny, int nz,
-                                                   void *__restrict__ D, void *__restrict__ P, int gx, int gy,
-                                                   const int *__restrict__ stop_at, int n)
+__device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x, int y, int z)
 {
-    if (stop_at && *stop_at < n) return;
-    const Tile t = decode_tile(gx, gy);
-    const int x = t.x * kBlockX + threadIdx.x, y = t.y * kBlockY + threadIdx.y, z = t.z;
-    if (x >= nx || y >= ny) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
     constexpr unsigned E = St::kBytes;
     const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
-    const __amdgpu_buffer_rsrc_t rM = make_rsrc(M, nbytes), rS = make_rsrc(S, nbytes), rh = make_rsrc(h, 3u * nbytes),
-                                 rD = make_rsrc(D, nbytes), rP = make_rsrc(P, (4u / E) * nbytes);
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes), rS = make_rsrc(a.S[r], nbytes),
+                                 rh = make_rsrc(a.v[r], 3u * nbytes), rD = make_rsrc(a.D[r], nbytes),
+                                 rP = make_rsrc(a.P[r], (4u / E) * nbytes);
     const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
     const float hx = St::load(rh, o, 0), hy = St::load(rh, o, nbytes), hz = St::load(rh, o, 2u * nbytes);
     const double im = bsample64<St>(rM, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz));
     const double is = bsample64<St>(rS, bcell_disp<E>(x, y, z, -hx, -hy, -hz, nx, ny, nz));
     St::store(rD, (float)(im - is), o, 0);
     StF32::store(rP, (float)(im + is), (4u / E) * o, 0);
+}
+
+// Workgroup -> (registration, x tile, y tile, z plane); false past the volume
+// or once the registration's level has stopped.
+__device__ __forceinline__ bool prewarp_voxel(const PrewarpArgs &a, int &r, int &x, int &y, int &z)
+{
+    const int g = xcd_logical_id(blockIdx.x, gridDim.x);
+    r = g / a.per;
+    const int lb = g - r * a.per;
+    if (a.stop_at[r] && *a.stop_at[r] < a.n) return false;
+    const int q = lb / a.gx;
+    x = (lb - q * a.gx) * kBlockX + threadIdx.x;
+    y = (q % a.gy) * kBlockY + threadIdx.y;
+    z = q / a.gy;
+    return x < a.nx && y < a.ny;
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void k_warp_diff(PrewarpArgs a)
+{
+    int r, x, y, z;
+    if (prewarp_voxel(a, r, x, y, z)) warp_diff_at<St>(a, r, x, y, z);
+}
+
+template <class St>
+__global__ __launch_bounds__(256) void k_warp_pair(PrewarpArgs a)
+{
+    int r, x, y, z;
+    if (prewarp_voxel(a, r, x, y, z)) warp_pair_at<St>(a, r, x, y, z);
+}
+
+// A batch that mixes the two kinds: each registration's kind (uniform per
+// workgroup).
+template <class St>
+__global__ __launch_bounds__(256) void k_warp_mixed(PrewarpArgs a)
+{
+    int r, x, y, z;
+    if (!prewarp_voxel(a, r, x, y, z)) return;
+    if (a.kind[r] == kPrewarpPair) warp_pair_at<St>(a, r, x, y, z);
+    else warp_diff_at<St>(a, r, x, y, z);
 }
 
 // ------------------------------------------------------------------------
@@ -319,28 +364,36 @@ hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, flo
     });
 }
 
-hipError_t launch_warp_diff(Ctx &c, const void *M, const void *S, const void *v, Dims d, void *D, int st,
-                            const int *stop_at, int n)
+hipError_t launch_prewarp(Ctx &c, const PrewarpLaunch &w)
 {
-    const Grid2 g = plane_grid(d);
-    return timed(c, K_WARP, [&](const Ev &ev) {
-        with_storage(st, [&](auto t) {
+    if (w.count < 1 || w.count > kMaxBatch) return hipErrorInvalidValue;
+    const Grid2 g = plane_grid(w.d);
+    PrewarpArgs a;
+    memset(&a, 0, sizeof a);
+    for (int r = 0; r < w.count; ++r) {
+        a.M[r] = w.M[r];
+        a.S[r] = w.S[r];
+        a.v[r] = w.v[r];
+        a.D[r] = w.D[r];
+        a.P[r] = w.P[r];
+        a.stop_at[r] = w.stop_at[r];
+        a.kind[r] = w.kind == kPrewarpMixed ? w.kinds[r] : w.kind;
+    }
+    a.nx = w.d.nx;
+    a.ny = w.d.ny;
+    a.nz = w.d.nz;
+    a.gx = g.gx;
+    a.gy = g.gy;
+    a.n = w.n;
+    a.per = (int)g.blocks;
+    const dim3 grid((unsigned)(g.blocks * w.count)), block(kBlockX, kBlockY);
+    const int k = w.kind == kPrewarpDiff ? K_WARP : (w.kind == kPrewarpPair ? K_WARP_PAIR : K_WARP_MIXED);
+    return timed(c, k, [&](const Ev &ev) {
+        with_storage(w.storage, [&](auto t) {
             using St = typename decltype(t)::type;
-            go(c, ev, k_warp_diff<St>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, v, d.nx, d.ny, d.nz, D,
-               g.gx, g.gy, stop_at, n);
-        });
-    });
-}
-
-hipError_t launch_warp_pair(Ctx &c, const void *M, const void *S, const void *h, Dims d, void *D, void *P, int st,
-                            const int *stop_at, int n)
-{
-    const Grid2 g = plane_grid(d);
-    return timed(c, K_WARP_PAIR, [&](const Ev &ev) {
-        with_storage(st, [&](auto t) {
-            using St = typename decltype(t)::type;
-            go(c, ev, k_warp_pair<St>, dim3((unsigned)g.blocks), dim3(kBlockX, kBlockY), M, S, h, d.nx, d.ny, d.nz, D,
-               P, g.gx, g.gy, stop_at, n);
+            if (w.kind == kPrewarpDiff) go(c, ev, k_warp_diff<St>, grid, block, a);
+            else if (w.kind == kPrewarpPair) go(c, ev, k_warp_pair<St>, grid, block, a);
+            else go(c, ev, k_warp_mixed<St>, grid, block, a);
         });
     });
 }

@@ -5,6 +5,8 @@
 // standalone x pass here serves dir_smooth.  The y and z passes are fused in
 // one kernel (z pass into LDS, then y pass out of LDS); each field component
 // has its own workgroups.
+#include <string.h>
+
 #include "device_common.h"
 
 namespace dir {
@@ -59,31 +61,46 @@ constexpr int max_tz()
     return (kTileY + 2 * R) * kBlockX * 4 * 8 <= 65536 ? 8 : 4;
 }
 
-// With red.partials set, workgroup 0 instead adds up the FP64 sums the force
-// kernel of this iteration left per workgroup (they are complete: that kernel
-// has finished), writes the history entry and takes the stopping decision;
-// the smoothing tiles are workgroups 1 and up.
+// One launch serves `count` registrations of one size (a lockstep batch; 1
+// outside batches): per-registration arguments are arrays indexed by
+// registration, and the grid holds `per` workgroups per registration.
+struct YZArgs {
+    const void *in[kMaxBatch];
+    void *out[kMaxBatch];
+    const int *stop_at[kMaxBatch];  // skip when *stop_at < n (NULL: never)
+    int nx, ny, nz;
+    int gx, gy, gz;                 // x tiles, y tiles, z chunks
+    int n;
+    int per;                        // workgroups per registration
+};
+
+// With red.count set, the first workgroup of each registration instead adds
+// up the FP64 sums the force kernel of this iteration left per workgroup
+// (they are complete: that kernel has finished), writes the history entry and
+// takes the stopping decision; the smoothing tiles follow it.
 template <int R, int TZ, class St>
-__global__ __launch_bounds__(256) void k_smooth_yz(const void *__restrict__ in, void *__restrict__ out, int nx,
-                                                   int ny, int nz, GaussTaps taps, int gx, int gy, int gz,
-                                                   const int *__restrict__ stop_at, int n, SumsReduce red)
+__global__ __launch_bounds__(256) void k_smooth_yz(YZArgs a, GaussTaps taps, SumsReduce red)
 {
     constexpr int ROWS = YZTile<R, TZ>::ROWS;
     __shared__ float zs[TZ][ROWS][kBlockX];
-    if (stop_at && *stop_at < n) return;
+    // workgroup id -> (registration, z chunk, y tile, x tile, component),
+    // numbered so that each XCD runs one contiguous range with z chunks
+    // fastest, then y tiles: the tiles an XCD has in flight at once form a
+    // compact (y, z) block of one x column, whose shared 2R halo planes and
+    // rows are then served from that XCD's L2.
+    const int g = xcd_logical_id(blockIdx.x, gridDim.x);
+    const int reg = g / a.per, lb = g - reg * a.per;  // wave-uniform
+    if (a.stop_at[reg] && *a.stop_at[reg] < a.n) return;
     const int tid = threadIdx.x + kBlockX * threadIdx.y;
-    if (red.partials && blockIdx.x == 0) {
-        reduce_sums(red.partials, red.nb, red.hist, n, red.st, red.eps, red.inv_n, tid);
+    if (red.count && lb == 0) {
+        reduce_sums(red.partials[reg], red.nb, red.hist[reg], a.n, red.st[reg], red.eps[reg], red.inv_n, tid);
         return;
     }
-    // workgroup id -> (z chunk, y tile, x tile, component), numbered so that
-    // each XCD runs one contiguous range with z chunks fastest, then y tiles:
-    // the tiles an XCD has in flight at once form a compact (y, z) block of
-    // one x column, whose shared 2R halo planes and rows are then served from
-    // that XCD's L2.  Workgroup 0 has logical id 0, so with a reducer the
-    // tiles are ids 1 and up.
-    const int b = xcd_logical_id(blockIdx.x, gridDim.x) - (red.partials ? 1 : 0);
+    const int nx = a.nx, ny = a.ny, nz = a.nz, gx = a.gx, gy = a.gy, gz = a.gz;
+    const int b = lb - (red.count ? 1 : 0);
     const int tz = b % gz, r1 = b / gz, ty = r1 % gy, r2 = r1 / gy, tx = r2 % gx, c = r2 / gx;
+    const void *const in = a.in[reg];
+    void *const out = a.out[reg];
     // threadIdx.y is the wavefront index (64 x 4 workgroup): uniform, which
     // lets the row offsets below live in scalar registers
     const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
@@ -158,13 +175,15 @@ __global__ __launch_bounds__(256) void k_smooth_yz(const void *__restrict__ in, 
 }
 
 template <int R, int TZ, class St>
-void launch_yz_tz(Ctx &c, const Ev &ev, const void *in, void *out, int ncomp, Dims d, const GaussTaps &taps,
-                  const int *stop_at, int n, const SumsReduce &red)
+void launch_yz_tz(Ctx &c, const Ev &ev, YZArgs a, int ncomp, int count, const GaussTaps &taps,
+                  const SumsReduce &red)
 {
-    const int gx = ceil_div(d.nx, kBlockX), gy = ceil_div(d.ny, kTileY), gz = ceil_div(d.nz, TZ);
-    const int64_t blocks = (int64_t)gx * gy * gz * ncomp + (red.partials ? 1 : 0);
-    go(c, ev, (k_smooth_yz<R, TZ, St>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), in, out,
-                       d.nx, d.ny, d.nz, taps, gx, gy, gz, stop_at, n, red);
+    a.gx = ceil_div(a.nx, kBlockX);
+    a.gy = ceil_div(a.ny, kTileY);
+    a.gz = ceil_div(a.nz, TZ);
+    a.per = a.gx * a.gy * a.gz * ncomp + (red.count ? 1 : 0);
+    const int64_t blocks = (int64_t)a.per * count;
+    go(c, ev, (k_smooth_yz<R, TZ, St>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), a, taps, red);
 }
 
 // Workgroups to aim for before the z chunk is made deeper (each chunk re-reads
@@ -172,27 +191,27 @@ void launch_yz_tz(Ctx &c, const Ev &ev, const void *in, void *out, int ncomp, Di
 constexpr int64_t kYZTargetBlocks = 1024;
 
 template <int R, class St>
-hipError_t launch_yz_r(Ctx &c, const void *in, void *out, int ncomp, Dims d, const GaussTaps &taps,
-                       const int *stop_at, int n, const SumsReduce &red)
+hipError_t launch_yz_r(Ctx &c, const YZArgs &a, int ncomp, int count, const GaussTaps &taps, const SumsReduce &red)
 {
-    const int64_t tiles = (int64_t)ceil_div(d.nx, kBlockX) * ceil_div(d.ny, kTileY) * ncomp;
-    const bool deep = max_tz<R>() == 8 && tiles * ceil_div(d.nz, 8) >= kYZTargetBlocks;
+    // the depth choice depends on the tiles of one registration
+    const int64_t tiles = (int64_t)ceil_div(a.nx, kBlockX) * ceil_div(a.ny, kTileY) * ncomp;
+    const bool deep = max_tz<R>() == 8 && tiles * ceil_div(a.nz, 8) >= kYZTargetBlocks;
     return timed(c, K_SMOOTH_YZ, [&](const Ev &ev) {
-        if (deep) launch_yz_tz<R, max_tz<R>(), St>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
-        else if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4, St>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
-        else launch_yz_tz<R, 2, St>(c, ev, in, out, ncomp, d, taps, stop_at, n, red);
+        if (deep) launch_yz_tz<R, max_tz<R>(), St>(c, ev, a, ncomp, count, taps, red);
+        else if (tiles * ceil_div(a.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4, St>(c, ev, a, ncomp, count, taps, red);
+        else launch_yz_tz<R, 2, St>(c, ev, a, ncomp, count, taps, red);
     });
 }
 
 }  // namespace
 
 template <class St>
-hipError_t launch_smooth_yz_st(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out,
-                               const int *stop_at, int n, const SumsReduce &red)
+hipError_t launch_smooth_yz_st(Ctx &c, const YZArgs &a, int ncomp, int count, const GaussTaps &taps,
+                               const SumsReduce &red)
 {
     switch (taps.radius) {
 #define DIR_R(r) \
-    case r: return launch_yz_r<r, St>(c, in, out, ncomp, d, taps, stop_at, n, red);
+    case r: return launch_yz_r<r, St>(c, a, ncomp, count, taps, red);
         DIR_R(0) DIR_R(1) DIR_R(2) DIR_R(3) DIR_R(4) DIR_R(5) DIR_R(6) DIR_R(7) DIR_R(8)
         DIR_R(9) DIR_R(10) DIR_R(11) DIR_R(12) DIR_R(13) DIR_R(14) DIR_R(15) DIR_R(16)
 #undef DIR_R
@@ -200,12 +219,24 @@ hipError_t launch_smooth_yz_st(Ctx &c, const void *in, int ncomp, Dims d, const 
     }
 }
 
-hipError_t launch_smooth_yz(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out, int st,
-                            const int *stop_at, int n, const SumsReduce &red)
+hipError_t launch_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, Dims d, const GaussTaps &taps,
+                            void *const *out, int st, const int *const *stop_at, int n, const SumsReduce &red)
 {
-    if (st == kStoreF16) return launch_smooth_yz_st<StF16>(c, in, ncomp, d, taps, out, stop_at, n, red);
-    if (st == kStoreBF16) return launch_smooth_yz_st<StBF16>(c, in, ncomp, d, taps, out, stop_at, n, red);
-    return launch_smooth_yz_st<StF32>(c, in, ncomp, d, taps, out, stop_at, n, red);
+    if (count < 1 || count > kMaxBatch || (red.count && red.count != count)) return hipErrorInvalidValue;
+    YZArgs a;
+    memset(&a, 0, sizeof a);
+    for (int r = 0; r < count; ++r) {
+        a.in[r] = in[r];
+        a.out[r] = out[r];
+        a.stop_at[r] = stop_at[r];
+    }
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.n = n;
+    if (st == kStoreF16) return launch_smooth_yz_st<StF16>(c, a, ncomp, count, taps, red);
+    if (st == kStoreBF16) return launch_smooth_yz_st<StBF16>(c, a, ncomp, count, taps, red);
+    return launch_smooth_yz_st<StF32>(c, a, ncomp, count, taps, red);
 }
 
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out)

@@ -1,0 +1,157 @@
+"""Lockstep batches (dir_register_batch): several registrations of one volume
+size run every iteration as one pre-warp, one force and one smoothing launch.
+Each field, its iteration counts and its per-iteration history must be bitwise
+those of the same registration run alone with dir_register (the kernels, their
+arithmetic and the order of every sum are the same), and the batch must refuse
+registrations that cannot run in lockstep."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_0909_0928_amd import phantom as P
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_0909_0928_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def h(B):
+    hh = B.dir_create(0)
+    yield hh
+    B.dir_destroy(hh)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).cuda()
+
+
+def _pairs(shape, count, seed):
+    out = []
+    for k in range(count):
+        ph = P.make_phantom(shape, seed=seed + k, max_u=2.5)
+        out.append((_dev(ph.static), _dev(ph.moving)))
+    return out
+
+
+# the six force settings of the benchmark: every kind of pre-warp and a mixed force launch
+SIX = [("passive", 1.0), ("active", 1.0), ("double", 1.0), ("passive", 0.4), ("inverse_consistent", 1.0),
+       ("double", 0.4)]
+
+
+def _alone(B, h, pairs, params):
+    res = []
+    for (S, M), p in zip(pairs, params):
+        f, st = B.dir_register(h, S, M, p)
+        res.append((f.clone(), st))
+    return res
+
+
+def _check_equal(batch, alone):
+    for k, ((fb, sb), (fa, sa)) in enumerate(zip(batch, alone)):
+        assert torch.equal(fb, fa), k
+        assert sb["iters_run"] == sa["iters_run"], k
+        # every FP64 sum bitwise (the relative norm is NaN while the field is zero)
+        assert np.array_equal(np.array(sb["history"]), np.array(sa["history"]), equal_nan=True), k
+        assert np.array_equal([sb["mse_final"], sb["relnorm_final"]], [sa["mse_final"], sa["relnorm_final"]],
+                              equal_nan=True), k
+
+
+# (shape xyz, iterations coarse to fine, storage): several force tiles, ragged edges in x, y and z
+CASES = [((67, 45, 19), [6, 5, 4], "f32"),
+         ((48, 40, 12), [5, 3], "f32"),
+         ((130, 33, 21), [4, 3], "f32"),
+         ((40, 36, 20), [5, 4], "f16"),
+         ((36, 28, 14), [4, 4], "bf16")]
+
+
+@pytest.mark.parametrize("shape,iters,storage", CASES)
+def test_mixed_batch_equals_alone(B, h, shape, iters, storage):
+    pairs = _pairs(shape, len(SIX), 700)
+    params = [B.make_params(v, iters, sigma=1.0, alpha=a, storage=storage) for v, a in SIX]
+    alone = _alone(B, h, pairs, params)
+    for _ in range(2):  # the second call reuses the batch workspace
+        batch = B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params)
+        _check_equal(batch, alone)
+
+
+@pytest.mark.parametrize("variant", ["passive", "evolved", "active", "double", "inverse_consistent"])
+def test_uniform_batch_equals_alone(B, h, variant):
+    pairs = _pairs((45, 38, 17), 3, 750)
+    params = [B.make_params(variant, [5, 4], sigma=1.5, alpha=a) for a in (1.0, 0.7, 0.4)]
+    _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params),
+                 _alone(B, h, pairs, params))
+
+
+def test_batch_of_one_and_of_eight(B, h):
+    pairs = _pairs((33, 30, 11), B.DIR_MAX_BATCH, 780)
+    params = [B.make_params(SIX[k % len(SIX)][0], [4, 3], sigma=1.0, alpha=SIX[k % len(SIX)][1])
+              for k in range(B.DIR_MAX_BATCH)]
+    alone = _alone(B, h, pairs, params)
+    _check_equal(B.dir_register_batch(h, [pairs[0][0]], [pairs[0][1]], params[:1]), alone[:1])
+    _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
+
+
+def test_batch_stopping_rule_per_registration(B, h):
+    # eps differs per registration: the stopped ones skip their remaining
+    # iterations inside the batch, as a lone registration stops early
+    pairs = _pairs((40, 32, 16), 4, 800)
+    eps = [0.0, 1e-3, 1e-4, 0.5]
+    params = [B.make_params("passive", [30, 25], sigma=1.0, eps=e) for e in eps]
+    alone = _alone(B, h, pairs, params)
+    assert any(st["iters_run"] != [30, 25] for _, st in alone)  # the rule fired somewhere
+    _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
+
+
+def test_batch_same_inputs_for_every_setting(B, h):
+    # the benchmark's form: one pair registered under six settings
+    (S, M), = _pairs((64, 48, 24), 1, 820)
+    params = [B.make_params(v, [6, 4, 3], sigma=1.5, alpha=a) for v, a in SIX]
+    alone = _alone(B, h, [(S, M)] * len(SIX), params)
+    _check_equal(B.dir_register_batch(h, [S] * len(SIX), [M] * len(SIX), params), alone)
+
+
+def test_batch_refuses_what_cannot_run_in_lockstep(B, h):
+    pairs = _pairs((32, 24, 10), 2, 840)
+    Ss, Ms = [S for S, _ in pairs], [M for _, M in pairs]
+    p0 = B.make_params("passive", [4, 3], sigma=1.0)
+    bad = [B.make_params("passive", [4, 2], sigma=1.0),             # other iterations
+           B.make_params("passive", [4, 3], sigma=1.5),             # other sigma
+           B.make_params("passive", [7], sigma=1.0),                # other levels
+           B.make_params("passive", [4, 3], sigma=1.0, storage="f16")]
+    for p1 in bad:
+        with pytest.raises(B.DemonsError) as e:
+            B.dir_register_batch(h, Ss, Ms, [p0, p1])
+        assert e.value.code == B.DIR_EINVAL
+    shared = torch.empty((3,) + tuple(Ss[0].shape), device="cuda")
+    with pytest.raises(B.DemonsError) as e:                         # one output field for both
+        B.dir_register_batch(h, Ss, Ms, [p0, p0], field_outs=[shared, shared])
+    assert e.value.code == B.DIR_EINVAL
+    # more than the batch limit, through the C ABI directly
+    n = B.DIR_MAX_BATCH + 1
+    arr = (ctypes.c_void_p * n)(*([Ss[0].data_ptr()] * n))
+    outs = [torch.empty_like(shared) for _ in range(n)]
+    parr = (B.dir_params * n)(*([p0] * n))
+    rc = B.lib().dir_register_batch(h.ptr, n, arr, arr, 32, 24, 10, None, parr,
+                                    (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs]), None)
+    assert rc == B.DIR_EINVAL
+    # the handle still works
+    f, _ = B.dir_register(h, Ss[0], Ms[0], p0)
+    assert torch.isfinite(f).all()
+
+
+def test_batch_at_the_benchmark_size(B, h):
+    # 256 x 256 x 100 with its three levels, in the launch configuration the
+    # benchmark times: the six settings in one batch against each alone
+    ph = P.make_phantom((256, 256, 100), seed=2, max_u=15.0)  # the benchmark's pair
+    S, M = _dev(ph.static), _dev(ph.moving)
+    params = [B.make_params(v, [100, 50, 25], sigma=1.5, alpha=a) for v, a in SIX]
+    alone = _alone(B, h, [(S, M)] * len(SIX), params)
+    _check_equal(B.dir_register_batch(h, [S] * len(SIX), [M] * len(SIX), params), alone)
