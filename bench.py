@@ -308,7 +308,9 @@ def _phantoms(jobs):
 def batch32(args):
     """32 independent inverse-consistent pairs of uneven sizes (x, y uniform in
     128..256, z in 64..128; seeds 1000 + i), 3 levels, 100/50/25 iterations:
-    all submitted at once to a request pool, against one after another."""
+    all submitted at once to a request pool; as four lockstep batches of 8 in
+    submission order, on one stream and split over two; and one after
+    another."""
     import torch
     from paper_0909_0928_amd import binding as B
     rng = np.random.default_rng(1000)
@@ -338,16 +340,40 @@ def batch32(args):
         res.update({"pool_slots": args.slots, "pool_seconds": dt, "pool_voxel_iter_per_s": vi / dt,
                     "pool_peak_running": pool.stats()["peak_running"]})
     h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))
-    for a, b, o in zip(S, M, outs):
-        B.dir_register(h, a, b, params, field_out=o, history=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for a, b, o in zip(S, M, outs):
-        B.dir_register(h, a, b, params, field_out=o, history=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    B.dir_destroy(h)
-    res.update({"sequential_seconds": dt, "sequential_voxel_iter_per_s": vi / dt, "speedup": dt / res["pool_seconds"]})
+    groups = [list(range(k, min(k + B.DIR_MAX_BATCH, len(S)))) for k in range(0, len(S), B.DIR_MAX_BATCH)]
+    hb = [B.dir_create(0, stream=torch.cuda.Stream(device=dev)) for _ in range(2)]
+
+    def run_batches(handle, gs):
+        for g in gs:
+            B.dir_register_batch(handle, [S[i] for i in g], [M[i] for i in g], [params] * len(g),
+                                 field_outs=[outs[i] for i in g], history=False)
+
+    def run_batches_two_streams():
+        import threading
+        ts = [threading.Thread(target=run_batches, args=(hb[k], groups[k::2])) for k in range(2)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+
+    def run_sequential():
+        for a, b, o in zip(S, M, outs):
+            B.dir_register(h, a, b, params, field_out=o, history=False)
+
+    for name, fn in (("batches", lambda: run_batches(hb[0], groups)), ("batches_two_streams", run_batches_two_streams),
+                     ("sequential", run_sequential)):
+        fn()                                          # warm-up: workspaces grow to their sizes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res.update({f"{name}_seconds": dt, f"{name}_voxel_iter_per_s": vi / dt})
+    for hh in [h] + hb:
+        B.dir_destroy(hh)
+    res["batch_size"] = B.DIR_MAX_BATCH
+    res["speedup"] = res["sequential_seconds"] / min(res["pool_seconds"], res["batches_seconds"],
+                                                     res["batches_two_streams_seconds"])
     print(json.dumps(res))
 
 

@@ -243,30 +243,33 @@ int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, 
 int32_t dir_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const dir_params *params, uint64_t *bytes);
 
 /* Lockstep batch (the iteration of Sec 2.4 and the pyramid of Sec 2.3, run
- * for several pairs at once): `count` (1..DIR_MAX_BATCH) registrations of
- * volumes of one size, given as host arrays of device pointers d_static[r],
- * d_moving[r] and d_field_out[r] and a host array params[r].  The
- * registrations must agree in levels, iterations per level, sigma, radius
- * and storage; variant, alpha, eps and compose_iters may differ.
+ * for several pairs at once): `count` (1..DIR_MAX_BATCH) registrations given
+ * as host arrays of device pointers d_static[r], d_moving[r] and
+ * d_field_out[r], their sizes dims[3r], dims[3r+1], dims[3r+2] (nx, ny, nz;
+ * they may differ), spacing_mm (NULL, or three values per registration, only
+ * validated as in dir_register) and params[r].  The registrations must agree
+ * in levels, iterations per level, sigma, radius and storage; size, variant,
+ * alpha, eps and compose_iters may differ.
  *
  * On a pyramid level whose images and fields, over all `count`
  * registrations, fit the device's 256 MB last-level cache (about 8 stored
  * values per voxel each), every iteration of all of them runs as one
  * pre-warp launch (for the variants that have one), one force launch and one
- * smoothing launch: the short, latency-bound launches of coarse levels then
- * carry `count` times the work.  A larger level streams from HBM either way
- * and runs registration by registration, so that each kernel finds the field
- * the previous one wrote still in that cache.
+ * smoothing launch (one per tile class when sizes differ: each registration
+ * keeps the workgroup layout it has alone): the short, latency-bound launches
+ * of coarse levels then carry the work of the whole batch.  A larger level
+ * streams from HBM either way and runs registration by registration, so that
+ * each kernel finds the field the previous one wrote still in that cache.
  *
  * Each field, its iteration counts and its history are bitwise those
  * dir_register computes alone.  Output fields must be distinct and must not
  * overlap any input.  stats: NULL or an array of `count` (each with
  * struct_size set); DIR_ENUMERIC if any registration's sums turn non-finite.
- * The workspace holds `count` registrations' worth.  Blocks until complete. */
+ * The workspace holds `count` registrations' worth of the largest.  Blocks
+ * until complete. */
 int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_static,
-                           const float *const *d_moving, int32_t nx, int32_t ny, int32_t nz,
-                           const double *spacing_mm, const dir_params *params, float *const *d_field_out,
-                           dir_stats *stats);
+                           const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
+                           const dir_params *params, float *const *d_field_out, dir_stats *stats);
 
 /* Request pool (serving).  A pool runs submitted registrations on `slots`
  * handles of its own, each with its own stream, so registrations that arrive

@@ -81,7 +81,7 @@ def lib():
         L.dir_step.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_step_stored.argtypes = [vp, i32, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
-        L.dir_register_batch.argtypes = [vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, vp]
+        L.dir_register_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.dir_wait.argtypes = [vp, vp]
         L.dir_set_graphs.argtypes = [vp, i32]
         L.dir_similarity.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
@@ -290,22 +290,25 @@ def dir_register(h, static, moving, params, field_out=None, spacing_mm=None, his
 
 
 def dir_register_batch(h, statics, movings, params, field_outs=None, spacing_mm=None, history=True):
-    """Lockstep batch of len(statics) registrations of one volume size (at
-    most DIR_MAX_BATCH); `params` is a list of dir_params that agree in
-    levels, iterations, sigma, radius and storage.  Returns a list of
-    (field, stats dict), each field bitwise the one dir_register computes."""
+    """Lockstep batch of len(statics) registrations (at most DIR_MAX_BATCH),
+    of any sizes; `params` is a list of dir_params that agree in levels,
+    iterations, sigma, radius and storage; `spacing_mm` is None or one triple
+    per registration.  Returns a list of (field, stats dict), each field
+    bitwise the one dir_register computes."""
     count = len(statics)
     if not 1 <= count <= DIR_MAX_BATCH or len(movings) != count or len(params) != count:
         raise ValueError(f"1..{DIR_MAX_BATCH} registrations, with one moving image and one dir_params each")
     if field_outs is None:
         field_outs = [None] * count
-    outs, sp = [], None
+    if spacing_mm is not None and len(spacing_mm) != count:
+        raise ValueError("spacing_mm: one (x, y, z) triple per registration")
+    outs, dims = [], []
     for k in range(count):
-        if statics[k].shape != statics[0].shape:
-            raise ValueError("every registration of a batch has the same volume size")
-        o, sp = _register_args(statics[k], movings[k], params[k], field_outs[k], spacing_mm)
+        o, _ = _register_args(statics[k], movings[k], params[k], field_outs[k], None)
         outs.append(o)
-    nx, ny, nz = _dims(statics[0])
+        dims.extend(_dims(statics[k]))
+    sp = (ctypes.c_double * (3 * count))(*[float(v) for t in spacing_mm for v in t]) if spacing_mm is not None \
+        else None
     if h.stream is not None and h.stream != torch.cuda.current_stream(h.device):
         h.stream.wait_stream(torch.cuda.current_stream(h.device))
     ptrs = lambda ts: (ctypes.c_void_p * count)(*[t.data_ptr() for t in ts])
@@ -316,8 +319,8 @@ def dir_register_batch(h, statics, movings, params, field_outs=None, spacing_mm=
         sts.append(st)
         bufs.append(buf)
     sarr = (dir_stats * count)(*sts)
-    rc = lib().dir_register_batch(h.ptr, count, ptrs(statics), ptrs(movings), nx, ny, nz, sp, parr, ptrs(outs),
-                                  sarr)
+    rc = lib().dir_register_batch(h.ptr, count, ptrs(statics), ptrs(movings), (ctypes.c_int32 * (3 * count))(*dims),
+                                  sp, parr, ptrs(outs), sarr)
     res = [(outs[k], _stats_dict(rc, sarr[k], bufs[k])) for k in range(count)]
     if rc != DIR_OK:
         raise DemonsError(rc, "dir_register_batch")

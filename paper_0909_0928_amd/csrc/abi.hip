@@ -483,11 +483,12 @@ GaussTaps identity_taps()
     return t;
 }
 
-// One iteration's force half for `count` registrations of one size (arrays
-// indexed by registration).
+// One iteration's force half for `count` registrations (arrays indexed by
+// registration).
 struct ForceHalf {
     int count = 1;
     int storage;
+    Dims d[kMaxBatch];
     int variant[kMaxBatch];
     float alpha2[kMaxBatch];
     const void *S[kMaxBatch], *M[kMaxBatch], *v[kMaxBatch];
@@ -500,12 +501,11 @@ struct ForceHalf {
 // The force half of one iteration: one pre-warp launch for the registrations
 // whose variant needs deformed-image gradients, then one force launch (u =
 // v + dr, x pass of the smoothing with `taps`, per-workgroup sums).
-hipError_t force_half(Ctx &c, const ForceHalf &b, Dims d, const GaussTaps &taps, int n)
+hipError_t force_half(Ctx &c, const ForceHalf &b, const GaussTaps &taps, int n)
 {
     PrewarpLaunch w;
     w.count = 0;
     w.storage = b.storage;
-    w.d = d;
     w.n = n;
     unsigned kinds = 0;
     for (int r = 0; r < b.count; ++r) {
@@ -521,6 +521,7 @@ hipError_t force_half(Ctx &c, const ForceHalf &b, Dims d, const GaussTaps &taps,
         w.D[q] = b.D[r];
         w.P[q] = b.P[r];
         w.stop_at[q] = b.stop_at[r];
+        w.d[q] = b.d[r];
     }
     if (w.count) {
         w.kind = kinds == (1u << kPrewarpDiff) ? kPrewarpDiff
@@ -543,9 +544,9 @@ hipError_t force_half(Ctx &c, const ForceHalf &b, Dims d, const GaussTaps &taps,
         f.out[r] = b.out[r];
         f.partials[r] = b.partials[r];
         f.stop_at[r] = b.stop_at[r];
+        f.d[r] = b.d[r];
     }
     f.storage = b.storage;
-    f.d = d;
     f.taps = &taps;
     f.n = n;
     return launch_force(c, f);
@@ -557,11 +558,11 @@ SumsReduce sums_reduce_one(double *partials, Dims d, double *hist, LevelState *s
     SumsReduce r;
     r.count = 1;
     r.partials[0] = partials;
-    r.nb = (int)force_blocks(d);
+    r.nb[0] = (int)force_blocks(d);
     r.hist[0] = hist;
     r.st[0] = st;
     r.eps[0] = eps;
-    r.inv_n = 1.0 / (double)d.n();
+    r.inv_n[0] = 1.0 / (double)d.n();
     return r;
 }
 
@@ -608,9 +609,10 @@ int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, co
     LevelState *st = h->state.as<LevelState>();
     DIR_TRY(launch_level_reset(c, st));
     SumsReduce red = sums_reduce_one(h->partials.as<double>(), d, h->history.as<double>(), st, 0.0);
-    red.inv_n = 1.0;  // report the plain sum of D^2
+    red.inv_n[0] = 1.0;  // report the plain sum of D^2
     ForceHalf fh;
     fh.storage = storage;
+    fh.d[0] = d;
     fh.variant[0] = variant;
     fh.alpha2[0] = (float)(alpha * alpha);
     fh.S[0] = Sx;
@@ -622,12 +624,12 @@ int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, co
     fh.stop_at[0] = nullptr;
     if (taps) {
         fh.out[0] = h->field[2].p;
-        DIR_TRY(force_half(c, fh, d, *taps, 0));
+        DIR_TRY(force_half(c, fh, *taps, 0));
         DIR_TRY(launch_smooth_yz(c, h->field[2].p, 3, d, *taps, fout, storage, nullptr, 0, red));
     } else {
         const GaussTaps id = identity_taps();
         fh.out[0] = fout;
-        DIR_TRY(force_half(c, fh, d, id, 0));
+        DIR_TRY(force_half(c, fh, id, 0));
         DIR_TRY(launch_finalize(c, red, 0));
     }
     if (conv) DIR_TRY(launch_convert(c, fout, storage, out, kStoreF32, 3 * (int64_t)n));
@@ -712,10 +714,10 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
 
 namespace {
 
-// Everything one registration, or a lockstep batch of registrations of one
-// size, needs to enqueue its kernels: validated arguments (arrays indexed by
-// registration), level sizes, the history layout and the workspace strides
-// between registrations.
+// Everything one registration, or a lockstep batch of registrations, needs to
+// enqueue its kernels: validated arguments and level sizes (arrays indexed by
+// registration), the history layout and the workspace strides between
+// registrations.
 struct RegSizes {
     size_t pyr, img0, field, img_a, img_b, partials, history, state;
     size_t total() const { return 2 * pyr + 2 * img0 + 2 * field + img_a + img_b + partials + history + state; }
@@ -728,9 +730,9 @@ struct RegPlan {
     int variant[kMaxBatch], K[kMaxBatch];
     float alpha2[kMaxBatch];
     double eps[kMaxBatch];
+    Dims dims[kMaxBatch][DIR_MAX_LEVELS];  // level sizes, finest first
     int storage, L;
     GaussTaps taps;
-    Dims dims[DIR_MAX_LEVELS];
     int iters[DIR_MAX_LEVELS];
     int64_t total_iters;
     int64_t hist_off[DIR_MAX_LEVELS];
@@ -838,8 +840,10 @@ extern "C" int32_t dir_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const
 namespace {
 
 // Fill the per-registration entries r of a plan from p (validated).
-void plan_entry(RegPlan &pl, int r, const float *S, const float *M, float *out, const dir_params *p)
+void plan_entry(RegPlan &pl, int r, const float *S, const float *M, float *out, Dims d, const dir_params *p)
 {
+    pl.dims[r][0] = d;
+    for (int k = 1; k < p->levels; ++k) pl.dims[r][k] = coarser(pl.dims[r][k - 1]);
     pl.S[r] = S;
     pl.M[r] = M;
     pl.out[r] = out;
@@ -850,13 +854,11 @@ void plan_entry(RegPlan &pl, int r, const float *S, const float *M, float *out, 
 }
 
 // The parts of a plan every registration of a batch shares (from p).
-void plan_shared(RegPlan &pl, int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
+void plan_shared(RegPlan &pl, const dir_params *p)
 {
     pl.storage = p->storage;
     pl.L = p->levels;
     pl.taps = make_taps(p->sigma, resolve_radius(p->sigma, p->radius));
-    pl.dims[0] = Dims{nx, ny, nz};
-    for (int k = 1; k < pl.L; ++k) pl.dims[k] = coarser(pl.dims[k - 1]);
     int64_t off = 0;
     for (int k = 0; k < pl.L; ++k) {
         pl.iters[k] = p->iters[k];  // coarsest first
@@ -864,6 +866,13 @@ void plan_shared(RegPlan &pl, int32_t nx, int32_t ny, int32_t nz, const dir_para
         off += p->iters[k];
     }
     pl.total_iters = off;
+}
+
+// Whether two float ranges of na and nb elements share memory.
+bool overlap(const float *a, size_t na, const float *b, size_t nb)
+{
+    const char *pa = reinterpret_cast<const char *>(a), *pb = reinterpret_cast<const char *>(b);
+    return pa < pb + sizeof(float) * nb && pb < pa + sizeof(float) * na;
 }
 
 // The output field must not overlap either input.
@@ -913,8 +922,8 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     DIR_TRY(h->state.ensure(z.state));
 
     pl.count = 1;
-    plan_shared(pl, nx, ny, nz, p);
-    plan_entry(pl, 0, d_static, d_moving, d_field_out, p);
+    plan_shared(pl, p);
+    plan_entry(pl, 0, d_static, d_moving, d_field_out, Dims{nx, ny, nz}, p);
     pl.stride = z;
     return DIR_OK;
 }
@@ -923,32 +932,35 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Validate a lockstep batch and size the workspace for it: `count`
-// registrations of one volume size whose parameters agree in everything the
-// iteration schedule and the smoothing depend on (levels, iterations per
-// level, sigma, radius, storage); variant, alpha, eps and the composition
-// steps may differ.
-int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float *const *M, int32_t nx, int32_t ny,
-               int32_t nz, const double *spacing_mm, const dir_params *p, float *const *out, RegPlan &pl)
+// registrations, of sizes dims[3r .. 3r+2] (nx, ny, nz), whose parameters
+// agree in everything the iteration schedule and the smoothing depend on
+// (levels, iterations per level, sigma, radius, storage); size, variant,
+// alpha, eps and the composition steps may differ.  spacing_mm: NULL or
+// three values per registration.
+int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float *const *M, const int32_t *dims,
+               const double *spacing_mm, const dir_params *p, float *const *out, RegPlan &pl)
 {
-    if (count < 1 || count > DIR_MAX_BATCH || !S || !M || !p || !out) return DIR_EINVAL;
-    if (!spacing_ok(spacing_mm)) return DIR_EINVAL;
-    const size_t n = (size_t)((int64_t)nx * ny * nz);
+    if (count < 1 || count > DIR_MAX_BATCH || !S || !M || !dims || !p || !out) return DIR_EINVAL;
+    size_t n[kMaxBatch];
     RegSizes z{};
     for (int r = 0; r < count; ++r) {
+        const int32_t nx = dims[3 * r], ny = dims[3 * r + 1], nz = dims[3 * r + 2];
         if (!S[r] || !M[r] || !out[r]) return DIR_EINVAL;
         const int rc = check_register_params(nx, ny, nz, &p[r]);
         if (rc != DIR_OK) return rc;
+        if (spacing_mm && !spacing_ok(spacing_mm + 3 * r)) return DIR_EINVAL;
         if (p[r].levels != p[0].levels || p[r].sigma != p[0].sigma || p[r].storage != p[0].storage ||
             resolve_radius(p[r].sigma, p[r].radius) != resolve_radius(p[0].sigma, p[0].radius))
             return DIR_EINVAL;
         for (int l = 0; l < p[0].levels; ++l)
             if (p[r].iters[l] != p[0].iters[l]) return DIR_EINVAL;
-        if (!disjoint_io(S[r], M[r], out[r], n)) return DIR_EINVAL;
-        const char *o = reinterpret_cast<const char *>(out[r]);
-        for (int q = 0; q < r; ++q) {  // every registration writes a field of its own
-            const char *oq = reinterpret_cast<const char *>(out[q]);
-            if (o < oq + 3 * sizeof(float) * n && oq < o + 3 * sizeof(float) * n) return DIR_EINVAL;
-            if (!disjoint_io(S[q], M[q], out[r], n) || !disjoint_io(S[r], M[r], out[q], n)) return DIR_EINVAL;
+        n[r] = (size_t)((int64_t)nx * ny * nz);
+        if (!disjoint_io(S[r], M[r], out[r], n[r])) return DIR_EINVAL;
+        for (int q = 0; q < r; ++q) {  // every registration writes a field of its own, read by no other
+            if (overlap(out[r], 3 * n[r], out[q], 3 * n[q]) || overlap(out[r], 3 * n[r], S[q], n[q]) ||
+                overlap(out[r], 3 * n[r], M[q], n[q]) || overlap(out[q], 3 * n[q], S[r], n[r]) ||
+                overlap(out[q], 3 * n[q], M[r], n[r]))
+                return DIR_EINVAL;
         }
         const RegSizes zr = register_sizes(nx, ny, nz, &p[r]);
         z.pyr = std::max(z.pyr, align256(zr.pyr));
@@ -978,8 +990,9 @@ int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float 
     DIR_TRY(h->state.ensure(c * z.state));
 
     pl.count = count;
-    plan_shared(pl, nx, ny, nz, &p[0]);
-    for (int r = 0; r < count; ++r) plan_entry(pl, r, S[r], M[r], out[r], &p[r]);
+    plan_shared(pl, &p[0]);
+    for (int r = 0; r < count; ++r)
+        plan_entry(pl, r, S[r], M[r], out[r], Dims{dims[3 * r], dims[3 * r + 1], dims[3 * r + 2]}, &p[r]);
     pl.stride = z;
     return DIR_OK;
 }
@@ -1000,9 +1013,9 @@ T *part(const DevBuf &b, size_t stride, int r)
 // launch carrying every registration's data would have evicted.
 constexpr size_t kLockstepBytes = size_t(256) << 20;
 
-bool lockstep_level(int count, Dims d, size_t es)
+bool lockstep_level(int count, int64_t voxels, size_t es)
 {
-    return count == 1 || (size_t)count * 8 * es * (size_t)d.n() <= kLockstepBytes;
+    return count == 1 || 8 * es * (size_t)voxels <= kLockstepBytes;
 }
 
 // Registration r of a batch's iteration descriptors, as a batch of one.
@@ -1011,6 +1024,7 @@ ForceHalf one_of(const ForceHalf &b, int r)
     ForceHalf o;
     o.count = 1;
     o.storage = b.storage;
+    o.d[0] = b.d[r];
     o.variant[0] = b.variant[r];
     o.alpha2[0] = b.alpha2[r];
     o.S[0] = b.S[r];
@@ -1032,6 +1046,8 @@ SumsReduce one_of(const SumsReduce &b, int r)
     o.hist[0] = b.hist[r];
     o.st[0] = b.st[r];
     o.eps[0] = b.eps[r];
+    o.nb[0] = b.nb[r];
+    o.inv_n[0] = b.inv_n[r];
     return o;
 }
 
@@ -1045,7 +1061,6 @@ SumsReduce one_of(const SumsReduce &b, int r)
 int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
 {
     const int L = pl.L, st_fmt = pl.storage, B = pl.count;
-    const Dims *dims = pl.dims;
     const GaussTaps &taps = pl.taps;
     const RegSizes &zs = pl.stride;
     const size_t es = storage_bytes(st_fmt);
@@ -1057,6 +1072,7 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
     // storage the finest level itself is a converted copy.
     const void *Sk[kMaxBatch][DIR_MAX_LEVELS], *Mk[kMaxBatch][DIR_MAX_LEVELS];
     for (int r = 0; r < B; ++r) {
+        const Dims *dims = pl.dims[r];
         Sk[r][0] = pl.S[r];
         Mk[r][0] = pl.M[r];
         size_t off = 0;
@@ -1103,20 +1119,24 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
         fh.D[r] = part(h->img_a, zs.img_a, r);
         fh.P[r] = part(h->img_b, zs.img_b, r);
         fh.partials[r] = part<double>(h->partials, zs.partials, r);
-        DIR_TRY(launch_zero(c, v[r], 3 * dims[L - 1].n(), st_fmt));
+        DIR_TRY(launch_zero(c, v[r], 3 * pl.dims[r][L - 1].n(), st_fmt));
     }
     for (int k = L - 1; k >= 0; --k) {
         const int li = L - 1 - k;
-        const Dims d = dims[k];
         h->timer.level = k;
         SumsReduce red;
         red.count = B;
-        red.nb = (int)force_blocks(d);
-        red.inv_n = 1.0 / (double)d.n();
+        Dims d[kMaxBatch];
+        int64_t voxels = 0;
         for (int r = 0; r < B; ++r) {
+            d[r] = pl.dims[r][k];
+            voxels += d[r].n();
+            fh.d[r] = d[r];
+            red.nb[r] = (int)force_blocks(d[r]);
+            red.inv_n[r] = 1.0 / (double)d[r].n();
             if (k < L - 1) {
                 void *dst = (k == 0 && final_v[r]) ? final_v[r] : (v[r] == fa[r] ? fb[r] : fa[r]);
-                DIR_TRY(launch_prolong(c, v[r], dims[k + 1], dst, d, st_fmt));
+                DIR_TRY(launch_prolong(c, v[r], pl.dims[r][k + 1], dst, d[r], st_fmt));
                 v[r] = dst;
             }
             xs[r] = v[r] == fa[r] ? fb[r] : fa[r];  // x-smoothed u of this level
@@ -1141,8 +1161,8 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
             for (int n = 0; n < iters; ++n) {
                 // v -> xs = x-smoothed (v + dr) -> v = y,z-smoothed xs; the
                 // smoothing kernel also reduces the sums of this iteration
-                DIR_TRY(force_half(c, f, d, taps, n));
-                DIR_TRY(launch_smooth_yz(c, f.count, xsv, 3, d, taps, vv, st_fmt, f.stop_at, n, rd));
+                DIR_TRY(force_half(c, f, taps, n));
+                DIR_TRY(launch_smooth_yz(c, f.count, xsv, 3, f.d, taps, vv, st_fmt, f.stop_at, n, rd));
                 if (poll && B == 1 && pl.eps[0] > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
                     int stop_at = kNeverStopped;
                     DIR_TRY(hipMemcpyAsync(&stop_at, &states[0][li].stop_at, sizeof(int), hipMemcpyDeviceToHost,
@@ -1153,7 +1173,7 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
             }
             return DIR_OK;
         };
-        if (lockstep_level(B, d, es)) {
+        if (lockstep_level(B, voxels, es)) {
             const int rc = run_level(fh, red, xs, v);
             if (rc != DIR_OK) return rc;
         } else {
@@ -1167,8 +1187,9 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
     // ---- output (FP32) ----
     h->timer.level = 0;
     for (int r = 0; r < B; ++r) {
-        if (pl.variant[r] == kInverseConsistent) DIR_TRY(launch_compose(c, v[r], st_fmt, dims[0], pl.K[r], pl.out[r]));
-        else if (!f32) DIR_TRY(launch_convert(c, v[r], st_fmt, pl.out[r], kStoreF32, 3 * dims[0].n()));
+        const Dims d0 = pl.dims[r][0];
+        if (pl.variant[r] == kInverseConsistent) DIR_TRY(launch_compose(c, v[r], st_fmt, d0, pl.K[r], pl.out[r]));
+        else if (!f32) DIR_TRY(launch_convert(c, v[r], st_fmt, pl.out[r], kStoreF32, 3 * d0.n()));
     }
     return DIR_OK;
 }
@@ -1180,9 +1201,9 @@ GraphKey graph_key(dir_handle *h, const RegPlan &pl, const dir_params *p)
     k.S = pl.S[0];
     k.M = pl.M[0];
     k.out = pl.out[0];
-    k.nx = pl.dims[0].nx;
-    k.ny = pl.dims[0].ny;
-    k.nz = pl.dims[0].nz;
+    k.nx = pl.dims[0][0].nx;
+    k.ny = pl.dims[0][0].ny;
+    k.nz = pl.dims[0][0].nz;
     memcpy(&k.params, p, sizeof k.params);
     const DevBuf *bufs[12] = {&h->pyr_s, &h->pyr_m,  &h->field[0], &h->field[1], &h->field[2],  &h->img_a,
                               &h->img_b, &h->img0_s, &h->img0_m,   &h->partials, &h->history, &h->state};
@@ -1345,9 +1366,8 @@ int32_t dir_wait(dir_handle *h, dir_stats *stats)
 }
 
 int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_static,
-                           const float *const *d_moving, int32_t nx, int32_t ny, int32_t nz,
-                           const double *spacing_mm, const dir_params *params, float *const *d_field_out,
-                           dir_stats *stats)
+                           const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
+                           const dir_params *params, float *const *d_field_out, dir_stats *stats)
 {
     int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
@@ -1356,7 +1376,7 @@ int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_s
         for (int r = 0; r < count; ++r)
             if (stats[r].struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
     RegPlan pl;
-    rc = plan_batch(h, count, d_static, d_moving, nx, ny, nz, spacing_mm, params, d_field_out, pl);
+    rc = plan_batch(h, count, d_static, d_moving, dims, spacing_mm, params, d_field_out, pl);
     if (rc != DIR_OK) return rc;
     rc = enqueue_register(h, pl, false);
     if (rc != DIR_OK) return rc;

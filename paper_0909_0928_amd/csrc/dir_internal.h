@@ -18,8 +18,8 @@ constexpr int kBlockY = 4;    // four wavefronts per workgroup
 enum Variant { kMixedVariants = -1, kPassive = 0, kEvolved = 1, kActive = 2, kDouble = 3, kInverseConsistent = 4 };
 
 // Registrations one launch of the per-iteration kernels can carry: a lockstep
-// batch of registrations of one volume size runs every iteration of all of
-// them as one pre-warp, one force and one smoothing launch.
+// batch runs every iteration of all its registrations as one pre-warp, one
+// force and one smoothing launch (one per tile class when their sizes differ).
 constexpr int kMaxBatch = 8;
 
 // Storage formats of images and fields inside a registration, numerically
@@ -75,8 +75,8 @@ struct SumsReduce {
     double *hist[kMaxBatch];               // level history; entry n at hist[4n]
     LevelState *st[kMaxBatch];
     double eps[kMaxBatch];
-    int nb;                                // force workgroups per registration
-    double inv_n;
+    int nb[kMaxBatch];                     // force workgroups of the registration
+    double inv_n[kMaxBatch];               // 1 / voxels (the mean of D^2)
 };
 
 // Per-kernel HIP-event timing.  A timed launch goes through
@@ -121,10 +121,10 @@ struct Ctx {
 // Number of workgroups (and FP64 sum slots) of the force kernel for a level.
 int64_t force_blocks(Dims d);
 
-// One force-kernel launch for `count` registrations of size d: u = v + dr
-// (Eqs 1-6), its x-smoothing with `taps` (identity taps give u), and the
-// per-workgroup FP64 sums.  Every volume is in format `storage`.  Arrays are
-// indexed by registration.
+// Force kernel for `count` registrations of sizes d[]: u = v + dr (Eqs 1-6),
+// its x-smoothing with `taps` (identity taps give u), and the per-workgroup
+// FP64 sums.  Every volume is in format `storage`.  Arrays are indexed by
+// registration; registrations of one tile width share a launch.
 struct ForceLaunch {
     int count = 1;
     int variant;                     // every registration's, or kMixedVariants
@@ -133,7 +133,7 @@ struct ForceLaunch {
     float alpha2[kMaxBatch];
     const void *S[kMaxBatch], *M[kMaxBatch], *v[kMaxBatch];
     const void *D[kMaxBatch], *P[kMaxBatch];  // from the pre-warp: D (active, double, IC), P = Im + Is (IC)
-    Dims d;
+    Dims d[kMaxBatch];
     const GaussTaps *taps;
     void *out[kMaxBatch];
     double *partials[kMaxBatch];     // 3 * force_blocks(d) doubles each
@@ -145,8 +145,8 @@ struct ForceLaunch {
 // pair D = Im - Is, P = Im + Is.
 enum PrewarpKind { kPrewarpMixed = -1, kPrewarpDiff = 0, kPrewarpPair = 1 };
 
-// One pre-warp launch for `count` registrations of size d (arrays indexed by
-// registration; P only for the pair kind).
+// One pre-warp launch for `count` registrations of sizes d[] (arrays indexed
+// by registration; P only for the pair kind).
 struct PrewarpLaunch {
     int count = 1;
     int kind;                        // every registration's, or kPrewarpMixed
@@ -155,7 +155,7 @@ struct PrewarpLaunch {
     const void *M[kMaxBatch], *S[kMaxBatch], *v[kMaxBatch];
     void *D[kMaxBatch], *P[kMaxBatch];
     const int *stop_at[kMaxBatch];
-    Dims d;
+    Dims d[kMaxBatch];
     int n;
 };
 
@@ -169,14 +169,16 @@ hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, flo
 hipError_t launch_prewarp(Ctx &c, const PrewarpLaunch &w);
 hipError_t launch_force(Ctx &c, const ForceLaunch &f);
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out);
-// y and z passes for `count` registrations of size d (arrays indexed by
-// registration); red.count is 0 or `count`.
-hipError_t launch_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, Dims d, const GaussTaps &taps,
-                            void *const *out, int st, const int *const *stop_at, int n, const SumsReduce &red);
+// y and z passes for `count` registrations of sizes d[] (arrays indexed by
+// registration; registrations of one z-chunk depth share a launch); red.count
+// is 0 or `count`.
+hipError_t launch_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, const Dims *d,
+                            const GaussTaps &taps, void *const *out, int st, const int *const *stop_at, int n,
+                            const SumsReduce &red);
 inline hipError_t launch_smooth_yz(Ctx &c, const void *in, int ncomp, Dims d, const GaussTaps &taps, void *out,
                                    int st, const int *stop_at, int n, const SumsReduce &red)
 {
-    return launch_smooth_yz(c, 1, &in, ncomp, d, taps, &out, st, &stop_at, n, red);
+    return launch_smooth_yz(c, 1, &in, ncomp, &d, taps, &out, st, &stop_at, n, red);
 }
 hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n);
 hipError_t launch_level_reset(Ctx &c, LevelState *st);

@@ -27,9 +27,17 @@ using namespace dev;
 
 // Volumes are in the storage format of the kernel instance (StF32, StF16 or
 // StBF16); the pointers are untyped.  One launch serves `count` registrations
-// of one size (a lockstep batch; 1 outside batches): per-registration
-// arguments are arrays indexed by registration, and the grid holds `blocks`
-// workgroups per registration.
+// (a lockstep batch; 1 outside batches), possibly of different sizes with the
+// same tile width TX: per-registration arguments are arrays indexed by
+// registration, and each registration has its own range of workgroups.
+// Volume size and workgroup layout of one registration of a launch.
+struct Geo {
+    int nx, ny, nz;
+    int gxt;             // x tiles
+    int rows_per_block;  // row steps per workgroup
+    int blocks;          // workgroups
+};
+
 struct ForceArgs {
     const void *S[kMaxBatch], *M[kMaxBatch], *v[kMaxBatch];
     const void *Dd[kMaxBatch], *P[kMaxBatch];  // pre-warped D (active, double, IC) and P = Im + Is (IC, always FP32)
@@ -38,11 +46,10 @@ struct ForceArgs {
     const int *stop_at[kMaxBatch];  // skip when *stop_at < n (NULL: never)
     float alpha2[kMaxBatch];
     int variant[kMaxBatch];         // read by the mixed-variant instance only
-    int nx, ny, nz;
+    Geo geo[kMaxBatch];
+    int first[kMaxBatch + 1];       // logical workgroups of registration r: first[r] .. first[r + 1] - 1
+    int count;
     int n;                          // iteration index within the level
-    int rows_per_block;
-    int gxt;                        // x tiles
-    int blocks;                     // workgroups per registration
 };
 
 // Byte offsets of one wave-uniform row (y, z) and of its stencil neighbour
@@ -101,11 +108,11 @@ struct Bufs {
 
 // u = v + dr at voxel (x, y, z) and its contributions |dr|, |v|, D^2.
 template <int V, class St>
-__device__ __forceinline__ void force_point(const ForceArgs &a, float alpha2, const Bufs &b, int x, int y, int z,
+__device__ __forceinline__ void force_point(const Geo &q, float alpha2, const Bufs &b, int x, int y, int z,
                                             const RowOffsets &ro, unsigned nbytes, float &u0, float &u1, float &u2,
                                             double &adr, double &av, double &d2)
 {
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = q.nx, ny = q.ny, nz = q.nz;
     constexpr unsigned ES = St::kBytes;
     LaneOffsets lo;
     lo.c = ES * (unsigned)x;
@@ -179,11 +186,12 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
     constexpr int W = ForceTile<TX>::W;
     const int tid = threadIdx.x;
     const int lane = tid % LANES, wrow = tid / LANES;
-    const int x0 = (lid % a.gxt) * TX;
-    const int rb = lid / a.gxt;
+    const Geo &q = a.geo[reg];
+    const int x0 = (lid % q.gxt) * TX;
+    const int rb = lid / q.gxt;
     const int R = RC >= 0 ? RC : taps.radius;
-    const int rows = a.ny * a.nz;
-    const unsigned N = (unsigned)a.nx * (unsigned)rows;
+    const int rows = q.ny * q.nz;
+    const unsigned N = (unsigned)q.nx * (unsigned)rows;
     constexpr unsigned ES = St::kBytes;
     const unsigned nbytes = ES * N;
     const float alpha2 = a.alpha2[reg];
@@ -196,28 +204,28 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
     b.out = make_rsrc(a.out[reg], 3u * nbytes);
     double s1 = 0.0, s2 = 0.0, sse = 0.0;
 
-    for (int it = 0; it < a.rows_per_block; ++it) {
+    for (int it = 0; it < q.rows_per_block; ++it) {
         // row index y + ny * z; the same for every lane of a wavefront
-        const int r = __builtin_amdgcn_readfirstlane((rb * a.rows_per_block + it) * W + wrow);
+        const int r = __builtin_amdgcn_readfirstlane((rb * q.rows_per_block + it) * W + wrow);
         const bool row_ok = r < rows;
         if (row_ok) {
-            const int y = r % a.ny, z = r / a.ny;
-            const unsigned rowb = ES * (unsigned)a.nx;  // bytes per row
+            const int y = r % q.ny, z = r / q.ny;
+            const unsigned rowb = ES * (unsigned)q.nx;  // bytes per row
             RowOffsets ro;
             ro.c = rowb * (unsigned)r;
-            ro.ym = rowb * (unsigned)(max(y - 1, 0) + a.ny * z);
-            ro.yp = rowb * (unsigned)(min(y + 1, a.ny - 1) + a.ny * z);
-            ro.zm = rowb * (unsigned)(y + a.ny * max(z - 1, 0));
-            ro.zp = rowb * (unsigned)(y + a.ny * min(z + 1, a.nz - 1));
+            ro.ym = rowb * (unsigned)(max(y - 1, 0) + q.ny * z);
+            ro.yp = rowb * (unsigned)(min(y + 1, q.ny - 1) + q.ny * z);
+            ro.zm = rowb * (unsigned)(y + q.ny * max(z - 1, 0));
+            ro.zp = rowb * (unsigned)(y + q.ny * min(z + 1, q.nz - 1));
             // Evaluate only the points of the tile and its halo that lie in
             // the row: a halo slot beyond a row end holds the end voxel's u
             // (clamped index), so the end lanes copy theirs there instead.
-            const int p_lo = max(R - x0, 0), p_hi = min(TX + 2 * R, a.nx - x0 + R);
+            const int p_lo = max(R - x0, 0), p_hi = min(TX + 2 * R, q.nx - x0 + R);
             for (int p = p_lo + lane; p < p_hi; p += LANES) {
                 const int xx = x0 - R + p;  // in [0, nx)
                 float u0, u1, u2;
                 double adr, av, d2;
-                force_point<V, St>(a, alpha2, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
+                force_point<V, St>(q, alpha2, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
                 ul[0][wrow][p] = u0;
                 ul[1][wrow][p] = u1;
                 ul[2][wrow][p] = u2;
@@ -229,7 +237,7 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
                     }
                 // slots past the row end up to the last one the x pass reads:
                 // min(TX, nx - x0) - 1 + 2R = min(p + R, TX + 2R - 1)
-                if (xx == a.nx - 1)
+                if (xx == q.nx - 1)
                     for (int q = p + 1; q <= min(p + R, TX + 2 * R - 1); ++q) {
                         ul[0][wrow][q] = u0;
                         ul[1][wrow][q] = u1;
@@ -243,11 +251,11 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
             }
         }
         __syncthreads();
-        const unsigned rowoff = ES * (unsigned)a.nx * (unsigned)r;
+        const unsigned rowoff = ES * (unsigned)q.nx * (unsigned)r;
 #pragma unroll
         for (int xl = lane; xl < TX; xl += LANES) {
             const int x = x0 + xl;
-            if (!row_ok || x >= a.nx) break;
+            if (!row_ok || x >= q.nx) break;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float s = 0.0f;
@@ -269,7 +277,7 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
     // ---- sums: fixed-order workgroup reduction into this workgroup's slots ----
     block_sum3(s1, s2, sse, tid);
     if (tid == 0) {
-        const int nb = a.blocks;
+        const int nb = q.blocks;
         double *p = a.partials[reg];
         p[lid] = s1;
         p[nb + lid] = s2;
@@ -278,7 +286,7 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
 }
 
 // One workgroup of a force launch.  Logical workgroup ids (XCD-contiguous)
-// run registration by registration; V = kMixedVariants takes each
+// run registration by registration (first[]); V = kMixedVariants takes each
 // registration's variant from the arguments (a uniform branch per workgroup).
 template <int V, int TX, int RC, class St>
 __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
@@ -286,7 +294,9 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
     __shared__ typename ForceTile<TX>::Rows ul;
     __shared__ float wl[2 * kMaxRadius + 1];  // taps, read as LDS broadcasts
     const int g = xcd_logical_id(blockIdx.x, gridDim.x);
-    const int reg = g / a.blocks, lid = g - reg * a.blocks;  // wave-uniform
+    int reg = 0;  // wave-uniform
+    while (reg + 1 < a.count && g >= a.first[reg + 1]) ++reg;
+    const int lid = g - a.first[reg];
     if (a.stop_at[reg] && *a.stop_at[reg] < a.n) return;
     if (threadIdx.x <= 2 * kMaxRadius) wl[threadIdx.x] = taps.w[threadIdx.x];  // ordered before use by the row barrier
     if constexpr (V != kMixedVariants) {
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
 __global__ __launch_bounds__(256) void k_finalize(SumsReduce red, int n)
 {
     const int r = blockIdx.x;
-    reduce_sums(red.partials[r], red.nb, red.hist[r], n, red.st[r], red.eps[r], red.inv_n, threadIdx.x);
+    reduce_sums(red.partials[r], red.nb[r], red.hist[r], n, red.st[r], red.eps[r], red.inv_n[r], threadIdx.x);
 }
 
 __global__ void k_level_reset(LevelState *st)
@@ -385,39 +395,38 @@ void launch_force_v(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a
     else launch_force_vs<V, StF32>(c, ev, g, a, taps);
 }
 
-}  // namespace
-
-int64_t force_blocks(Dims d) { return force_grid(d).blocks; }
-
-hipError_t launch_force(Ctx &c, const ForceLaunch &f)
+// One launch for the registrations `sel[0 .. k-1]` of f, which share a tile
+// width.
+hipError_t launch_force_group(Ctx &c, const ForceLaunch &f, const ForceGrid *g, const int *sel, int k)
 {
-    if (f.count < 1 || f.count > kMaxBatch) return hipErrorInvalidValue;
-    const ForceGrid g = force_grid(f.d);
     ForceArgs a;
     memset(&a, 0, sizeof a);
-    for (int r = 0; r < f.count; ++r) {
-        a.S[r] = f.S[r];
-        a.M[r] = f.M[r];
-        a.v[r] = f.v[r];
-        a.Dd[r] = f.D[r];
-        a.P[r] = f.P[r];
-        a.out[r] = f.out[r];
-        a.partials[r] = f.partials[r];
-        a.stop_at[r] = f.stop_at[r];
-        a.alpha2[r] = f.alpha2[r];
-        a.variant[r] = f.variant == kMixedVariants ? f.variants[r] : f.variant;
+    int variant = f.variant == kMixedVariants ? f.variants[sel[0]] : f.variant;
+    int64_t total = 0;
+    for (int q = 0; q < k; ++q) {
+        const int r = sel[q];
+        a.S[q] = f.S[r];
+        a.M[q] = f.M[r];
+        a.v[q] = f.v[r];
+        a.Dd[q] = f.D[r];
+        a.P[q] = f.P[r];
+        a.out[q] = f.out[r];
+        a.partials[q] = f.partials[r];
+        a.stop_at[q] = f.stop_at[r];
+        a.alpha2[q] = f.alpha2[r];
+        a.variant[q] = f.variant == kMixedVariants ? f.variants[r] : f.variant;
+        if (a.variant[q] != variant) variant = kMixedVariants;
+        a.geo[q] = Geo{f.d[r].nx, f.d[r].ny, f.d[r].nz, g[r].gxt, g[r].rows_per_block, (int)g[r].blocks};
+        a.first[q] = (int)total;
+        total += g[r].blocks;
     }
-    a.nx = f.d.nx;
-    a.ny = f.d.ny;
-    a.nz = f.d.nz;
+    a.first[k] = (int)total;
+    a.count = k;
     a.n = f.n;
-    a.rows_per_block = g.rows_per_block;
-    a.gxt = g.gxt;
-    a.blocks = (int)g.blocks;
-    ForceGrid gl = g;
-    gl.blocks = g.blocks * f.count;  // the launch: every registration's workgroups
+    ForceGrid gl = g[sel[0]];
+    gl.blocks = total;  // the launch: every registration's workgroups
     return timed(c, K_FORCE, [&](const Ev &ev) {
-        switch (f.variant) {
+        switch (variant) {
         case kPassive: launch_force_v<kPassive>(c, ev, gl, a, *f.taps, f.storage); break;
         case kEvolved: launch_force_v<kEvolved>(c, ev, gl, a, *f.taps, f.storage); break;
         case kActive: launch_force_v<kActive>(c, ev, gl, a, *f.taps, f.storage); break;
@@ -426,6 +435,32 @@ hipError_t launch_force(Ctx &c, const ForceLaunch &f)
         default: launch_force_v<kMixedVariants>(c, ev, gl, a, *f.taps, f.storage); break;
         }
     });
+}
+
+}  // namespace
+
+int64_t force_blocks(Dims d) { return force_grid(d).blocks; }
+
+// Registrations whose rows take the same tile width share a launch; each
+// keeps the workgroup layout it has alone.
+hipError_t launch_force(Ctx &c, const ForceLaunch &f)
+{
+    if (f.count < 1 || f.count > kMaxBatch) return hipErrorInvalidValue;
+    ForceGrid g[kMaxBatch];
+    for (int r = 0; r < f.count; ++r) g[r] = force_grid(f.d[r]);
+    bool done[kMaxBatch] = {};
+    for (int r = 0; r < f.count; ++r) {
+        if (done[r]) continue;
+        int sel[kMaxBatch], k = 0;
+        for (int q = r; q < f.count; ++q)
+            if (!done[q] && g[q].tx == g[r].tx) {
+                sel[k++] = q;
+                done[q] = true;
+            }
+        const hipError_t e = launch_force_group(c, f, g, sel, k);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n)

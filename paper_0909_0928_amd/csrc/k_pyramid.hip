@@ -95,18 +95,25 @@ __global__ __launch_bounds__(256) void k_warp(const float *__restrict__ I, const
     out[i] = (float)sample64(I, make_cell_disp(x, y, z, v[i], v[N + i], v[2 * N + i], nx, ny, nz));
 }
 
-// Pre-warp of one iteration for `count` registrations of one size (a
-// lockstep batch; 1 outside batches): per-registration arguments are arrays
-// indexed by registration, and the grid holds `per` 64 x 4 workgroups (one
-// per x tile, y tile and z plane) per registration.
+// Volume size and tiling of one registration of a launch.
+struct PlaneGeo {
+    int nx, ny, nz;
+    int gx, gy;  // x tiles, y tiles
+};
+
+// Pre-warp of one iteration for `count` registrations (a lockstep batch; 1
+// outside batches), possibly of different sizes: per-registration arguments
+// are arrays indexed by registration, and each registration has its own range
+// of 64 x 4 workgroups (one per x tile, y tile and z plane).
 struct PrewarpArgs {
     const void *M[kMaxBatch], *S[kMaxBatch], *v[kMaxBatch];
     void *D[kMaxBatch], *P[kMaxBatch];
     const int *stop_at[kMaxBatch];  // skip when *stop_at < n (NULL: never)
     int kind[kMaxBatch];            // read by the mixed instance only
-    int nx, ny, nz, gx, gy;
+    PlaneGeo geo[kMaxBatch];
+    int first[kMaxBatch + 1];       // logical workgroups of registration r: first[r] .. first[r + 1] - 1
+    int count;
     int n;
-    int per;
 };
 
 // Intensity difference for the active and double forces: D = M(x - v) - S(x),
@@ -117,7 +124,7 @@ struct PrewarpArgs {
 template <class St>
 __device__ __forceinline__ void warp_diff_at(const PrewarpArgs &a, int r, int x, int y, int z)
 {
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = a.geo[r].nx, ny = a.geo[r].ny, nz = a.geo[r].nz;
     constexpr unsigned E = St::kBytes;
     const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes), rS = make_rsrc(a.S[r], nbytes),
@@ -136,7 +143,7 @@ __device__ __forceinline__ void warp_diff_at(const PrewarpArgs &a, int r, int x,
 template <class St>
 __device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x, int y, int z)
 {
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = a.geo[r].nx, ny = a.geo[r].ny, nz = a.geo[r].nz;
     constexpr unsigned E = St::kBytes;
     const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
     const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes), rS = make_rsrc(a.S[r], nbytes),
@@ -155,14 +162,16 @@ __device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x,
 __device__ __forceinline__ bool prewarp_voxel(const PrewarpArgs &a, int &r, int &x, int &y, int &z)
 {
     const int g = xcd_logical_id(blockIdx.x, gridDim.x);
-    r = g / a.per;
-    const int lb = g - r * a.per;
+    r = 0;  // wave-uniform
+    while (r + 1 < a.count && g >= a.first[r + 1]) ++r;
+    const int lb = g - a.first[r];
     if (a.stop_at[r] && *a.stop_at[r] < a.n) return false;
-    const int q = lb / a.gx;
-    x = (lb - q * a.gx) * kBlockX + threadIdx.x;
-    y = (q % a.gy) * kBlockY + threadIdx.y;
-    z = q / a.gy;
-    return x < a.nx && y < a.ny;
+    const PlaneGeo &t = a.geo[r];
+    const int q = lb / t.gx;
+    x = (lb - q * t.gx) * kBlockX + threadIdx.x;
+    y = (q % t.gy) * kBlockY + threadIdx.y;
+    z = q / t.gy;
+    return x < t.nx && y < t.ny;
 }
 
 template <class St>
@@ -367,10 +376,14 @@ hipError_t launch_warp(Ctx &c, const float *img, const float *field, Dims d, flo
 hipError_t launch_prewarp(Ctx &c, const PrewarpLaunch &w)
 {
     if (w.count < 1 || w.count > kMaxBatch) return hipErrorInvalidValue;
-    const Grid2 g = plane_grid(w.d);
     PrewarpArgs a;
     memset(&a, 0, sizeof a);
+    int64_t total = 0;
     for (int r = 0; r < w.count; ++r) {
+        const Grid2 g = plane_grid(w.d[r]);
+        a.geo[r] = PlaneGeo{w.d[r].nx, w.d[r].ny, w.d[r].nz, g.gx, g.gy};
+        a.first[r] = (int)total;
+        total += g.blocks;
         a.M[r] = w.M[r];
         a.S[r] = w.S[r];
         a.v[r] = w.v[r];
@@ -379,14 +392,10 @@ hipError_t launch_prewarp(Ctx &c, const PrewarpLaunch &w)
         a.stop_at[r] = w.stop_at[r];
         a.kind[r] = w.kind == kPrewarpMixed ? w.kinds[r] : w.kind;
     }
-    a.nx = w.d.nx;
-    a.ny = w.d.ny;
-    a.nz = w.d.nz;
-    a.gx = g.gx;
-    a.gy = g.gy;
+    a.first[w.count] = (int)total;
+    a.count = w.count;
     a.n = w.n;
-    a.per = (int)g.blocks;
-    const dim3 grid((unsigned)(g.blocks * w.count)), block(kBlockX, kBlockY);
+    const dim3 grid((unsigned)total), block(kBlockX, kBlockY);
     const int k = w.kind == kPrewarpDiff ? K_WARP : (w.kind == kPrewarpPair ? K_WARP_PAIR : K_WARP_MIXED);
     return timed(c, k, [&](const Ev &ev) {
         with_storage(w.storage, [&](auto t) {

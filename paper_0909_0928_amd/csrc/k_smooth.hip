@@ -61,17 +61,24 @@ constexpr int max_tz()
     return (kTileY + 2 * R) * kBlockX * 4 * 8 <= 65536 ? 8 : 4;
 }
 
-// One launch serves `count` registrations of one size (a lockstep batch; 1
-// outside batches): per-registration arguments are arrays indexed by
-// registration, and the grid holds `per` workgroups per registration.
+// Volume size and tiling of one registration of a launch.
+struct YZGeo {
+    int nx, ny, nz;
+    int gx, gy, gz;  // x tiles, y tiles, z chunks
+};
+
+// One launch serves `count` registrations (a lockstep batch; 1 outside
+// batches), possibly of different sizes with the same z-chunk depth:
+// per-registration arguments are arrays indexed by registration, and each
+// registration has its own range of workgroups.
 struct YZArgs {
     const void *in[kMaxBatch];
     void *out[kMaxBatch];
     const int *stop_at[kMaxBatch];  // skip when *stop_at < n (NULL: never)
-    int nx, ny, nz;
-    int gx, gy, gz;                 // x tiles, y tiles, z chunks
+    YZGeo geo[kMaxBatch];
+    int first[kMaxBatch + 1];       // logical workgroups of registration r: first[r] .. first[r + 1] - 1
+    int count;
     int n;
-    int per;                        // workgroups per registration
 };
 
 // With red.count set, the first workgroup of each registration instead adds
@@ -89,14 +96,18 @@ __global__ __launch_bounds__(256) void k_smooth_yz(YZArgs a, GaussTaps taps, Sum
     // compact (y, z) block of one x column, whose shared 2R halo planes and
     // rows are then served from that XCD's L2.
     const int g = xcd_logical_id(blockIdx.x, gridDim.x);
-    const int reg = g / a.per, lb = g - reg * a.per;  // wave-uniform
+    int reg = 0;  // wave-uniform
+    while (reg + 1 < a.count && g >= a.first[reg + 1]) ++reg;
+    const int lb = g - a.first[reg];
     if (a.stop_at[reg] && *a.stop_at[reg] < a.n) return;
     const int tid = threadIdx.x + kBlockX * threadIdx.y;
     if (red.count && lb == 0) {
-        reduce_sums(red.partials[reg], red.nb, red.hist[reg], a.n, red.st[reg], red.eps[reg], red.inv_n, tid);
+        reduce_sums(red.partials[reg], red.nb[reg], red.hist[reg], a.n, red.st[reg], red.eps[reg], red.inv_n[reg],
+                    tid);
         return;
     }
-    const int nx = a.nx, ny = a.ny, nz = a.nz, gx = a.gx, gy = a.gy, gz = a.gz;
+    const YZGeo &q = a.geo[reg];
+    const int nx = q.nx, ny = q.ny, nz = q.nz, gx = q.gx, gy = q.gy, gz = q.gz;
     const int b = lb - (red.count ? 1 : 0);
     const int tz = b % gz, r1 = b / gz, ty = r1 % gy, r2 = r1 / gy, tx = r2 % gx, c = r2 / gx;
     const void *const in = a.in[reg];
@@ -175,43 +186,112 @@ __global__ __launch_bounds__(256) void k_smooth_yz(YZArgs a, GaussTaps taps, Sum
 }
 
 template <int R, int TZ, class St>
-void launch_yz_tz(Ctx &c, const Ev &ev, YZArgs a, int ncomp, int count, const GaussTaps &taps,
-                  const SumsReduce &red)
+void launch_yz_tz(Ctx &c, const Ev &ev, YZArgs a, int ncomp, const GaussTaps &taps, const SumsReduce &red)
 {
-    a.gx = ceil_div(a.nx, kBlockX);
-    a.gy = ceil_div(a.ny, kTileY);
-    a.gz = ceil_div(a.nz, TZ);
-    a.per = a.gx * a.gy * a.gz * ncomp + (red.count ? 1 : 0);
-    const int64_t blocks = (int64_t)a.per * count;
-    go(c, ev, (k_smooth_yz<R, TZ, St>), dim3((unsigned)blocks), dim3(kBlockX, kBlockY), a, taps, red);
+    int64_t total = 0;
+    for (int r = 0; r < a.count; ++r) {
+        YZGeo &q = a.geo[r];
+        q.gx = ceil_div(q.nx, kBlockX);
+        q.gy = ceil_div(q.ny, kTileY);
+        q.gz = ceil_div(q.nz, TZ);
+        a.first[r] = (int)total;
+        total += (int64_t)q.gx * q.gy * q.gz * ncomp + (red.count ? 1 : 0);
+    }
+    a.first[a.count] = (int)total;
+    go(c, ev, (k_smooth_yz<R, TZ, St>), dim3((unsigned)total), dim3(kBlockX, kBlockY), a, taps, red);
 }
 
 // Workgroups to aim for before the z chunk is made deeper (each chunk re-reads
 // 2R halo planes, so deeper chunks cost fewer loads per output).
 constexpr int64_t kYZTargetBlocks = 1024;
 
-template <int R, class St>
-hipError_t launch_yz_r(Ctx &c, const YZArgs &a, int ncomp, int count, const GaussTaps &taps, const SumsReduce &red)
+// z-chunk depth for a registration of size d: the deepest whose tiles still
+// number kYZTargetBlocks (or half that for 4).
+template <int R>
+int yz_depth(Dims d, int ncomp)
 {
-    // the depth choice depends on the tiles of one registration
-    const int64_t tiles = (int64_t)ceil_div(a.nx, kBlockX) * ceil_div(a.ny, kTileY) * ncomp;
-    const bool deep = max_tz<R>() == 8 && tiles * ceil_div(a.nz, 8) >= kYZTargetBlocks;
+    const int64_t tiles = (int64_t)ceil_div(d.nx, kBlockX) * ceil_div(d.ny, kTileY) * ncomp;
+    if (max_tz<R>() == 8 && tiles * ceil_div(d.nz, 8) >= kYZTargetBlocks) return 8;
+    if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) return 4;
+    return 2;
+}
+
+template <int R, class St>
+hipError_t launch_yz_r(Ctx &c, const YZArgs &a, int ncomp, int tz, const GaussTaps &taps, const SumsReduce &red)
+{
     return timed(c, K_SMOOTH_YZ, [&](const Ev &ev) {
-        if (deep) launch_yz_tz<R, max_tz<R>(), St>(c, ev, a, ncomp, count, taps, red);
-        else if (tiles * ceil_div(a.nz, 4) >= kYZTargetBlocks / 2) launch_yz_tz<R, 4, St>(c, ev, a, ncomp, count, taps, red);
-        else launch_yz_tz<R, 2, St>(c, ev, a, ncomp, count, taps, red);
+        if (tz == 8) launch_yz_tz<R, max_tz<R>(), St>(c, ev, a, ncomp, taps, red);
+        else if (tz == 4) launch_yz_tz<R, 4, St>(c, ev, a, ncomp, taps, red);
+        else launch_yz_tz<R, 2, St>(c, ev, a, ncomp, taps, red);
     });
+}
+
+// One launch for the registrations sel[0 .. k-1], which share depth tz.
+template <int R, class St>
+hipError_t launch_yz_group(Ctx &c, int n, const void *const *in, int ncomp, const Dims *d, const GaussTaps &taps,
+                           void *const *out, const int *const *stop_at, const SumsReduce &red, const int *sel,
+                           int k, int tz)
+{
+    YZArgs a;
+    memset(&a, 0, sizeof a);
+    SumsReduce rs = red;
+    for (int q = 0; q < k; ++q) {
+        const int r = sel[q];
+        a.in[q] = in[r];
+        a.out[q] = out[r];
+        a.stop_at[q] = stop_at[r];
+        a.geo[q].nx = d[r].nx;
+        a.geo[q].ny = d[r].ny;
+        a.geo[q].nz = d[r].nz;
+        if (red.count) {
+            rs.partials[q] = red.partials[r];
+            rs.hist[q] = red.hist[r];
+            rs.st[q] = red.st[r];
+            rs.eps[q] = red.eps[r];
+            rs.nb[q] = red.nb[r];
+            rs.inv_n[q] = red.inv_n[r];
+        }
+    }
+    a.count = k;
+    a.n = n;
+    if (red.count) rs.count = k;
+    return launch_yz_r<R, St>(c, a, ncomp, tz, taps, rs);
+}
+
+// Registrations of one z-chunk depth share a launch; each keeps the tiling it
+// has alone.
+template <int R, class St>
+hipError_t launch_yz_all(Ctx &c, int count, const void *const *in, int ncomp, const Dims *d,
+                         const GaussTaps &taps, void *const *out, const int *const *stop_at, int n,
+                         const SumsReduce &red)
+{
+    int tz[kMaxBatch];
+    for (int r = 0; r < count; ++r) tz[r] = yz_depth<R>(d[r], ncomp);
+    bool done[kMaxBatch] = {};
+    for (int r = 0; r < count; ++r) {
+        if (done[r]) continue;
+        int sel[kMaxBatch], k = 0;
+        for (int q = r; q < count; ++q)
+            if (!done[q] && tz[q] == tz[r]) {
+                sel[k++] = q;
+                done[q] = true;
+            }
+        const hipError_t e = launch_yz_group<R, St>(c, n, in, ncomp, d, taps, out, stop_at, red, sel, k, tz[r]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
 
 template <class St>
-hipError_t launch_smooth_yz_st(Ctx &c, const YZArgs &a, int ncomp, int count, const GaussTaps &taps,
+hipError_t launch_smooth_yz_st(Ctx &c, int count, const void *const *in, int ncomp, const Dims *d,
+                               const GaussTaps &taps, void *const *out, const int *const *stop_at, int n,
                                const SumsReduce &red)
 {
     switch (taps.radius) {
 #define DIR_R(r) \
-    case r: return launch_yz_r<r, St>(c, a, ncomp, count, taps, red);
+    case r: return launch_yz_all<r, St>(c, count, in, ncomp, d, taps, out, stop_at, n, red);
         DIR_R(0) DIR_R(1) DIR_R(2) DIR_R(3) DIR_R(4) DIR_R(5) DIR_R(6) DIR_R(7) DIR_R(8)
         DIR_R(9) DIR_R(10) DIR_R(11) DIR_R(12) DIR_R(13) DIR_R(14) DIR_R(15) DIR_R(16)
 #undef DIR_R
@@ -219,24 +299,14 @@ hipError_t launch_smooth_yz_st(Ctx &c, const YZArgs &a, int ncomp, int count, co
     }
 }
 
-hipError_t launch_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, Dims d, const GaussTaps &taps,
-                            void *const *out, int st, const int *const *stop_at, int n, const SumsReduce &red)
+hipError_t launch_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, const Dims *d,
+                            const GaussTaps &taps, void *const *out, int st, const int *const *stop_at, int n,
+                            const SumsReduce &red)
 {
     if (count < 1 || count > kMaxBatch || (red.count && red.count != count)) return hipErrorInvalidValue;
-    YZArgs a;
-    memset(&a, 0, sizeof a);
-    for (int r = 0; r < count; ++r) {
-        a.in[r] = in[r];
-        a.out[r] = out[r];
-        a.stop_at[r] = stop_at[r];
-    }
-    a.nx = d.nx;
-    a.ny = d.ny;
-    a.nz = d.nz;
-    a.n = n;
-    if (st == kStoreF16) return launch_smooth_yz_st<StF16>(c, a, ncomp, count, taps, red);
-    if (st == kStoreBF16) return launch_smooth_yz_st<StBF16>(c, a, ncomp, count, taps, red);
-    return launch_smooth_yz_st<StF32>(c, a, ncomp, count, taps, red);
+    if (st == kStoreF16) return launch_smooth_yz_st<StF16>(c, count, in, ncomp, d, taps, out, stop_at, n, red);
+    if (st == kStoreBF16) return launch_smooth_yz_st<StBF16>(c, count, in, ncomp, d, taps, out, stop_at, n, red);
+    return launch_smooth_yz_st<StF32>(c, count, in, ncomp, d, taps, out, stop_at, n, red);
 }
 
 hipError_t launch_smooth_x(Ctx &c, const float *in, int ncomp, Dims d, const GaussTaps &taps, float *out)

@@ -1,5 +1,6 @@
-"""Lockstep batches (dir_register_batch): several registrations of one volume
-size run every iteration as one pre-warp, one force and one smoothing launch.
+"""Lockstep batches (dir_register_batch): several registrations, of one size or
+of several, run every iteration as one pre-warp, one force and one smoothing
+launch (per tile class).
 Each field, its iteration counts and its per-iteration history must be bitwise
 those of the same registration run alone with dir_register (the kernels, their
 arithmetic and the order of every sum are the same), and the batch must refuse
@@ -99,6 +100,35 @@ def test_batch_of_one_and_of_eight(B, h):
     _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
 
 
+# sizes that take every force tile width (64, 128, 256, 512 voxels) and
+# different z-chunk depths of the smoothing
+RAGGED = [(40, 36, 20), (100, 33, 17), (130, 45, 21), (300, 20, 9), (64, 64, 40), (257, 30, 12)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_ragged_batch_equals_alone(B, h, storage):
+    pairs = []
+    for k, shape in enumerate(RAGGED):
+        pairs += _pairs(shape, 1, 860 + k)
+    params = [B.make_params(v, [5, 4, 3], sigma=1.0, alpha=a, storage=storage) for v, a in SIX]
+    alone = _alone(B, h, pairs, params)
+    for _ in range(2):
+        _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
+
+
+def test_ragged_batch_of_uneven_ic_pairs(B, h):
+    # the uneven inverse-consistent workload's shape mix, scaled down: x, y in
+    # 64..128, z in 32..64, three levels
+    rng = np.random.default_rng(11)
+    shapes = [(int(rng.integers(64, 129)), int(rng.integers(64, 129)), int(rng.integers(32, 65))) for _ in range(8)]
+    pairs = []
+    for k, shape in enumerate(shapes):
+        pairs += _pairs(shape, 1, 880 + k)
+    params = [B.make_params("inverse_consistent", [6, 4, 3], sigma=1.5)] * len(shapes)
+    alone = _alone(B, h, pairs, params)
+    _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
+
+
 def test_batch_stopping_rule_per_registration(B, h):
     # eps differs per registration: the stopped ones skip their remaining
     # iterations inside the batch, as a lone registration stops early
@@ -139,7 +169,8 @@ def test_batch_refuses_what_cannot_run_in_lockstep(B, h):
     arr = (ctypes.c_void_p * n)(*([Ss[0].data_ptr()] * n))
     outs = [torch.empty_like(shared) for _ in range(n)]
     parr = (B.dir_params * n)(*([p0] * n))
-    rc = B.lib().dir_register_batch(h.ptr, n, arr, arr, 32, 24, 10, None, parr,
+    dims = (ctypes.c_int32 * (3 * n))(*([32, 24, 10] * n))
+    rc = B.lib().dir_register_batch(h.ptr, n, arr, arr, dims, None, parr,
                                     (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs]), None)
     assert rc == B.DIR_EINVAL
     # the handle still works
