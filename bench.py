@@ -308,7 +308,8 @@ def _phantoms(jobs):
 def batch32(args):
     """32 independent inverse-consistent pairs of uneven sizes (x, y uniform in
     128..256, z in 64..128; seeds 1000 + i), 3 levels, 100/50/25 iterations:
-    all submitted at once to a request pool; as four lockstep batches of 8 in
+    all submitted at once to a request pool (one by one on 8 slots, and in
+    lockstep batches of up to 8 on 2 slots); as four lockstep batches of 8 in
     submission order, on one stream and split over two; and one after
     another."""
     import torch
@@ -326,19 +327,20 @@ def batch32(args):
     vi = sum(voxel_iters(sh, ITERS) for sh in shapes)
     res = {"workload": "32 inverse-consistent pairs, x,y in 128..256, z in 64..128, 3 levels 100/50/25, sigma 1.5",
            "storage": args.storage, "voxel_iters": vi}
-    with B.Pool(slots=args.slots, max_bytes=0) as pool:
-        def run_pool():
-            ts = [pool.submit(a, b, params, field_out=o) for a, b, o in zip(S, M, outs)]
-            for t in ts:
-                pool.wait(t)
-        run_pool()                                   # warm-up: workspaces grow to their sizes
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_pool()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res.update({"pool_slots": args.slots, "pool_seconds": dt, "pool_voxel_iter_per_s": vi / dt,
-                    "pool_peak_running": pool.stats()["peak_running"]})
+    for key, slots, max_batch in (("pool", args.slots, 1), ("pool_batching", 2, B.DIR_MAX_BATCH)):
+        with B.Pool(slots=slots, max_bytes=0, max_batch=max_batch) as pool:
+            def run_pool():
+                ts = [pool.submit(a, b, params, field_out=o) for a, b, o in zip(S, M, outs)]
+                for t in ts:
+                    pool.wait(t)
+            run_pool()                               # warm-up: workspaces grow to their sizes
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run_pool()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res.update({f"{key}_slots": slots, f"{key}_max_batch": max_batch, f"{key}_seconds": dt,
+                        f"{key}_voxel_iter_per_s": vi / dt, f"{key}_peak_running": pool.stats()["peak_running"]})
     h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))
     groups = [list(range(k, min(k + B.DIR_MAX_BATCH, len(S)))) for k in range(0, len(S), B.DIR_MAX_BATCH)]
     hb = [B.dir_create(0, stream=torch.cuda.Stream(device=dev)) for _ in range(2)]
@@ -372,8 +374,8 @@ def batch32(args):
     for hh in [h] + hb:
         B.dir_destroy(hh)
     res["batch_size"] = B.DIR_MAX_BATCH
-    res["speedup"] = res["sequential_seconds"] / min(res["pool_seconds"], res["batches_seconds"],
-                                                     res["batches_two_streams_seconds"])
+    res["speedup"] = res["sequential_seconds"] / min(res["pool_seconds"], res["pool_batching_seconds"],
+                                                     res["batches_seconds"], res["batches_two_streams_seconds"])
     print(json.dumps(res))
 
 
@@ -402,7 +404,7 @@ def serve(args):
     lat = np.zeros(n)
     done_at = np.zeros(n)
     checked = []
-    with B.Pool(slots=args.slots, max_bytes=budget) as pool:
+    with B.Pool(slots=args.slots, max_bytes=budget, max_batch=args.max_batch) as pool:
         # warm-up: every size and setting once, so workspaces exist
         for k in range(len(SERVE_SIZES)):
             for j in range(len(SETTINGS)):
@@ -448,7 +450,7 @@ def serve(args):
     print(json.dumps({"workload": f"Poisson arrivals at {args.rate}/s, {n} requests, sizes 128x128x64 / 256x256x100 / "
                                   f"384x384x128 / 512x512x160 with p 0.3/0.4/0.2/0.1, six settings uniformly, "
                                   f"3 levels 100/50/25",
-                      "storage": args.storage, "slots": args.slots, "budget_bytes": budget,
+                      "storage": args.storage, "slots": args.slots, "max_batch": args.max_batch, "budget_bytes": budget,
                       "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                                      "p99": float(np.percentile(lat, 99) * 1e3),
                                      "max": float(lat.max() * 1e3), "per_size_p50": per_size},
@@ -482,6 +484,8 @@ def main():
     ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")
     ap.add_argument("--slots", type=int, default=8, help="batch32/serve: pool slots (streams)")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serve: pool workspace budget in GiB")
+    ap.add_argument("--max-batch", type=int, default=1,
+                    help="serve: registrations a pool slot may run as one lockstep batch (1: one by one)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain device copies of known size (counter calibration)")
     ap.add_argument("--profile-run", action="store_true",

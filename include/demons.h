@@ -174,9 +174,11 @@ int32_t dir_register(dir_handle *h, const float *d_static, const float *d_moving
 int32_t dir_register_async(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
                            int32_t nz, const double *spacing_mm, const dir_params *params, float *d_field_out);
 
-/* Wait for the registration enqueued by dir_register_async and fill `stats`
- * (may be NULL) as dir_register does; returns its status (DIR_ENUMERIC for a
- * non-finite sum) or DIR_EINVAL when none is in flight. */
+/* Wait for the registration enqueued by dir_register_async (or the batch
+ * enqueued by dir_register_batch_async) and fill `stats` as dir_register
+ * does: NULL, or one entry per registration in flight.  Returns its status
+ * (DIR_ENUMERIC for a non-finite sum in any of them) or DIR_EINVAL when
+ * none is in flight. */
 int32_t dir_wait(dir_handle *h, dir_stats *stats);
 
 /* Deformed image (Sec 2.5 interpolation kernel): d_out(x) = vol(x - v(x)),
@@ -271,6 +273,12 @@ int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_s
                            const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
                            const dir_params *params, float *const *d_field_out, dir_stats *stats);
 
+/* The same batch enqueued without waiting (as dir_register_async); dir_wait
+ * collects it, with stats NULL or an array of `count`. */
+int32_t dir_register_batch_async(dir_handle *h, int32_t count, const float *const *d_static,
+                                 const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
+                                 const dir_params *params, float *const *d_field_out);
+
 /* Request pool (serving).  A pool runs submitted registrations on `slots`
  * handles of its own, each with its own stream, so registrations that arrive
  * while others run overlap with them on the device.  Requests are admitted in
@@ -302,6 +310,14 @@ int32_t dir_pool_poll(dir_pool *p, int64_t ticket, dir_stats *stats, int32_t *do
 int32_t dir_pool_wait(dir_pool *p, int64_t ticket, dir_stats *stats);
 int32_t dir_pool_stats(const dir_pool *p, uint64_t *held_bytes_now, uint64_t *peak_bytes, int32_t *peak_running,
                        int32_t *queued_now);
+/* Registrations one slot may run as a lockstep batch (1..DIR_MAX_BATCH;
+ * 1, the default, admits requests one by one).  Above 1 the request at the
+ * head of the queue is admitted with the queued requests after it that can
+ * run in lockstep with it (dir_register_batch: the same levels, iterations,
+ * sigma, radius and storage), up to the limit, as one batch on one slot,
+ * whose workspace the budget counts.  Results are still bitwise those of
+ * dir_register. */
+int32_t dir_pool_set_max_batch(dir_pool *p, int32_t max_batch);
 
 /* How well a field registers the pair, the two measures the paper follows
  * over the iterations (Sec 3.2): *mse, the mean of (Im - S)^2, and *cc, the

@@ -82,6 +82,8 @@ def lib():
         L.dir_step_stored.argtypes = [vp, i32, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.dir_register_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.dir_register_batch_async.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.dir_pool_set_max_batch.argtypes = [vp, i32]
         L.dir_wait.argtypes = [vp, vp]
         L.dir_set_graphs.argtypes = [vp, i32]
         L.dir_similarity.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
@@ -104,7 +106,8 @@ def lib():
         L.dir_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
-                     "dir_register_async", "dir_register_batch", "dir_wait", "dir_set_graphs", "dir_step_stored", "dir_similarity",
+                     "dir_register_async", "dir_register_batch", "dir_register_batch_async", "dir_wait",
+                     "dir_pool_set_max_batch", "dir_set_graphs", "dir_step_stored", "dir_similarity",
                      "dir_workspace_bytes", "dir_pool_create", "dir_pool_destroy", "dir_pool_submit",
                      "dir_pool_progress", "dir_pool_poll", "dir_pool_wait", "dir_pool_stats",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
@@ -289,12 +292,7 @@ def dir_register(h, static, moving, params, field_out=None, spacing_mm=None, his
     return field_out, stats
 
 
-def dir_register_batch(h, statics, movings, params, field_outs=None, spacing_mm=None, history=True):
-    """Lockstep batch of len(statics) registrations (at most DIR_MAX_BATCH),
-    of any sizes; `params` is a list of dir_params that agree in levels,
-    iterations, sigma, radius and storage; `spacing_mm` is None or one triple
-    per registration.  Returns a list of (field, stats dict), each field
-    bitwise the one dir_register computes."""
+def _batch_args(h, statics, movings, params, field_outs, spacing_mm, history):
     count = len(statics)
     if not 1 <= count <= DIR_MAX_BATCH or len(movings) != count or len(params) != count:
         raise ValueError(f"1..{DIR_MAX_BATCH} registrations, with one moving image and one dir_params each")
@@ -319,12 +317,31 @@ def dir_register_batch(h, statics, movings, params, field_outs=None, spacing_mm=
         sts.append(st)
         bufs.append(buf)
     sarr = (dir_stats * count)(*sts)
-    rc = lib().dir_register_batch(h.ptr, count, ptrs(statics), ptrs(movings), (ctypes.c_int32 * (3 * count))(*dims),
-                                  sp, parr, ptrs(outs), sarr)
-    res = [(outs[k], _stats_dict(rc, sarr[k], bufs[k])) for k in range(count)]
+    args = (h.ptr, count, ptrs(statics), ptrs(movings), (ctypes.c_int32 * (3 * count))(*dims), sp, parr, ptrs(outs))
+    return args, outs, sarr, bufs
+
+
+def dir_register_batch(h, statics, movings, params, field_outs=None, spacing_mm=None, history=True):
+    """Lockstep batch of len(statics) registrations (at most DIR_MAX_BATCH),
+    of any sizes; `params` is a list of dir_params that agree in levels,
+    iterations, sigma, radius and storage; `spacing_mm` is None or one triple
+    per registration.  Returns a list of (field, stats dict), each field
+    bitwise the one dir_register computes."""
+    args, outs, sarr, bufs = _batch_args(h, statics, movings, params, field_outs, spacing_mm, history)
+    rc = lib().dir_register_batch(*args, sarr)
+    res = [(outs[k], _stats_dict(rc, sarr[k], bufs[k])) for k in range(len(outs))]
     if rc != DIR_OK:
         raise DemonsError(rc, "dir_register_batch")
     return res
+
+
+def dir_register_batch_async(h, statics, movings, params, field_outs=None, spacing_mm=None, history=True):
+    """dir_register_batch without the wait; dir_wait(h) returns its list of
+    (field, stats dict)."""
+    args, outs, sarr, bufs = _batch_args(h, statics, movings, params, field_outs, spacing_mm, history)
+    _check(lib().dir_register_batch_async(*args), "dir_register_batch_async")
+    h.inflight = ("batch", (statics, movings, params), outs, sarr, bufs)
+    return outs
 
 
 def dir_register_async(h, static, moving, params, field_out=None, spacing_mm=None, history=True):
@@ -347,6 +364,14 @@ def dir_wait(h):
     """Collect the registration enqueued by dir_register_async: (field, stats)."""
     if h.inflight is None:
         raise DemonsError(DIR_EINVAL, "dir_wait: nothing in flight")
+    if h.inflight[0] == "batch":
+        _, _, outs, sarr, bufs = h.inflight
+        rc = lib().dir_wait(h.ptr, sarr)
+        h.inflight = None
+        res = [(outs[k], _stats_dict(rc, sarr[k], bufs[k])) for k in range(len(outs))]
+        if rc != DIR_OK:
+            raise DemonsError(rc, "dir_wait")
+        return res
     _, _, field_out, _, st, buf = h.inflight
     rc = lib().dir_wait(h.ptr, ctypes.byref(st))
     h.inflight = None
@@ -511,13 +536,20 @@ def dir_workspace_bytes(shape_zyx, params):
 
 class Pool:
     """dir_pool: registrations of any size admitted by workspace budget onto
-    `slots` streams.  submit() keeps the request's tensors alive until its
-    result is taken by poll() or wait()."""
+    `slots` streams, up to `max_batch` compatible ones per slot as a lockstep
+    batch.  submit() keeps the request's tensors alive until its result is
+    taken by poll() or wait()."""
 
-    def __init__(self, slots=4, max_bytes=0, device=0):
+    def __init__(self, slots=4, max_bytes=0, device=0, max_batch=1):
         self.ptr = ctypes.c_void_p()
         _check(lib().dir_pool_create(ctypes.byref(self.ptr), int(device), int(slots), ctypes.c_uint64(max_bytes)),
                "dir_pool_create")
+        if max_batch != 1:
+            rc = lib().dir_pool_set_max_batch(self.ptr, int(max_batch))
+            if rc != DIR_OK:
+                lib().dir_pool_destroy(self.ptr)
+                self.ptr = ctypes.c_void_p()
+                raise DemonsError(rc, "dir_pool_set_max_batch")
         self.device = device
         self._live = {}
 

@@ -786,6 +786,28 @@ RegSizes register_sizes(int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
     return z;
 }
 
+// Round a per-registration byte count up to a 256-byte boundary.
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace strides of a batch (validated parameters): per buffer, the
+// largest registration's size rounded up to 256 bytes.
+RegSizes batch_strides(int count, const int32_t *dims, const dir_params *p)
+{
+    RegSizes z{};
+    for (int r = 0; r < count; ++r) {
+        const RegSizes zr = register_sizes(dims[3 * r], dims[3 * r + 1], dims[3 * r + 2], &p[r]);
+        z.pyr = std::max(z.pyr, align256(zr.pyr));
+        z.img0 = std::max(z.img0, align256(zr.img0));
+        z.field = std::max(z.field, align256(zr.field));
+        z.img_a = std::max(z.img_a, align256(zr.img_a));
+        z.img_b = std::max(z.img_b, align256(zr.img_b));
+        z.partials = std::max(z.partials, align256(zr.partials));
+        z.history = std::max(z.history, align256(zr.history));
+        z.state = std::max(z.state, align256(zr.state));
+    }
+    return z;
+}
+
 }  // namespace
 
 namespace dir {
@@ -802,6 +824,17 @@ size_t workspace_after(const dir_handle *h, int32_t nx, int32_t ny, int32_t nz, 
 {
     const RegSizes z = register_sizes(nx, ny, nz, p);
     auto mx = [](size_t a, size_t b) { return a > b ? a : b; };
+    return mx(h->pyr_s.bytes, z.pyr) + mx(h->pyr_m.bytes, z.pyr) + mx(h->img0_s.bytes, z.img0) +
+           mx(h->img0_m.bytes, z.img0) + mx(h->field[0].bytes, z.field) + mx(h->field[1].bytes, z.field) +
+           h->field[2].bytes + mx(h->img_a.bytes, z.img_a) + mx(h->img_b.bytes, z.img_b) +
+           mx(h->partials.bytes, z.partials) + mx(h->history.bytes, z.history) + mx(h->state.bytes, z.state);
+}
+
+size_t workspace_after_batch(const dir_handle *h, int32_t count, const int32_t *dims, const dir_params *p)
+{
+    const RegSizes z = batch_strides(count, dims, p);
+    const size_t c = (size_t)count;
+    auto mx = [c](size_t a, size_t b) { return a > c * b ? a : c * b; };
     return mx(h->pyr_s.bytes, z.pyr) + mx(h->pyr_m.bytes, z.pyr) + mx(h->img0_s.bytes, z.img0) +
            mx(h->img0_m.bytes, z.img0) + mx(h->field[0].bytes, z.field) + mx(h->field[1].bytes, z.field) +
            h->field[2].bytes + mx(h->img_a.bytes, z.img_a) + mx(h->img_b.bytes, z.img_b) +
@@ -928,9 +961,6 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     return DIR_OK;
 }
 
-// Round a per-registration byte count up to a 256-byte boundary.
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
 // Validate a lockstep batch and size the workspace for it: `count`
 // registrations, of sizes dims[3r .. 3r+2] (nx, ny, nz), whose parameters
 // agree in everything the iteration schedule and the smoothing depend on
@@ -942,7 +972,6 @@ int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float 
 {
     if (count < 1 || count > DIR_MAX_BATCH || !S || !M || !dims || !p || !out) return DIR_EINVAL;
     size_t n[kMaxBatch];
-    RegSizes z{};
     for (int r = 0; r < count; ++r) {
         const int32_t nx = dims[3 * r], ny = dims[3 * r + 1], nz = dims[3 * r + 2];
         if (!S[r] || !M[r] || !out[r]) return DIR_EINVAL;
@@ -962,16 +991,8 @@ int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float 
                 overlap(out[q], 3 * n[q], M[r], n[r]))
                 return DIR_EINVAL;
         }
-        const RegSizes zr = register_sizes(nx, ny, nz, &p[r]);
-        z.pyr = std::max(z.pyr, align256(zr.pyr));
-        z.img0 = std::max(z.img0, align256(zr.img0));
-        z.field = std::max(z.field, align256(zr.field));
-        z.img_a = std::max(z.img_a, align256(zr.img_a));
-        z.img_b = std::max(z.img_b, align256(zr.img_b));
-        z.partials = std::max(z.partials, align256(zr.partials));
-        z.history = std::max(z.history, align256(zr.history));
-        z.state = std::max(z.state, align256(zr.state));
     }
+    const RegSizes z = batch_strides(count, dims, p);
     const size_t c = (size_t)count;
     if (z.pyr) {
         DIR_TRY(h->pyr_s.ensure(c * z.pyr));
@@ -1308,8 +1329,10 @@ bool fill_stats(const InFlight &f, const LevelState *hs, const double *hh, dir_s
 }
 
 // Wait for the registration (or batch) in flight and fill stats[0 .. count-1]
-// (may be NULL).  DIR_ENUMERIC if any registration's sums are not finite.
-int collect_register(dir_handle *h, dir_stats *stats)
+// (may be NULL) and, if not NULL, status[0 .. count-1] (DIR_OK or
+// DIR_ENUMERIC each).  DIR_ENUMERIC if any registration's sums are not
+// finite.
+int collect_register(dir_handle *h, dir_stats *stats, int32_t *status = nullptr)
 {
     const InFlight f = h->inflight;
     h->inflight.active = false;
@@ -1327,12 +1350,26 @@ int collect_register(dir_handle *h, dir_stats *stats)
                               sizeof(double) * 4 * f.total_iters);
             if (rc != DIR_OK) return rc;
         }
-        if (!fill_stats(f, hs, hh.data(), stats ? &stats[r] : nullptr)) finite = false;
+        const bool ok = fill_stats(f, hs, hh.data(), stats ? &stats[r] : nullptr);
+        if (status) status[r] = ok ? DIR_OK : DIR_ENUMERIC;
+        if (!ok) finite = false;
     }
     return finite ? DIR_OK : DIR_ENUMERIC;
 }
 
 }  // namespace
+
+namespace dir {
+
+int collect_each(dir_handle *h, dir_stats *stats, int32_t *status)
+{
+    const int rc = enter(h);
+    if (rc != DIR_OK) return rc;
+    if (!h->inflight.active) return DIR_EINVAL;
+    return collect_register(h, stats, status);
+}
+
+}  // namespace dir
 
 extern "C" {
 
@@ -1361,26 +1398,37 @@ int32_t dir_wait(dir_handle *h, dir_stats *stats)
     int rc = enter(h);
     if (rc != DIR_OK) return rc;
     if (!h->inflight.active) return DIR_EINVAL;
-    if (stats && stats->struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
+    if (stats)
+        for (int r = 0; r < h->inflight.count; ++r)
+            if (stats[r].struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
     return collect_register(h, stats);
 }
 
-int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_static,
-                           const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
-                           const dir_params *params, float *const *d_field_out, dir_stats *stats)
+int32_t dir_register_batch_async(dir_handle *h, int32_t count, const float *const *d_static,
+                                 const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
+                                 const dir_params *params, float *const *d_field_out)
 {
     int rc = enter_idle(h);
     if (rc != DIR_OK) return rc;
-    if (count < 1 || count > DIR_MAX_BATCH) return DIR_EINVAL;
-    if (stats)
-        for (int r = 0; r < count; ++r)
-            if (stats[r].struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
     RegPlan pl;
     rc = plan_batch(h, count, d_static, d_moving, dims, spacing_mm, params, d_field_out, pl);
     if (rc != DIR_OK) return rc;
     rc = enqueue_register(h, pl, false);
     if (rc != DIR_OK) return rc;
     note_inflight(h, pl);
+    return DIR_OK;
+}
+
+int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_static,
+                           const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
+                           const dir_params *params, float *const *d_field_out, dir_stats *stats)
+{
+    if (count < 1 || count > DIR_MAX_BATCH) return DIR_EINVAL;
+    if (stats)
+        for (int r = 0; r < count; ++r)
+            if (stats[r].struct_size != (int32_t)sizeof(dir_stats)) return DIR_EINVAL;
+    const int rc = dir_register_batch_async(h, count, d_static, d_moving, dims, spacing_mm, params, d_field_out);
+    if (rc != DIR_OK) return rc;
     return collect_register(h, stats);
 }
 

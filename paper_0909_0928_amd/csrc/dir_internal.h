@@ -199,5 +199,11 @@ size_t workspace_now(const dir_handle *h);
 // Bytes the handle holds after a registration with these parameters
 // (each buffer grows to the larger of its current and needed size).
 size_t workspace_after(const dir_handle *h, int32_t nx, int32_t ny, int32_t nz, const dir_params *p);
+// The same for a lockstep batch (dir_register_batch arguments).
+size_t workspace_after_batch(const dir_handle *h, int32_t count, const int32_t *dims, const dir_params *p);
 void workspace_release(dir_handle *h);  // free the workspace (no registration may be in flight)
+// Collect what is in flight on h (one registration or a batch): stats[r]
+// (struct_size set) and status[r] (DIR_OK or DIR_ENUMERIC) per registration;
+// the device status of the whole as the return value.
+int collect_each(dir_handle *h, dir_stats *stats, int32_t *status);
 }  // namespace dir

@@ -2,9 +2,12 @@
 // a fixed set of slots (a handle with its own stream each), admitted in
 // arrival order while a slot is free and the workspace the slots hold stays
 // within a byte budget, so requests that arrive while others run overlap with
-// them on the device.  The pool is driven by the caller's calls (no thread of
-// its own): every call first collects finished registrations, without
-// blocking, and admits queued ones.
+// them on the device.  With a batch limit above 1, the request at the head of
+// the queue is admitted together with the queued requests after it that can
+// run in lockstep with it (the same levels, iterations, sigma, radius and
+// storage), up to that limit, as one lockstep batch on one slot.  The pool is
+// driven by the caller's calls (no thread of its own): every call first
+// collects finished registrations, without blocking, and admits queued ones.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -21,8 +24,9 @@ namespace {
 struct Slot {
     dir_handle *h = nullptr;
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;  // recorded after the registration's work
-    int64_t ticket = 0;         // 0: free
+    hipEvent_t done = nullptr;          // recorded after the registration's work
+    int count = 0;                      // registrations running (0: free)
+    int64_t tickets[DIR_MAX_BATCH] = {};
 };
 
 struct Request {
@@ -45,6 +49,7 @@ struct Result {
 struct dir_pool {
     int device = 0;
     uint64_t budget = 0;  // 0: no limit
+    int max_batch = 1;    // registrations one slot may run in lockstep
     std::vector<Slot> slots;
     std::deque<Request> queue;
     std::map<int64_t, Result> results;
@@ -66,73 +71,147 @@ uint64_t held_bytes(const dir_pool *p)
 int32_t collect(dir_pool *p)
 {
     for (Slot &s : p->slots) {
-        if (!s.ticket) continue;
+        if (!s.count) continue;
         const hipError_t q = hipEventQuery(s.done);
         if (q == hipErrorNotReady) continue;
-        Result r;
-        memset(&r.stats, 0, sizeof r.stats);
-        r.stats.struct_size = sizeof(dir_stats);
-        r.status = q == hipSuccess ? dir_wait(s.h, &r.stats) : DIR_EDEVICE;
-        if (q != hipSuccess) dir_wait(s.h, nullptr);
-        p->results[s.ticket] = r;
-        s.ticket = 0;
+        dir_stats st[DIR_MAX_BATCH];
+        int32_t status[DIR_MAX_BATCH];
+        memset(st, 0, sizeof st);
+        for (int r = 0; r < s.count; ++r) {
+            st[r].struct_size = sizeof(dir_stats);
+            status[r] = DIR_EDEVICE;
+        }
+        const int rc = dir::collect_each(s.h, st, status);
+        for (int r = 0; r < s.count; ++r) {
+            Result res;
+            res.stats = st[r];
+            res.status = (q != hipSuccess || (rc != DIR_OK && rc != DIR_ENUMERIC)) ? DIR_EDEVICE : status[r];
+            p->results[s.tickets[r]] = res;
+        }
+        s.count = 0;
     }
     return DIR_OK;
 }
 
-// Admit queued requests in order while one fits.
+// Whether request b can run in lockstep with request a.
+bool lockstep_with(const Request &a, const Request &b)
+{
+    const dir_params &x = a.params, &y = b.params;
+    if (x.levels != y.levels || x.sigma != y.sigma || x.radius != y.radius || x.storage != y.storage) return false;
+    for (int l = 0; l < x.levels; ++l)
+        if (x.iters[l] != y.iters[l]) return false;
+    return true;
+}
+
+// The head request and the queued ones that can join it, in queue order.
+struct Group {
+    int count = 0;
+    int idx[DIR_MAX_BATCH];  // queue positions
+    int32_t dims[3 * DIR_MAX_BATCH];
+    dir_params params[DIR_MAX_BATCH];
+};
+
+Group head_group(const dir_pool *p)
+{
+    Group g;
+    const Request &head = p->queue.front();
+    for (int i = 0; i < (int)p->queue.size() && g.count < p->max_batch; ++i) {
+        const Request &q = p->queue[i];
+        if (i > 0 && (!lockstep_with(head, q) || q.has_spacing != head.has_spacing)) continue;
+        g.idx[g.count] = i;
+        g.dims[3 * g.count] = q.nx;
+        g.dims[3 * g.count + 1] = q.ny;
+        g.dims[3 * g.count + 2] = q.nz;
+        g.params[g.count] = q.params;
+        ++g.count;
+    }
+    return g;
+}
+
+// Workspace slot s holds after running group g.
+uint64_t bytes_after(const Slot &s, const Group &g)
+{
+    return g.count == 1 ? dir::workspace_after(s.h, g.dims[0], g.dims[1], g.dims[2], &g.params[0])
+                        : dir::workspace_after_batch(s.h, g.count, g.dims, g.params);
+}
+
+// Enqueue group g on slot s; the requests' results on failure.
+void start(dir_pool *p, Slot &s, const Group &g)
+{
+    const float *S[DIR_MAX_BATCH], *M[DIR_MAX_BATCH];
+    float *out[DIR_MAX_BATCH];
+    double spacing[3 * DIR_MAX_BATCH];
+    int64_t tickets[DIR_MAX_BATCH];
+    for (int r = 0; r < g.count; ++r) {
+        const Request &q = p->queue[g.idx[r]];
+        S[r] = q.S;
+        M[r] = q.M;
+        out[r] = q.out;
+        tickets[r] = q.ticket;
+        for (int k = 0; k < 3; ++k) spacing[3 * r + k] = q.spacing[k];
+    }
+    const bool has_spacing = p->queue[g.idx[0]].has_spacing;
+    int32_t rc;
+    if (g.count == 1)
+        rc = dir_register_async(s.h, S[0], M[0], g.dims[0], g.dims[1], g.dims[2], has_spacing ? spacing : nullptr,
+                                &g.params[0], out[0]);
+    else
+        rc = dir_register_batch_async(s.h, g.count, S, M, g.dims, has_spacing ? spacing : nullptr, g.params, out);
+    if (rc == DIR_OK && hipEventRecord(s.done, s.stream) != hipSuccess) {
+        dir::collect_each(s.h, nullptr, nullptr);
+        rc = DIR_EDEVICE;
+    }
+    if (rc == DIR_OK) {
+        s.count = g.count;
+        for (int r = 0; r < g.count; ++r) s.tickets[r] = tickets[r];
+    } else {
+        for (int r = 0; r < g.count; ++r) p->results[tickets[r]] = Result{rc, {}};
+    }
+    for (int r = g.count - 1; r >= 0; --r) p->queue.erase(p->queue.begin() + g.idx[r]);  // positions ascend
+}
+
+// Admit queued requests in order while the head (with as much of its group
+// as fits) fits.
 int32_t admit(dir_pool *p)
 {
     while (!p->queue.empty()) {
-        const Request &q = p->queue.front();
-        // the free slot whose workspace grows least
-        int best = -1;
-        uint64_t best_growth = 0;
-        for (int i = 0; i < (int)p->slots.size(); ++i) {
-            const Slot &s = p->slots[i];
-            if (s.ticket) continue;
-            const uint64_t g = dir::workspace_after(s.h, q.nx, q.ny, q.nz, &q.params) - dir::workspace_now(s.h);
-            if (best < 0 || g < best_growth) {
-                best = i;
-                best_growth = g;
+        Group g = head_group(p);
+        int chosen = -1;
+        while (chosen < 0) {
+            // the free slot whose workspace grows least
+            int best = -1;
+            uint64_t best_growth = 0;
+            for (int i = 0; i < (int)p->slots.size(); ++i) {
+                const Slot &s = p->slots[i];
+                if (s.count) continue;
+                const uint64_t gr = bytes_after(s, g) - dir::workspace_now(s.h);
+                if (best < 0 || gr < best_growth) {
+                    best = i;
+                    best_growth = gr;
+                }
             }
-        }
-        if (best < 0) return DIR_OK;  // every slot busy
-        Slot &s = p->slots[best];
-        if (p->budget) {
-            uint64_t after = held_bytes(p) + best_growth;
-            if (after > p->budget) {
+            if (best < 0) return DIR_OK;  // every slot busy
+            Slot &s = p->slots[best];
+            bool fits = !p->budget || held_bytes(p) + best_growth <= p->budget;
+            if (!fits) {
                 // give back the workspace of the other free slots, then this one's
                 for (Slot &o : p->slots)
-                    if (!o.ticket && &o != &s) dir::workspace_release(o.h);
-                after = held_bytes(p) + (dir::workspace_after(s.h, q.nx, q.ny, q.nz, &q.params) -
-                                         dir::workspace_now(s.h));
-                if (after > p->budget) {
+                    if (!o.count && &o != &s) dir::workspace_release(o.h);
+                fits = held_bytes(p) + (bytes_after(s, g) - dir::workspace_now(s.h)) <= p->budget;
+                if (!fits) {
                     dir::workspace_release(s.h);
-                    after = held_bytes(p) + dir::workspace_after(s.h, q.nx, q.ny, q.nz, &q.params);
+                    fits = held_bytes(p) + bytes_after(s, g) <= p->budget;
                 }
-                if (after > p->budget) return DIR_OK;  // wait for a running registration
             }
+            if (fits) chosen = best;
+            else if (g.count > 1) --g.count;  // a smaller group (down to the head alone, which fits an idle pool)
+            else return DIR_OK;               // wait for a running registration
         }
-        const int32_t rc = dir_register_async(s.h, q.S, q.M, q.nx, q.ny, q.nz, q.has_spacing ? q.spacing : nullptr,
-                                              &q.params, q.out);
-        if (rc == DIR_OK) {
-            const hipError_t e = hipEventRecord(s.done, s.stream);
-            if (e != hipSuccess) {
-                dir_wait(s.h, nullptr);
-                p->results[q.ticket] = Result{DIR_EDEVICE, {}};
-            } else {
-                s.ticket = q.ticket;
-            }
-        } else {
-            Result r{rc, {}};
-            p->results[q.ticket] = r;
-        }
-        p->queue.pop_front();
+        start(p, p->slots[chosen], g);
         const uint64_t held = held_bytes(p);
         if (held > p->peak_bytes) p->peak_bytes = held;
         int32_t running = 0;
-        for (const Slot &o : p->slots) running += o.ticket ? 1 : 0;
+        for (const Slot &o : p->slots) running += o.count;
         if (running > p->peak_running) p->peak_running = running;
     }
     return DIR_OK;
@@ -155,7 +234,8 @@ bool queued(const dir_pool *p, int64_t t)
 int running_slot(const dir_pool *p, int64_t t)
 {
     for (int i = 0; i < (int)p->slots.size(); ++i)
-        if (p->slots[i].ticket == t) return i;
+        for (int r = 0; r < p->slots[i].count; ++r)
+            if (p->slots[i].tickets[r] == t) return i;
     return -1;
 }
 
@@ -213,12 +293,19 @@ int32_t dir_pool_destroy(dir_pool *p)
     if (!p) return DIR_OK;
     hipSetDevice(p->device);
     for (Slot &s : p->slots) {
-        if (s.ticket) dir_wait(s.h, nullptr);
+        if (s.count) dir::collect_each(s.h, nullptr, nullptr);
         dir_destroy(s.h);
         hipEventDestroy(s.done);
         hipStreamDestroy(s.stream);
     }
     delete p;
+    return DIR_OK;
+}
+
+int32_t dir_pool_set_max_batch(dir_pool *p, int32_t max_batch)
+{
+    if (!p || max_batch < 1 || max_batch > DIR_MAX_BATCH) return DIR_EINVAL;
+    p->max_batch = max_batch;
     return DIR_OK;
 }
 
@@ -279,7 +366,7 @@ int32_t dir_pool_wait(dir_pool *p, int64_t ticket, dir_stats *stats)
         if (i < 0 && !queued(p, ticket)) return DIR_EINVAL;
         if (i < 0) {  // queued: wait for the oldest running registration to free room
             for (int k = 0; k < (int)p->slots.size() && i < 0; ++k)
-                if (p->slots[k].ticket) i = k;
+                if (p->slots[k].count) i = k;
             if (i < 0) return DIR_EDEVICE;  // nothing runs and it was not admitted: cannot happen
         }
         if (hipEventSynchronize(p->slots[i].done) != hipSuccess) return DIR_EDEVICE;

@@ -186,3 +186,21 @@ def test_batch_at_the_benchmark_size(B, h):
     params = [B.make_params(v, [100, 50, 25], sigma=1.5, alpha=a) for v, a in SIX]
     alone = _alone(B, h, [(S, M)] * len(SIX), params)
     _check_equal(B.dir_register_batch(h, [S] * len(SIX), [M] * len(SIX), params), alone)
+
+
+def test_async_batch_equals_alone(B):
+    # dir_register_batch_async on a handle with its own stream, collected by dir_wait
+    pairs = _pairs((50, 42, 18), 3, 900)
+    params = [B.make_params(v, [5, 4], sigma=1.0, alpha=a) for v, a in SIX[:3]]
+    hs = B.dir_create(0, stream=torch.cuda.Stream())
+    try:
+        alone = _alone(B, hs, pairs, params)
+        outs = B.dir_register_batch_async(hs, [S for S, _ in pairs], [M for _, M in pairs], params)
+        with pytest.raises(B.DemonsError) as e:  # the handle is busy until dir_wait
+            B.dir_register(hs, pairs[0][0], pairs[0][1], params[0])
+        assert e.value.code == B.DIR_EBUSY
+        res = B.dir_wait(hs)
+        assert [f.data_ptr() for f, _ in res] == [o.data_ptr() for o in outs]
+        _check_equal(res, alone)
+    finally:
+        B.dir_destroy(hs)

@@ -103,3 +103,56 @@ def test_pool_wait_poll_and_errors(B, inputs, alone):
         with pytest.raises(B.DemonsError) as e:
             pool.submit(S, M, _params(B, req))                 # needs more than the whole budget
         assert e.value.code == B.DIR_ENOMEM
+
+
+# compatible schedules (levels, iterations, sigma, storage) at uneven sizes and
+# every variant: a pool with a batch limit runs them as lockstep batches
+COMPATIBLE = [((48, 40, 12), "passive", 1.0), ((96, 80, 40), "inverse_consistent", 1.0),
+              ((33, 29, 17), "active", 1.0), ((64, 64, 32), "double", 0.4), ((27, 45, 9), "evolved", 1.0),
+              ((80, 64, 24), "passive", 0.4), ((40, 40, 24), "inverse_consistent", 1.0),
+              ((72, 56, 20), "active", 1.0), ((130, 36, 16), "double", 1.0)]
+
+
+@pytest.fixture(scope="module")
+def compatible(B):
+    ins, alone = [], []
+    h = B.dir_create(0)
+    try:
+        for k, (shape, variant, alpha) in enumerate(COMPATIBLE):
+            ph = P.make_phantom(shape, seed=600 + k, max_u=2.5)
+            S, M = _dev(ph.static), _dev(ph.moving)
+            p = B.make_params(variant, [5, 4], sigma=1.0, alpha=alpha)
+            f, st = B.dir_register(h, S, M, p)
+            ins.append((S, M, p))
+            alone.append((f.clone(), st["iters_run"]))
+    finally:
+        B.dir_destroy(h)
+    return ins, alone
+
+
+@pytest.mark.parametrize("slots,max_batch,budget_factor", [(1, 4, 0.0), (2, 8, 0.0), (3, 8, 2.5), (1, 8, 1.0)])
+def test_pool_batches_equal_alone_and_budget_holds(B, compatible, slots, max_batch, budget_factor):
+    ins, alone = compatible
+    needs = [B.dir_workspace_bytes(tuple(S.shape), p) for S, _, p in ins]
+    budget = int(budget_factor * max(needs))  # 0: no limit; 1.0: room for one registration only
+    with B.Pool(slots=slots, max_bytes=budget, max_batch=max_batch) as pool:
+        tickets = [pool.submit(S, M, p) for S, M, p in ins]
+        got = {t: pool.wait(t) for t in reversed(tickets)}  # collect in an order other than submission
+        st = pool.stats()
+    for k, t in enumerate(tickets):
+        f, stats = got[t]
+        assert torch.equal(f, alone[k][0]), COMPATIBLE[k]
+        assert stats["iters_run"] == alone[k][1]
+    if budget:
+        assert st["peak_bytes"] <= budget
+    if budget_factor == 0.0:
+        assert st["peak_running"] >= 2  # requests ran as batches (one slot) or overlapped
+    assert st["peak_running"] <= slots * max_batch
+    assert st["queued"] == 0
+
+
+def test_pool_rejects_a_bad_batch_limit(B):
+    for bad in (0, B.DIR_MAX_BATCH + 1):
+        with pytest.raises(B.DemonsError) as e:
+            B.Pool(slots=1, max_batch=bad)
+        assert e.value.code == B.DIR_EINVAL
