@@ -204,3 +204,36 @@ def test_async_batch_equals_alone(B):
         _check_equal(res, alone)
     finally:
         B.dir_destroy(hs)
+
+
+def test_non_finite_input_is_reported_per_registration(B, h):
+    # a NaN voxel in one moving image makes that registration's sums
+    # non-finite (DIR_ENUMERIC); the others of its batch are unaffected
+    pairs = _pairs((36, 30, 14), 3, 920)
+    bad = pairs[1][1].clone()
+    bad[7, 11, 13] = float("nan")
+    pairs[1] = (pairs[1][0], bad)
+    params = [B.make_params(v, [4, 3], sigma=1.0, alpha=a) for v, a in SIX[:3]]
+    with pytest.raises(B.DemonsError) as e:
+        B.dir_register(h, pairs[1][0], pairs[1][1], params[1])
+    assert e.value.code == B.DIR_ENUMERIC
+    good = _alone(B, h, [pairs[0], pairs[2]], [params[0], params[2]])
+    with pytest.raises(B.DemonsError) as e:
+        B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params)
+    assert e.value.code == B.DIR_ENUMERIC
+    # through a batching pool each ticket carries its own status
+    (Sb, Mb), = _pairs((160, 160, 80), 1, 930)
+    with B.Pool(slots=1, max_batch=3) as pool:
+        # a long registration occupies the only slot, so the next three queue and are admitted together
+        blocker = pool.submit(Sb, Mb, B.make_params("passive", [30, 20], sigma=1.0))
+        tickets = [pool.submit(S, M, p) for (S, M), p in zip(pairs, params)]
+        pool.wait(blocker)
+        f0, _ = pool.wait(tickets[0])
+        with pytest.raises(B.DemonsError) as e:
+            pool.wait(tickets[1])
+        assert e.value.code == B.DIR_ENUMERIC
+        f2, _ = pool.wait(tickets[2])
+        assert pool.stats()["peak_running"] == 3
+    assert torch.equal(f0, good[0][0]) and torch.equal(f2, good[1][0])
+    f, _ = B.dir_register(h, pairs[0][0], pairs[0][1], params[0])  # the handle still works
+    assert torch.equal(f, good[0][0])
