@@ -104,3 +104,26 @@ def test_size_limit_and_empty_volumes():
     for shape in ((1, 1, 357913942), (1024, 1024, 342), (0, 4, 4), (4, 0, 4), (4, 4, 0), (4, -1, 4)):
         with pytest.raises(B.DemonsError):
             B.dir_workspace_bytes(shape, p)
+
+
+def test_batch_and_pool_argument_checks():
+    """Batch and pool entry points reject bad arguments before any device call."""
+    from paper_0909_0928_amd import binding as B
+    L = B.lib()
+    assert B.DIR_MAX_BATCH == 8
+    # NULL handle / pool
+    assert L.dir_register_batch(None, 1, None, None, None, None, None, None, None) == B.DIR_EINVAL
+    assert L.dir_register_batch_async(None, 1, None, None, None, None, None, None) == B.DIR_EINVAL
+    assert L.dir_pool_set_max_batch(None, 2) == B.DIR_EINVAL
+    assert L.dir_wait(None, None) == B.DIR_EINVAL
+    # the binding checks list lengths and counts before touching the library
+    p = B.make_params("passive", [2], sigma=1.0)
+    h = B.Handle(None, 0)
+    with pytest.raises(ValueError):
+        B.dir_register_batch(h, [], [], [])
+    with pytest.raises(ValueError):
+        B.dir_register_batch(h, [None] * 9, [None] * 9, [p] * 9)
+    with pytest.raises(ValueError):
+        B.dir_register_batch(h, [None, None], [None], [p, p])
+    with pytest.raises(ValueError):  # not GPU tensors
+        B.dir_register_batch(h, [None], [None], [p])
