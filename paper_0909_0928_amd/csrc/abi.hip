@@ -31,7 +31,7 @@ struct DevBuf {
     {
         if (need <= bytes) return hipSuccess;
         if (p) {
-            hipFree(p);
+            (void)hipFree(p);
             p = nullptr;
             bytes = 0;
         }
@@ -41,7 +41,7 @@ struct DevBuf {
     }
     void release()
     {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -242,11 +242,11 @@ void Timer::reset()
 void Timer::release()
 {
     for (const Rec &r : pending_) {
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     pending_.clear();
-    for (hipEvent_t e : pool_) hipEventDestroy(e);
+    for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
     pool_.clear();
 }
 
@@ -305,9 +305,9 @@ int32_t dir_destroy(dir_handle *h)
 {
     if (!h) return DIR_OK;
     int rc = enter(h);
-    if (rc == DIR_OK) hipStreamSynchronize(h->stream);
+    if (rc == DIR_OK) (void)hipStreamSynchronize(h->stream);
     h->timer.release();
-    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     h->pyr_s.release();
     h->pyr_m.release();
     for (auto &f : h->field) f.release();
@@ -336,7 +336,7 @@ int32_t dir_set_graphs(dir_handle *h, int32_t enable)
     h->graphs = enable != 0;
     if (!h->graphs && h->graph_exec) {
         rc = finish(h);
-        hipGraphExecDestroy(h->graph_exec);
+        (void)hipGraphExecDestroy(h->graph_exec);
         h->graph_exec = nullptr;
     }
     return rc;
@@ -854,7 +854,7 @@ void workspace_release(dir_handle *h)
     h->history.release();
     h->state.release();
     if (h->graph_exec) {
-        hipGraphExecDestroy(h->graph_exec);
+        (void)hipGraphExecDestroy(h->graph_exec);
         h->graph_exec = nullptr;
     }
 }
@@ -1240,12 +1240,12 @@ int capture_register(dir_handle *h, const RegPlan &pl, hipGraphExec_t *exec)
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->stream, &g);
     if (rc != DIR_OK) {
-        if (e == hipSuccess && g) hipGraphDestroy(g);
+        if (e == hipSuccess && g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
     const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (ei != hipSuccess) return fail_hip(ei, "hipGraphInstantiate");
     return DIR_OK;
 }
@@ -1280,7 +1280,7 @@ int submit_register(dir_handle *h, const float *d_static, const float *d_moving,
         const GraphKey key = graph_key(h, pl, p);
         if (!h->graph_exec || memcmp(&key, &h->graph_key, sizeof key) != 0) {
             if (h->graph_exec) {
-                hipGraphExecDestroy(h->graph_exec);
+                (void)hipGraphExecDestroy(h->graph_exec);
                 h->graph_exec = nullptr;
             }
             rc = capture_register(h, pl, &h->graph_exec);

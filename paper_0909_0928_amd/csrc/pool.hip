@@ -277,8 +277,8 @@ int32_t dir_pool_create(dir_pool **out, int32_t device, int32_t slots, uint64_t 
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
             dir_create(&s.h, device, s.stream) != DIR_OK) {
             if (s.h) dir_destroy(s.h);
-            if (s.done) hipEventDestroy(s.done);
-            if (s.stream) hipStreamDestroy(s.stream);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
             dir_pool_destroy(p);
             return DIR_EDEVICE;
         }
@@ -291,12 +291,12 @@ int32_t dir_pool_create(dir_pool **out, int32_t device, int32_t slots, uint64_t 
 int32_t dir_pool_destroy(dir_pool *p)
 {
     if (!p) return DIR_OK;
-    hipSetDevice(p->device);
+    (void)hipSetDevice(p->device);
     for (Slot &s : p->slots) {
         if (s.count) dir::collect_each(s.h, nullptr, nullptr);
         dir_destroy(s.h);
-        hipEventDestroy(s.done);
-        hipStreamDestroy(s.stream);
+        (void)hipEventDestroy(s.done);
+        (void)hipStreamDestroy(s.stream);
     }
     delete p;
     return DIR_OK;
