@@ -213,17 +213,25 @@ __global__ __launch_bounds__(256) void k_compose(const void *__restrict__ h, int
     constexpr unsigned E = St::kBytes;
     const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
     const __amdgpu_buffer_rsrc_t H = make_rsrc(h, 3u * E * N);
-    // p = (x, y, z) - (hx, hy, hz): the position is kept as the displacement
+    // p = (x, y, z) - (hx, hy, hz): the position is kept as the displacement.
+    // K updates of p, then h at the last p: K + 1 samples.  A sample equal to
+    // the one before is a fixed point of the FP32 map, which every later
+    // sample repeats, so the loop ends there with the same result.
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-    for (int k = 0; k < K; ++k)
-        bsample3<St>(H, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz), E * N, hx, hy, hz);
-    float ax, ay, az;
-    bsample3<St>(H, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz), E * N, ax, ay, az);
+    for (int k = 0; k <= K; ++k) {
+        float sx, sy, sz;
+        bsample3<St>(H, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz), E * N, sx, sy, sz);
+        const bool fixed = sx == hx && sy == hy && sz == hz;
+        hx = sx;
+        hy = sy;
+        hz = sz;
+        if (fixed) break;
+    }
     const __amdgpu_buffer_rsrc_t O = make_rsrc(out, 12u * N);
     const unsigned o = 4u * (unsigned)(x + nx * (y + ny * z));
-    bstore(O, 2.0f * ax, o, 0u);
-    bstore(O, 2.0f * ay, o, 4u * N);
-    bstore(O, 2.0f * az, o, 8u * N);
+    bstore(O, 2.0f * hx, o, 0u);
+    bstore(O, 2.0f * hy, o, 4u * N);
+    bstore(O, 2.0f * hz, o, 8u * N);
 }
 
 // Similarity of S and the deformed M (Sec 3.2 follows registrations by the
