@@ -1149,31 +1149,47 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
 
     // ---- image pyramids in the storage format (Sec 2.3) ----
     // Level 1 is restricted from the caller's FP32 images; with 16-bit
-    // storage the finest level itself is a converted copy.
+    // storage the finest level itself is a converted copy.  Registrations of
+    // a batch that are given the same image (the same device pointer and
+    // size) share its pyramid: it is built once.
     const void *Sk[kMaxBatch][DIR_MAX_LEVELS], *Mk[kMaxBatch][DIR_MAX_LEVELS];
-    for (int r = 0; r < B; ++r) {
-        const Dims *dims = pl.dims[r];
-        Sk[r][0] = pl.S[r];
-        Mk[r][0] = pl.M[r];
-        size_t off = 0;
-        for (int k = 1; k < L; ++k) {
-            char *s = part<char>(h->pyr_s, zs.pyr, r) + es * off, *m = part<char>(h->pyr_m, zs.pyr, r) + es * off;
-            const int in_fmt = k == 1 ? kStoreF32 : st_fmt;
-            h->timer.level = k;
-            DIR_TRY(launch_restrict(c, Sk[r][k - 1], in_fmt, dims[k - 1], s, st_fmt, dims[k]));
-            DIR_TRY(launch_restrict(c, Mk[r][k - 1], in_fmt, dims[k - 1], m, st_fmt, dims[k]));
-            Sk[r][k] = s;
-            Mk[r][k] = m;
-            off += (size_t)dims[k].n();
+    // img[r] -> pyramid pyr[r][.] in pyr_buf's part r (or 16-bit copy img0's part r)
+    auto pyramid = [&](const float *const *img, const void *(*pyr)[DIR_MAX_LEVELS], const DevBuf &pyr_buf,
+                       const DevBuf &img0) -> int {
+        for (int r = 0; r < B; ++r) {
+            int same = -1;
+            for (int q = 0; q < r && same < 0; ++q)
+                if (img[q] == img[r] && pl.dims[q][0].nx == pl.dims[r][0].nx &&
+                    pl.dims[q][0].ny == pl.dims[r][0].ny && pl.dims[q][0].nz == pl.dims[r][0].nz)
+                    same = q;
+            if (same >= 0) {
+                for (int k = 0; k < L; ++k) pyr[r][k] = pyr[same][k];
+                continue;
+            }
+            const Dims *dims = pl.dims[r];
+            pyr[r][0] = img[r];
+            size_t off = 0;
+            for (int k = 1; k < L; ++k) {
+                char *dst = part<char>(pyr_buf, zs.pyr, r) + es * off;
+                h->timer.level = k;
+                DIR_TRY(launch_restrict(c, pyr[r][k - 1], k == 1 ? kStoreF32 : st_fmt, dims[k - 1], dst, st_fmt,
+                                        dims[k]));
+                pyr[r][k] = dst;
+                off += (size_t)dims[k].n();
+            }
+            if (!f32) {
+                h->timer.level = 0;
+                void *dst = part(img0, zs.img0, r);
+                DIR_TRY(launch_convert(c, img[r], kStoreF32, dst, st_fmt, dims[0].n()));
+                pyr[r][0] = dst;
+            }
         }
-        if (!f32) {
-            h->timer.level = 0;
-            void *s0 = part(h->img0_s, zs.img0, r), *m0 = part(h->img0_m, zs.img0, r);
-            DIR_TRY(launch_convert(c, pl.S[r], kStoreF32, s0, st_fmt, dims[0].n()));
-            DIR_TRY(launch_convert(c, pl.M[r], kStoreF32, m0, st_fmt, dims[0].n()));
-            Sk[r][0] = s0;
-            Mk[r][0] = m0;
-        }
+        return DIR_OK;
+    };
+    {
+        int rc = pyramid(pl.S, Sk, h->pyr_s, h->img0_s);
+        if (rc == DIR_OK) rc = pyramid(pl.M, Mk, h->pyr_m, h->img0_m);
+        if (rc != DIR_OK) return rc;
     }
 
     // ---- levels, coarse to fine (Sec 2.3) ----
