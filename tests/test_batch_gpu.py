@@ -239,18 +239,20 @@ def test_non_finite_input_is_reported_per_registration(B, h):
     assert torch.equal(f, good[0][0])
 
 
-@pytest.mark.parametrize("storage,shapes", [
+@pytest.mark.parametrize("storage,shapes,iters", [
     # FP32: each 82 MB level fits the cache three at a time, the four together do not
-    ("f32", [(160, 160, 100), (150, 170, 96), (160, 160, 100), (144, 160, 104)]),
+    ("f32", [(160, 160, 100), (150, 170, 96), (160, 160, 100), (144, 160, 104)], [4, 3, 2]),
+    # the same with one level: no level in lockstep at all
+    ("f32", [(160, 160, 100), (150, 170, 96), (160, 160, 100), (144, 160, 104)], [3]),
     # F16: each 105 MB level fits two at a time, the three together do not
-    ("f16", [(256, 256, 100)] * 3)])
-def test_batch_levels_on_concurrent_streams(B, h, storage, shapes):
+    ("f16", [(256, 256, 100)] * 3, [4, 3, 2])])
+def test_batch_levels_on_concurrent_streams(B, h, storage, shapes, iters):
     # the finest level does not run in lockstep; its registrations run on
     # several streams at once, and each result is still the lone one
     pairs = []
     for k, shape in enumerate(shapes):
         pairs += _pairs(shape, 1, 940 + k)
-    params = [B.make_params(v, [4, 3, 2], sigma=1.5, alpha=a, storage=storage) for v, a in SIX[:len(shapes)]]
+    params = [B.make_params(v, iters, sigma=1.5, alpha=a, storage=storage) for v, a in SIX[:len(shapes)]]
     alone = _alone(B, h, pairs, params)
     for _ in range(2):
         _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
