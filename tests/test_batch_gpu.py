@@ -256,3 +256,33 @@ def test_batch_levels_on_concurrent_streams(B, h, storage, shapes, iters):
     alone = _alone(B, h, pairs, params)
     for _ in range(2):
         _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
+
+
+def test_batch_timing_counts_launches_per_tile_class_and_lane(B):
+    # per-kernel timing on a batch: one force launch per tile class and
+    # iteration on the lockstep level, one per registration and iteration on
+    # the level run on concurrent streams; fields unchanged by the timing
+    shapes = [(160, 160, 100), (100, 150, 96), (160, 160, 100), (150, 170, 96)]  # tile widths 256, 128, 256, 256
+    pairs = []
+    for k, shape in enumerate(shapes):
+        pairs += _pairs(shape, 1, 960 + k)
+    params = [B.make_params(v, [3, 2], sigma=1.0, alpha=a) for v, a in SIX[:4]]
+    hs = B.dir_create(0, stream=torch.cuda.Stream())
+    try:
+        ref = B.dir_register_batch(hs, [S for S, _ in pairs], [M for _, M in pairs], params)
+        ref = [(f.clone(), st) for f, st in ref]
+        B.dir_timing_enable(hs, ["force", "smooth_yz", "restrict"])
+        got = B.dir_register_batch(hs, [S for S, _ in pairs], [M for _, M in pairs], params)
+        reads = {k: (B.dir_timing_read(hs, k, level=0), B.dir_timing_read(hs, k, level=1))
+                 for k in ("force", "smooth_yz", "restrict")}
+        B.dir_timing_enable(hs, ())
+    finally:
+        B.dir_destroy(hs)
+    _check_equal(got, ref)
+    # level 1 (80x80x50 and smaller, lockstep): x tiles of 128 for nx = 80 and of 64 for nx = 50: two force
+    # launches per iteration; one smoothing launch (one z-chunk depth); level 0: 4 registrations x 2 iterations
+    (ms0, n0), (ms1, n1) = reads["force"]
+    assert n1 == 3 * 2 and n0 == 4 * 2 and ms0 > 0 and ms1 > 0
+    (ys0, m0), (ys1, m1) = reads["smooth_yz"]
+    assert m0 == 4 * 2 and m1 >= 3 and ys0 > 0
+    assert reads["restrict"][1][1] == 2 * 4  # S and M of four registrations into level 1
