@@ -581,6 +581,11 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ms
 
+    # smoothing depths timed for these sizes (they leave every result unchanged)
+    depths = {"batch": B.dir_autotune(hb, tuple(S.shape), plist[0], count=len(SETTINGS)),
+              "single": B.dir_autotune(hb, tuple(S.shape), plist[0], count=1)}
+    print(f"[bench] tuned smoothing depths {depths}", file=sys.stderr, flush=True)
+
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -695,7 +700,8 @@ def main():
                                "coarse to fine, sigma 1.5 (R 5), six force settings per step as one "
                                "lockstep batch",
                    "shape_xyz": list(SHAPE), "iters_coarse_to_fine": ITERS, "sigma": SIGMA, "radius": RADIUS,
-                   "settings": [s[0] for s in SETTINGS], "voxel_iters_per_step": vi_reg * len(SETTINGS)},
+                   "settings": [s[0] for s in SETTINGS], "voxel_iters_per_step": vi_reg * len(SETTINGS),
+                   "smoothing_z_depths_finest_first": depths},
         "latency_ms": {"p50": float(np.percentile(lats, 50)) if compare else None,
                        "p99": float(np.percentile(lats, 99)) if compare else None,
                        "per_setting_p50": per_var, "alone": True,

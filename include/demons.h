@@ -279,6 +279,21 @@ int32_t dir_register_batch_async(dir_handle *h, int32_t count, const float *cons
                                  const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
                                  const dir_params *params, float *const *d_field_out);
 
+/* Autotuning of launch shapes that leave every result unchanged.  The y/z
+ * smoothing kernel (Sec 2.5 low-pass filter) walks z in chunks of 2, 4 or 8
+ * planes per workgroup; the depth decides only which workgroup computes which
+ * output.  dir_autotune times each depth on the handle's stream at every
+ * pyramid level of an nx*ny*nz volume under params (levels, sigma, radius,
+ * storage), for launches that carry `count` (1..DIR_MAX_BATCH) registrations
+ * as a lockstep batch does, and keeps the fastest for all handles of the
+ * process; depths (NULL or params->levels entries, finest first) receives
+ * them.  Untuned launches use a fixed rule.  It uses the handle's field
+ * buffers as scratch and blocks.  dir_autotune_clear forgets every choice.
+ * Thread-safe with respect to registrations on other handles. */
+int32_t dir_autotune(dir_handle *h, int32_t nx, int32_t ny, int32_t nz, const dir_params *params, int32_t count,
+                     int32_t *depths);
+void dir_autotune_clear(void);
+
 /* Request pool (serving).  A pool runs submitted registrations on `slots`
  * handles of its own, each with its own stream, so registrations that arrive
  * while others run overlap with them on the device.  Requests are admitted in

@@ -84,6 +84,9 @@ def lib():
         L.dir_register_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.dir_register_batch_async.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.dir_pool_set_max_batch.argtypes = [vp, i32]
+        L.dir_autotune.argtypes = [vp, i32, i32, i32, vp, i32, vp]
+        L.dir_autotune_clear.argtypes = []
+        L.dir_autotune_clear.restype = None
         L.dir_wait.argtypes = [vp, vp]
         L.dir_set_graphs.argtypes = [vp, i32]
         L.dir_similarity.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64)]
@@ -107,7 +110,7 @@ def lib():
         for name in ("dir_create", "dir_set_stream", "dir_destroy", "dir_synchronize", "dir_register", "dir_warp",
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
                      "dir_register_async", "dir_register_batch", "dir_register_batch_async", "dir_wait",
-                     "dir_pool_set_max_batch", "dir_set_graphs", "dir_step_stored", "dir_similarity",
+                     "dir_pool_set_max_batch", "dir_autotune", "dir_set_graphs", "dir_step_stored", "dir_similarity",
                      "dir_workspace_bytes", "dir_pool_create", "dir_pool_destroy", "dir_pool_submit",
                      "dir_pool_progress", "dir_pool_poll", "dir_pool_wait", "dir_pool_stats",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
@@ -342,6 +345,21 @@ def dir_register_batch_async(h, statics, movings, params, field_outs=None, spaci
     _check(lib().dir_register_batch_async(*args), "dir_register_batch_async")
     h.inflight = ("batch", (statics, movings, params), outs, sarr, bufs)
     return outs
+
+
+def dir_autotune(h, shape_zyx, params, count=1):
+    """Time the smoothing kernel's z-chunk depths at every pyramid level of a
+    volume of shape (nz, ny, nx) for launches of `count` registrations and
+    keep the fastest (process-wide); returns them, finest level first."""
+    nz, ny, nx = shape_zyx
+    depths = (ctypes.c_int32 * params.levels)()
+    _check(lib().dir_autotune(h.ptr, int(nx), int(ny), int(nz), ctypes.byref(params), int(count), depths),
+           "dir_autotune")
+    return list(depths)
+
+
+def dir_autotune_clear():
+    lib().dir_autotune_clear()
 
 
 def dir_register_async(h, static, moving, params, field_out=None, spacing_mm=None, history=True):

@@ -1506,6 +1506,41 @@ int32_t dir_wait(dir_handle *h, dir_stats *stats)
     return collect_register(h, stats);
 }
 
+int32_t dir_autotune(dir_handle *h, int32_t nx, int32_t ny, int32_t nz, const dir_params *p, int32_t count,
+                     int32_t *depths)
+{
+    int rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    rc = check_register_params(nx, ny, nz, p);
+    if (rc != DIR_OK) return rc;
+    if (count < 1 || count > DIR_MAX_BATCH) return DIR_EINVAL;
+    const int st = p->storage;
+    const size_t es = storage_bytes(st);
+    const GaussTaps taps = make_taps(p->sigma, resolve_radius(p->sigma, p->radius));
+    Dims d{nx, ny, nz};
+    const size_t field = align256(3 * es * (size_t)d.n());  // one registration's finest field
+    DIR_TRY(h->field[0].ensure((size_t)count * field));
+    DIR_TRY(h->field[1].ensure((size_t)count * field));
+    Ctx c{h->stream, nullptr};
+    // the depth decides the work distribution only, so the values do not matter: zeros
+    DIR_TRY(launch_zero(c, h->field[0].p, (int64_t)(count * field / es), st));
+    for (int k = 0; k < p->levels; ++k) {
+        if (k > 0) d = coarser(d);
+        const void *in[kMaxBatch];
+        void *out[kMaxBatch];
+        for (int r = 0; r < count; ++r) {
+            in[r] = part(h->field[0], field, r);
+            out[r] = part(h->field[1], field, r);
+        }
+        int chosen = 0;
+        DIR_TRY(tune_smooth_yz(c, count, in, 3, d, taps, out, st, 3, &chosen));
+        if (depths) depths[k] = chosen;
+    }
+    return DIR_OK;
+}
+
+void dir_autotune_clear(void) { clear_smooth_yz_tuning(); }
+
 int32_t dir_register_batch_async(dir_handle *h, int32_t count, const float *const *d_static,
                                  const float *const *d_moving, const int32_t *dims, const double *spacing_mm,
                                  const dir_params *params, float *const *d_field_out)

@@ -181,6 +181,13 @@ inline hipError_t launch_smooth_yz(Ctx &c, const void *in, int ncomp, Dims d, co
     return launch_smooth_yz(c, 1, &in, ncomp, &d, taps, &out, st, &stop_at, n, red);
 }
 hipError_t launch_finalize(Ctx &c, const SumsReduce &red, int n);
+// Time the smoothing kernel's z-chunk depths for launches of `count`
+// registrations of size d (fields in[], out[] in format st, `reps` timed
+// launches per depth, blocking) and keep the fastest for such launches in a
+// process-wide table that launch_smooth_yz consults; *chosen receives it.
+hipError_t tune_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, Dims d, const GaussTaps &taps,
+                          void *const *out, int st, int reps, int *chosen);
+void clear_smooth_yz_tuning();
 hipError_t launch_level_reset(Ctx &c, LevelState *st);
 hipError_t launch_compose(Ctx &c, const void *h, int h_st, Dims d, int K, float *out);
 hipError_t launch_zero(Ctx &c, void *p, int64_t n, int st);

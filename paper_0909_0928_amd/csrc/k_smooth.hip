@@ -7,6 +7,10 @@
 // has its own workgroups.
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device_common.h"
 
 namespace dir {
@@ -216,6 +220,27 @@ int yz_depth(Dims d, int ncomp)
     return 2;
 }
 
+// Depths measured by tune_smooth_yz, per (size, components, registrations
+// per launch, bytes per stored value, radius); process-wide.  The depth only
+// decides which workgroup computes which output, never the arithmetic of an
+// output, so it leaves every result unchanged.
+struct YZKey {
+    int nx, ny, nz, ncomp, count, es, R;
+    bool operator<(const YZKey &o) const
+    {
+        return std::tie(nx, ny, nz, ncomp, count, es, R) < std::tie(o.nx, o.ny, o.nz, o.ncomp, o.count, o.es, o.R);
+    }
+};
+std::mutex g_yz_mu;
+std::map<YZKey, int> g_yz_depth;
+
+int yz_tuned(const YZKey &k)
+{
+    std::lock_guard<std::mutex> lock(g_yz_mu);
+    const auto it = g_yz_depth.find(k);
+    return it == g_yz_depth.end() ? 0 : it->second;
+}
+
 template <int R, class St>
 hipError_t launch_yz_r(Ctx &c, const YZArgs &a, int ncomp, int tz, const GaussTaps &taps, const SumsReduce &red)
 {
@@ -266,7 +291,10 @@ hipError_t launch_yz_all(Ctx &c, int count, const void *const *in, int ncomp, co
                          const SumsReduce &red)
 {
     int tz[kMaxBatch];
-    for (int r = 0; r < count; ++r) tz[r] = yz_depth<R>(d[r], ncomp);
+    for (int r = 0; r < count; ++r) {
+        const int t = yz_tuned(YZKey{d[r].nx, d[r].ny, d[r].nz, ncomp, count, (int)St::kBytes, R});
+        tz[r] = t ? t : yz_depth<R>(d[r], ncomp);
+    }
     bool done[kMaxBatch] = {};
     for (int r = 0; r < count; ++r) {
         if (done[r]) continue;
@@ -282,7 +310,93 @@ hipError_t launch_yz_all(Ctx &c, int count, const void *const *in, int ncomp, co
     return hipSuccess;
 }
 
+// Time every z-chunk depth for `count` registrations of size d (fields in
+// and out, `reps` launches each, the fastest launch counting) and keep the
+// fastest depth for such launches.
+template <int R, class St>
+hipError_t tune_yz(Ctx &c, int count, const void *const *in, int ncomp, Dims d, const GaussTaps &taps,
+                   void *const *out, int reps, int *chosen)
+{
+    YZArgs a;
+    memset(&a, 0, sizeof a);
+    for (int r = 0; r < count; ++r) {
+        a.in[r] = in[r];
+        a.out[r] = out[r];
+        a.geo[r].nx = d.nx;
+        a.geo[r].ny = d.ny;
+        a.geo[r].nz = d.nz;
+    }
+    a.count = count;
+    SumsReduce none;
+    memset(&none, 0, sizeof none);  // count 0: no reduction
+    Ev ev;
+    hipError_t e = hipEventCreate(&ev.a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&ev.b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(ev.a);
+        return e;
+    }
+    int best = 0;
+    float best_ms = 0.0f;
+    const int cands[3] = {2, 4, max_tz<R>() == 8 ? 8 : 0};
+    for (int tz : cands) {
+        if (!tz) continue;
+        float fastest = 0.0f;
+        for (int k = 0; k <= reps && e == hipSuccess; ++k) {  // the first launch is not counted
+            if (tz == 8) launch_yz_tz<R, max_tz<R>(), St>(c, ev, a, ncomp, taps, none);
+            else if (tz == 4) launch_yz_tz<R, 4, St>(c, ev, a, ncomp, taps, none);
+            else launch_yz_tz<R, 2, St>(c, ev, a, ncomp, taps, none);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipEventSynchronize(ev.b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.a, ev.b);
+            if (e == hipSuccess && k > 0 && (fastest == 0.0f || ms < fastest)) fastest = ms;
+        }
+        if (e != hipSuccess) break;
+        if (!best || fastest < best_ms) {
+            best = tz;
+            best_ms = fastest;
+        }
+    }
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+    if (e != hipSuccess) return e;
+    {
+        std::lock_guard<std::mutex> lock(g_yz_mu);
+        g_yz_depth[YZKey{d.nx, d.ny, d.nz, ncomp, count, (int)St::kBytes, R}] = best;
+    }
+    *chosen = best;
+    return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t tune_smooth_yz(Ctx &c, int count, const void *const *in, int ncomp, Dims d, const GaussTaps &taps,
+                          void *const *out, int st, int reps, int *chosen)
+{
+    if (count < 1 || count > kMaxBatch || reps < 1) return hipErrorInvalidValue;
+    auto run = [&](auto tag) -> hipError_t {
+        using St = typename decltype(tag)::type;
+        switch (taps.radius) {
+#define DIR_R(r) \
+    case r: return tune_yz<r, St>(c, count, in, ncomp, d, taps, out, reps, chosen);
+            DIR_R(0) DIR_R(1) DIR_R(2) DIR_R(3) DIR_R(4) DIR_R(5) DIR_R(6) DIR_R(7) DIR_R(8)
+            DIR_R(9) DIR_R(10) DIR_R(11) DIR_R(12) DIR_R(13) DIR_R(14) DIR_R(15) DIR_R(16)
+#undef DIR_R
+        default: return hipErrorInvalidValue;
+        }
+    };
+    if (st == kStoreF16) return run(Tag<StF16>{});
+    if (st == kStoreBF16) return run(Tag<StBF16>{});
+    return run(Tag<StF32>{});
+}
+
+void clear_smooth_yz_tuning()
+{
+    std::lock_guard<std::mutex> lock(g_yz_mu);
+    g_yz_depth.clear();
+}
 
 template <class St>
 hipError_t launch_smooth_yz_st(Ctx &c, int count, const void *const *in, int ncomp, const Dims *d,

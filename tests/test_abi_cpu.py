@@ -127,3 +127,11 @@ def test_batch_and_pool_argument_checks():
         B.dir_register_batch(h, [None, None], [None], [p, p])
     with pytest.raises(ValueError):  # not GPU tensors
         B.dir_register_batch(h, [None], [None], [p])
+
+
+def test_autotune_argument_checks():
+    from paper_0909_0928_amd import binding as B
+    L = B.lib()
+    p = B.make_params("passive", [2], sigma=1.0)
+    assert L.dir_autotune(None, 8, 8, 8, ctypes.byref(p), 1, None) == B.DIR_EINVAL
+    B.dir_autotune_clear()  # host only

@@ -286,3 +286,22 @@ def test_batch_timing_counts_launches_per_tile_class_and_lane(B):
     (ys0, m0), (ys1, m1) = reads["smooth_yz"]
     assert m0 == 4 * 2 and m1 >= 3 and ys0 > 0
     assert reads["restrict"][1][1] == 2 * 4  # S and M of four registrations into level 1
+
+
+def test_autotuned_smoothing_depth_leaves_results_unchanged(B, h):
+    # the tuned z-chunk depth changes only which workgroup computes which
+    # output: fields and histories are bitwise those of the fixed rule
+    pairs = _pairs((96, 80, 40), 1, 980) * 6
+    params = [B.make_params(v, [5, 4, 3], sigma=1.5, alpha=a) for v, a in SIX]
+    B.dir_autotune_clear()
+    try:
+        before = B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params)
+        before = [(f.clone(), st) for f, st in before]
+        alone = _alone(B, h, pairs[:1], params[:1])
+        depths6 = B.dir_autotune(h, pairs[0][0].shape, params[0], count=6)
+        depths1 = B.dir_autotune(h, pairs[0][0].shape, params[0], count=1)
+        assert len(depths6) == 3 and all(d in (2, 4, 8) for d in depths6 + depths1)
+        _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), before)
+        _check_equal(_alone(B, h, pairs[:1], params[:1]), alone)
+    finally:
+        B.dir_autotune_clear()
