@@ -91,7 +91,7 @@ def test_uniform_batch_equals_alone(B, h, variant):
                  _alone(B, h, pairs, params))
 
 
-def test_batch_of_one_and_of_eight(B, h):
+def test_batch_of_one_and_of_the_limit(B, h):
     pairs = _pairs((33, 30, 11), B.DIR_MAX_BATCH, 780)
     params = [B.make_params(SIX[k % len(SIX)][0], [4, 3], sigma=1.0, alpha=SIX[k % len(SIX)][1])
               for k in range(B.DIR_MAX_BATCH)]
