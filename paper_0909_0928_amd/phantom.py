@@ -258,3 +258,31 @@ def random_field(shape, seed, amp=2.0):
 # Workloads of the benchmark and the parity tests (sizes in voxels, x fastest).
 CONFIG_SMALL = dict(shape=(64, 64, 32), seed=1, max_u=3.0, spacing_mm=(1.0, 1.0, 1.0))
 CONFIG_FULL = dict(shape=(256, 256, 100), seed=2, max_u=15.0, spacing_mm=(1.1, 1.1, 2.5))
+
+
+def noise_volume_f32(shape, seed, scale=100.0):
+    """Seeded FP32 noise volume [nz, ny, nx], drawn directly in FP32 so that
+    volumes of hundreds of millions of voxels stay cheap to build and hold."""
+    nx, ny, nz = shape
+    out = np.random.default_rng(seed).standard_normal(size=(nz, ny, nx), dtype=np.float32)
+    out *= np.float32(scale)
+    return out
+
+
+def separable_field_f32(shape, seed, amp=2.0):
+    """Seeded smooth FP32 field [3, nz, ny, nx] with |v_c| <= amp per component:
+    each component is a sum of one sinusoid per axis, (f_z + f_y) + f_x in
+    FP32, so a crop of it is a plain slice of the stored array and its
+    slope stays below 0.4 * amp / 3 per voxel."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    out = np.empty((3, nz, ny, nx), dtype=np.float32)
+    for c in range(3):
+        axes = []
+        for n in (nz, ny, nx):
+            k = rng.uniform(0.05, 0.4)
+            ph = rng.uniform(0.0, 2.0 * math.pi)
+            axes.append((np.float32(amp / 3.0) * np.sin(k * np.arange(n) + ph)).astype(np.float32))
+        fz, fy, fx = axes
+        np.add(fz[:, None, None] + fy[None, :, None], fx[None, None, :], out=out[c])
+    return out
