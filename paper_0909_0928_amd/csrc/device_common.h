@@ -277,6 +277,23 @@ __device__ __forceinline__ BCell bcell_disp(int x, int y, int z, float vx, float
     return c;
 }
 
+// The samples at byte offsets o and o + dx (dx 0 or 4) of an FP32 volume from
+// one 8-byte load, so that a trilinear gather issues four loads instead of
+// eight (the address rate of the gather is what bounds the pre-warp kernel).
+// With dx = 0 (an axis clamped onto one grid point) the load ends at o, and
+// so never reaches past the volume, except at offset 0, where it reads the
+// element after the first; the buffer's range check answers a dword past a
+// one-element volume with 0, which is not used.  No branch: a divergent
+// path for that one case costs more than the gathers save.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bpair(__amdgpu_buffer_rsrc_t r, unsigned o, unsigned dx, float &lo, float &hi)
+{
+    const bool back = dx == 0u && o >= 4u;
+    const u32x2 p = __builtin_amdgcn_raw_buffer_load_b64(r, back ? o - 4u : o, 0, 0);
+    lo = __uint_as_float(back ? p.y : p.x);
+    hi = dx ? __uint_as_float(p.y) : lo;
+}
+
 // Trilinear FP64 sample through a buffer resource (see sample64) of a volume
 // stored in format St.
 template <class St = StF32>
@@ -284,6 +301,18 @@ __device__ __forceinline__ double bsample64(__amdgpu_buffer_rsrc_t I, const BCel
 {
     const double ax = c.wx, bx = 1.0 - ax, ay = c.wy, by = 1.0 - ay, az = c.wz, bz = 1.0 - az;
     const unsigned o = c.o, oy = o + c.dy, oz = o + c.dz, oyz = oz + c.dy;
+    if constexpr (St::kBytes == 4) {
+        float a0, a1, b0, b1, c0, c1, d0, d1;
+        bpair(I, o, c.dx, a0, a1);
+        bpair(I, oy, c.dx, b0, b1);
+        bpair(I, oz, c.dx, c0, c1);
+        bpair(I, oyz, c.dx, d0, d1);
+        const double c00 = ax * (double)a0 + bx * (double)a1;
+        const double c10 = ax * (double)b0 + bx * (double)b1;
+        const double c01 = ax * (double)c0 + bx * (double)c1;
+        const double c11 = ax * (double)d0 + bx * (double)d1;
+        return az * (ay * c00 + by * c10) + bz * (ay * c01 + by * c11);
+    }
     const double c00 = ax * (double)St::load(I, o, 0) + bx * (double)St::load(I, o + c.dx, 0);
     const double c10 = ax * (double)St::load(I, oy, 0) + bx * (double)St::load(I, oy + c.dx, 0);
     const double c01 = ax * (double)St::load(I, oz, 0) + bx * (double)St::load(I, oz + c.dx, 0);

@@ -201,3 +201,56 @@ def test_max_size_register(B, h, big):
         ref.append(vc[(slice(None),) + loc])
     ref = np.array(ref).T
     assert _rel(got, ref, np.zeros_like(ref)) < REL_TOL
+
+
+UNIT_ROUNDOFF = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def _round_f32(a, fmt):
+    """FP32 array rounded to the 16-bit format (nearest even), back in FP32,
+    slab by slab: what the kernels hold after their storage conversion."""
+    out = np.empty_like(a)
+    flat_in, flat_out = a.reshape(-1, a.shape[-1]), out.reshape(-1, a.shape[-1])
+    step = 1 << 16
+    for r0 in range(0, flat_in.shape[0], step):
+        x = flat_in[r0:r0 + step]
+        if fmt == "f16":
+            flat_out[r0:r0 + step] = x.astype(np.float16).astype(np.float32)
+        else:  # bfloat16: upper 16 bits of binary32, ties to even (finite inputs)
+            u = x.view(np.uint32)
+            u = (u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) & np.uint32(0xFFFF0000)
+            flat_out[r0:r0 + step] = u.view(np.float32)
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("variant", ["passive", "inverse_consistent"])
+def test_max_size_step_stored(B, h, big, fmt, variant):
+    """16-bit storage at the largest size: the oracle gets the same
+    16-bit-representable inputs, so the step agrees to the rounding of the two
+    stored intermediates (x-smoothed u and the output)."""
+    S, M, v, _, _, _ = big
+    _say(f"max-size dir_step_stored {fmt} {variant}: rounding inputs on the host")
+    Sr, Mr, vr = (_round_f32(a, fmt) for a in (S, M, v))
+    dS, dM, dv = (torch.from_numpy(a).cuda() for a in (Sr, Mr, vr))
+    _say(f"max-size dir_step_stored {fmt} {variant}")
+    out, sums = B.dir_step_stored(h, fmt, variant, 1.0, dS, dM, dv, SIGMA, RADIUS)
+    torch.cuda.synchronize()
+    got = _pick(out)
+    del out, dS, dM, dv
+    torch.cuda.empty_cache()
+    m = RADIUS + math.ceil(AMP) + 3
+    ref = []
+    for p in SAMPLES:
+        sl, loc = _crop(p, m)
+        u, _ = O.force(O.VARIANTS[variant], Sr[sl].astype(np.float64), Mr[sl].astype(np.float64),
+                       vr[(slice(None),) + sl].astype(np.float64))
+        ref.append(O.smooth(u, SIGMA, RADIUS)[(slice(None),) + loc])
+    ref = np.array(ref).T
+    assert _rel(got, ref, np.zeros_like(ref)) <= 2.5 * UNIT_ROUNDOFF[fmt]
+    assert all(math.isfinite(s) and s > 0 for s in sums)
+    total = 0.0
+    for z0 in range(0, NZ, 16):
+        s = vr[:, z0:z0 + 16].astype(np.float64)
+        total += float(np.sqrt((s * s).sum(axis=0)).sum())
+    assert abs(sums[1] - total) <= REL_TOL * total

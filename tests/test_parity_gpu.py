@@ -153,6 +153,27 @@ def test_force(B, h, shape3, variant, alpha):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
 
+@pytest.mark.parametrize("shape3", [(1, 1, 1), (1, 1, 2), (2, 1, 1), (1, 2, 1)])
+@pytest.mark.parametrize("variant", ALL)
+def test_degenerate_volumes(B, h, shape3, variant):
+    """One- and two-voxel volumes: every sample clamped onto the border, the
+    trilinear gathers at the volume's first element and its last."""
+    S, M = _img(shape3, 80), _img(shape3, 81)
+    v = _fld(shape3, 82)
+    u_gpu, sums_gpu = B.dir_force(h, variant, 1.0, dev(S), dev(M), dev(v))
+    u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v)
+    assert rel(host(u_gpu) - v, u_ref - v) < REL_TOL
+    for k in range(3):
+        assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
+    out, _ = B.dir_step(h, variant, 1.0, dev(S), dev(M), dev(v), 1.5, 5)
+    # the update is often zero here (no gradient along a one-voxel axis), so
+    # the error is taken relative to the field itself
+    assert rel(host(out), O.smooth(u_ref, 1.5, 5)) < REL_TOL
+    mse, _ = B.dir_similarity(h, dev(S), dev(M), dev(v))
+    d = O.warp(M, v) - S
+    assert abs(mse - float((d * d).mean())) <= 1e-9 * float((d * d).mean())
+
+
 STEP_SHAPES = [(11, 13, 17), (9, 33, 65), (20, 40, 72), (7, 30, 129), (2, 3, 300), (1, 2, 257), (3, 4, 530), (1, 3, 1100)]
 
 
