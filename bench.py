@@ -22,7 +22,9 @@ Prints one JSON line:
   - roofline: the kernel that takes the most device time, its algorithmic
     bytes per launch over its average launch time, from a separate pass of
     batch steps in which its launches carry dispatch-stamped HIP events;
-  - cpu_baseline: the FP64 CPU oracle on a bounded sample of the workload.
+  - cpu_baseline: the FP64 CPU oracle on a bounded sample of the workload;
+  - parity: each setting's whole-registration field against the oracle's
+    (RMS over voxels of the difference), from the same oracle runs.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -38,6 +40,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+RMS_BOUND_VOX = 0.01   # end-to-end field RMS difference against the oracle, voxels
 SHAPE = (256, 256, 100)          # nx, ny, nz
 ITERS = [100, 50, 25]            # coarsest first
 SIGMA = 1.5
@@ -118,17 +121,27 @@ def measured_traffic(kernel):
     return rec["traffic_bytes_per_launch"], "profiles/" + os.path.basename(path)
 
 
-def cpu_baseline(S, M):
-    """The FP64 oracle on one full step of the same workload (all six settings)."""
+def cpu_baseline(S, M, gpu_fields=None):
+    """The FP64 oracle on one full step of the same workload (all six settings).
+
+    With gpu_fields (setting -> the GPU's FP32 field of that registration),
+    also the RMS over voxels of |GPU field - oracle field| per setting, taken
+    outside the timed calls."""
     import oracle as O
-    t0 = time.perf_counter()
-    for _, var, alpha in SETTINGS:
-        O.register(S, M, O.VARIANTS[var], ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha)
-    dt = time.perf_counter() - t0
+    dt = 0.0
+    rms = {}
+    for name, var, alpha in SETTINGS:
+        t0 = time.perf_counter()
+        f, _, _, _ = O.register(S, M, O.VARIANTS[var], ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha)
+        dt += time.perf_counter() - t0
+        if gpu_fields is not None and name in gpu_fields:
+            d = gpu_fields[name].astype(np.float64) - f
+            rms[name] = float(np.sqrt((d * d).sum(axis=0).mean()))
     vi = voxel_iters(SHAPE, ITERS) * len(SETTINGS)
-    return {"value": vi / dt, "unit": "voxel-iter/s", "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"one step: the 256x256x100 pair registered with all six settings, {ITERS} iterations "
-                      f"coarse to fine ({vi} voxel-iterations, {dt:.1f} s, FP64)", "seconds": dt}
+    out = {"value": vi / dt, "unit": "voxel-iter/s", "cores": O.max_threads(), "kind": "oracle",
+           "sample": f"one step: the 256x256x100 pair registered with all six settings, {ITERS} iterations "
+                     f"coarse to fine ({vi} voxel-iterations, {dt:.1f} s, FP64)", "seconds": dt}
+    return out, rms
 
 
 # Reduced-precision study: 512x512x160 phantoms (max displacement 20
@@ -676,8 +689,12 @@ def main():
     z, y, x = np.unravel_index(sample, ph.static.shape)
     vt, _ = ph.ground_truth(x.astype(float), y.astype(float), z.astype(float))
     gt = {}
+    want_cpu = not args.no_cpu_baseline and compare
+    gpu_fields = {}
     for name, _, _ in ([] if (args.no_gt or not compare) else SETTINGS):
         B.dir_register(h, S, M, params[name], field_out=outs[0], history=False)
+        if want_cpu:
+            gpu_fields[name] = outs[0].cpu().numpy()
         f = outs[0].view(3, -1)[:, torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
         d = f - vt
         mm = np.sqrt((d[0] * SPACING[0]) ** 2 + (d[1] * SPACING[1]) ** 2 + (d[2] * SPACING[2]) ** 2)
@@ -687,10 +704,15 @@ def main():
     for hh in handles:
         B.dir_destroy(hh)
 
-    cpu = None
-    if not args.no_cpu_baseline and compare:
+    cpu, parity = None, None
+    if want_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(S64, M64)
+        cpu, rms = cpu_baseline(S64, M64, gpu_fields or None)
+        if rms:
+            parity = {"rms_vs_oracle_vox": rms, "bound_vox": RMS_BOUND_VOX,
+                      "note": "whole registrations of this step against the FP64 oracle on the same inputs; "
+                              "the alpha 0.4 settings are ill-conditioned: perturbing the oracle's own inputs "
+                              "by one FP32 rounding moves its result by more than the bound"}
 
     line = {
         "metric": METRIC, "value": value, "unit": "voxel-iter/s", "n_gpus": 1, "steps": args.steps,
@@ -711,6 +733,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "gt_error": gt,
+        "parity": parity,
         "per_kernel_ms_one_step": {k: v[0] for k, v in per_kernel.items() if v[1]},
     }
     print(json.dumps(line))
