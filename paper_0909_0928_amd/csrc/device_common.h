@@ -196,30 +196,40 @@ struct StF32 {
     }
 };
 
+// The 16-bit formats also convert to and from their bit patterns (from_bits,
+// to_bits), which the smoothing kernel uses to move two values per 4-byte
+// access; load and store are those conversions around a 2-byte access.
 struct StF16 {  // IEEE binary16
     static constexpr unsigned kBytes = 2;
+    static __device__ __forceinline__ float from_bits(unsigned u) { return __half2float(__ushort_as_half((unsigned short)u)); }
+    static __device__ __forceinline__ unsigned to_bits(float v) { return __half_as_ushort(__float2half_rn(v)); }
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
     {
-        return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+        return from_bits(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
     }
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)to_bits(v), r, voff, soff, 0);
     }
 };
 
 struct StBF16 {  // bfloat16: the upper half of a binary32
     static constexpr unsigned kBytes = 2;
-    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
-    {
-        return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0) << 16);
-    }
-    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+    static __device__ __forceinline__ float from_bits(unsigned u) { return __uint_as_float((u & 0xffffu) << 16); }
+    static __device__ __forceinline__ unsigned to_bits(float v)
     {
         // round to nearest, ties to even, on the 16 bits dropped (finite v)
         unsigned u = __float_as_uint(v);
         u += 0x7fffu + ((u >> 16) & 1u);
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(u >> 16), r, voff, soff, 0);
+        return u >> 16;
+    }
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+    {
+        return from_bits(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, float v, unsigned voff, unsigned soff)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)to_bits(v), r, voff, soff, 0);
     }
 };
 

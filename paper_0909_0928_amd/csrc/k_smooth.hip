@@ -189,9 +189,141 @@ __global__ __launch_bounds__(256) void k_smooth_yz(YZArgs a, GaussTaps taps, Sum
     }
 }
 
+// The same tile, 128 columns wide, for 16-bit fields of even nx: each lane
+// owns two neighbouring columns, so that every load and store moves both of
+// them in one 4-byte access (a 16-bit access moves half the bytes of an FP32
+// one for the same cost).  Every output is the same sum in the same order as
+// in k_smooth_yz, so the results are identical.  Lanes past the last column
+// pair repeat it and store nothing.
+template <int R, int TZ>
+struct YZTile2 {
+    static constexpr int ROWS = kTileY + 2 * R;
+    static_assert(TZ * ROWS * 2 * kBlockX * 4 <= 65536, "LDS tile above 64 KB");
+};
+
+template <int R, int TZ, class St>
+__global__ __launch_bounds__(256) void k_smooth_yz2(YZArgs a, GaussTaps taps, SumsReduce red)
+{
+    static_assert(St::kBytes == 2, "two 16-bit columns per 4-byte access");
+    constexpr int ROWS = YZTile2<R, TZ>::ROWS;
+    __shared__ float2 zs[TZ][ROWS][kBlockX];
+    const int g = xcd_logical_id(blockIdx.x, gridDim.x);
+    int reg = 0;  // wave-uniform
+    while (reg + 1 < a.count && g >= a.first[reg + 1]) ++reg;
+    const int lb = g - a.first[reg];
+    if (a.stop_at[reg] && *a.stop_at[reg] < a.n) return;
+    const int tid = threadIdx.x + kBlockX * threadIdx.y;
+    if (red.count && lb == 0) {
+        reduce_sums(red.partials[reg], red.nb[reg], red.hist[reg], a.n, red.st[reg], red.eps[reg], red.inv_n[reg],
+                    tid);
+        return;
+    }
+    const YZGeo &q = a.geo[reg];
+    const int nx = q.nx, ny = q.ny, nz = q.nz, gx = q.gx, gy = q.gy, gz = q.gz;
+    const int b = lb - (red.count ? 1 : 0);
+    const int tz = b % gz, r1 = b / gz, ty = r1 % gy, r2 = r1 / gy, tx = r2 % gx, c = r2 / gx;
+    const void *const in = a.in[reg];
+    void *const out = a.out[reg];
+    const int lane = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int x = min(tx * 2 * kBlockX + 2 * lane, nx - 2);  // first column of the lane's pair
+    const int y_base = ty * kTileY, z0 = tz * TZ;
+    constexpr unsigned ES = 2;
+    const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    const unsigned rowb = ES * (unsigned)nx, planeb = rowb * (unsigned)ny;
+    const __amdgpu_buffer_rsrc_t src = make_rsrc(static_cast<const char *>(in) + (size_t)c * ES * N, ES * N);
+    const __amdgpu_buffer_rsrc_t dst = make_rsrc(static_cast<char *>(out) + (size_t)c * ES * N, ES * N);
+    const unsigned xb = ES * (unsigned)x;  // 4-byte aligned: x and nx are even
+    float w[2 * R + 1];
+#pragma unroll
+    for (int j = 0; j <= 2 * R; ++j) w[j] = taps.w[j];
+    unsigned zoff[TZ + 2 * R];
+#pragma unroll
+    for (int k = 0; k < TZ + 2 * R; ++k) zoff[k] = planeb * (unsigned)clampi(z0 - R + k, nz);
+
+    // phase 1: z pass for rows y_base - R .. y_base + kTileY + R - 1
+    for (int row = wave; row < ROWS; row += kBlockY) {
+        const unsigned ra = rowb * (unsigned)clampi(y_base - R + row, ny);
+        unsigned pk[TZ + 2 * R];
+#pragma unroll
+        for (int k = 0; k < TZ + 2 * R; ++k) pk[k] = __builtin_amdgcn_raw_buffer_load_b32(src, xb, ra + zoff[k], 0);
+#pragma unroll
+        for (int k = 0; k < TZ; ++k) {
+            float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= 2 * R; ++j) {
+                s0 = fmaf(w[j], St::from_bits(pk[k + j]), s0);
+                s1 = fmaf(w[j], St::from_bits(pk[k + j] >> 16), s1);
+            }
+            zs[k][row][lane] = make_float2(s0, s1);
+        }
+    }
+    __syncthreads();
+
+    // phase 2: y pass, rows y_base + 4 * wave .. + 3, both columns
+    const int xo = tx * 2 * kBlockX + 2 * lane;
+    const int y0 = y_base + wave * kRowsPerThread;
+    if (xo >= nx || y0 >= ny) return;
+    const unsigned ob = ES * (unsigned)xo;
+    for (int k = 0; k < TZ; ++k) {
+        if (z0 + k >= nz) break;
+        float2 v[kRowsPerThread + 2 * R];
+#pragma unroll
+        for (int j = 0; j < kRowsPerThread + 2 * R; ++j) v[j] = zs[k][wave * kRowsPerThread + j][lane];
+        const unsigned zb = planeb * (unsigned)(z0 + k);
+#pragma unroll
+        for (int qq = 0; qq < kRowsPerThread; ++qq) {
+            float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+            for (int j = 0; j <= 2 * R; ++j) {
+                s0 = fmaf(w[j], v[qq + j].x, s0);
+                s1 = fmaf(w[j], v[qq + j].y, s1);
+            }
+            if (y0 + qq < ny)
+                __builtin_amdgcn_raw_buffer_store_b32(St::to_bits(s0) | (St::to_bits(s1) << 16), dst, ob,
+                                                      zb + rowb * (unsigned)(y0 + qq), 0);
+        }
+    }
+}
+
+// Two columns per lane: 16-bit storage, even nx, and a depth whose tile fits.
+template <int R, int TZ, class St>
+constexpr bool yz_two_columns()
+{
+    return St::kBytes == 2 && TZ * (kTileY + 2 * R) * 2 * kBlockX * 4 <= 65536;
+}
+
+// Workgroups below which a launch keeps one column per lane: small launches
+// are bound by latency, and halving their workgroups measured slower
+// (64x64x25 levels of a six-registration batch).
+constexpr int64_t kYZTwoColumnMinBlocks = 1024;
+
 template <int R, int TZ, class St>
 void launch_yz_tz(Ctx &c, const Ev &ev, YZArgs a, int ncomp, const GaussTaps &taps, const SumsReduce &red)
 {
+    if constexpr (yz_two_columns<R, TZ, St>()) {
+        bool even = true;
+        int64_t blocks2 = 0;
+        for (int r = 0; r < a.count; ++r) {
+            const YZGeo &q = a.geo[r];
+            even = even && q.nx % 2 == 0;
+            blocks2 += (int64_t)ceil_div(q.nx, 2 * kBlockX) * ceil_div(q.ny, kTileY) * ceil_div(q.nz, TZ) * ncomp;
+        }
+        if (even && blocks2 >= kYZTwoColumnMinBlocks) {
+            int64_t total = 0;
+            for (int r = 0; r < a.count; ++r) {
+                YZGeo &q = a.geo[r];
+                q.gx = ceil_div(q.nx, 2 * kBlockX);
+                q.gy = ceil_div(q.ny, kTileY);
+                q.gz = ceil_div(q.nz, TZ);
+                a.first[r] = (int)total;
+                total += (int64_t)q.gx * q.gy * q.gz * ncomp + (red.count ? 1 : 0);
+            }
+            a.first[a.count] = (int)total;
+            go(c, ev, (k_smooth_yz2<R, TZ, St>), dim3((unsigned)total), dim3(kBlockX, kBlockY), a, taps, red);
+            return;
+        }
+    }
+
     int64_t total = 0;
     for (int r = 0; r < a.count; ++r) {
         YZGeo &q = a.geo[r];
