@@ -342,10 +342,17 @@ void launch_yz_tz(Ctx &c, const Ev &ev, YZArgs a, int ncomp, const GaussTaps &ta
 constexpr int64_t kYZTargetBlocks = 1024;
 
 // z-chunk depth for a registration of size d: the deepest whose tiles still
-// number kYZTargetBlocks (or half that for 4).
-template <int R>
+// number kYZTargetBlocks (or half that for 4).  A 16-bit field of even nx
+// takes depth 4 when its two-column tiles are enough for the two-column
+// kernel: the autotuner preferred that to depth 8 at 256x256x100.
+template <int R, class St>
 int yz_depth(Dims d, int ncomp)
 {
+    if constexpr (yz_two_columns<R, 4, St>()) {
+        const int64_t blocks2 =
+            (int64_t)ceil_div(d.nx, 2 * kBlockX) * ceil_div(d.ny, kTileY) * ceil_div(d.nz, 4) * ncomp;
+        if (d.nx % 2 == 0 && blocks2 >= kYZTwoColumnMinBlocks) return 4;
+    }
     const int64_t tiles = (int64_t)ceil_div(d.nx, kBlockX) * ceil_div(d.ny, kTileY) * ncomp;
     if (max_tz<R>() == 8 && tiles * ceil_div(d.nz, 8) >= kYZTargetBlocks) return 8;
     if (tiles * ceil_div(d.nz, 4) >= kYZTargetBlocks / 2) return 4;
@@ -425,7 +432,7 @@ hipError_t launch_yz_all(Ctx &c, int count, const void *const *in, int ncomp, co
     int tz[kMaxBatch];
     for (int r = 0; r < count; ++r) {
         const int t = yz_tuned(YZKey{d[r].nx, d[r].ny, d[r].nz, ncomp, count, (int)St::kBytes, R});
-        tz[r] = t ? t : yz_depth<R>(d[r], ncomp);
+        tz[r] = t ? t : yz_depth<R, St>(d[r], ncomp);
     }
     bool done[kMaxBatch] = {};
     for (int r = 0; r < count; ++r) {
