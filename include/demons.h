@@ -234,8 +234,10 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
                         int32_t radius, float *d_field_out, double *sums);
 
 /* Output field of the inverse-consistent variant from its half field h:
- * w(z) = 2 h(p) with p = z - h(p), p found by K fixed-point updates from
- * p = z (K < 0 selects 10).  d_half, d_out: 3 planes, must not overlap. */
+ * w(z) = 2 h(p) with p = z - h(p), p found by K fixed-point updates
+ * p <- z - h(p) that start from the first-order inverse p = z - h(z)
+ * (K < 0 selects 10; K = 0 gives w(z) = 2 h(z - h(z))).  d_half, d_out:
+ * 3 planes, must not overlap. */
 int32_t dir_compose(dir_handle *h, const float *d_half, int32_t nx, int32_t ny, int32_t nz, int32_t K,
                     float *d_out);
 

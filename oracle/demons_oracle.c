@@ -439,8 +439,9 @@ int orc_iterate(int variant, double alpha, double sigma, int radius, const doubl
 /* Output field of the inverse-consistent variant.  The iteration returns the
  * symmetric half field h with M(p - h(p)) = S(p + h(p)) at a match.  Writing
  * z = p + h(p) gives M(z - 2 h(p)) = S(z), so the field in the convention of
- * the other variants is w(z) = 2 h(p) with p = z - h(p), solved by K
- * fixed-point updates starting at p = z (reading of Sec 2.2, text after
+ * the other variants is w(z) = 2 h(p) with p = z - h(p).  p is found by
+ * fixed-point iteration: it starts at the first-order inverse p = z - h(z)
+ * and takes K further updates p <- z - h(p) (reading of Sec 2.2, text after
  * Eq 6). */
 void orc_compose(const double *h, int64_t nx, int64_t ny, int64_t nz, int K, double *w)
 {
@@ -449,7 +450,9 @@ void orc_compose(const double *h, int64_t nx, int64_t ny, int64_t nz, int K, dou
     for (int64_t z = 0; z < nz; ++z)
         for (int64_t y = 0; y < ny; ++y)
             for (int64_t x = 0; x < nx; ++x) {
-                double px = (double)x, py = (double)y, pz = (double)z;
+                int64_t i = at(x, y, z, nx, ny);
+                /* start: p = z - h(z), h read at the grid point itself */
+                double px = (double)x - h[i], py = (double)y - h[N + i], pz = (double)z - h[2 * N + i];
                 for (int k = 0; k < K; ++k) {
                     double hx = orc_trilerp(h, nx, ny, nz, px, py, pz);
                     double hy = orc_trilerp(h + N, nx, ny, nz, px, py, pz);
@@ -458,7 +461,6 @@ void orc_compose(const double *h, int64_t nx, int64_t ny, int64_t nz, int K, dou
                     py = (double)y - hy;
                     pz = (double)z - hz;
                 }
-                int64_t i = at(x, y, z, nx, ny);
                 w[i] = 2.0 * orc_trilerp(h, nx, ny, nz, px, py, pz);
                 w[N + i] = 2.0 * orc_trilerp(h + N, nx, ny, nz, px, py, pz);
                 w[2 * N + i] = 2.0 * orc_trilerp(h + 2 * N, nx, ny, nz, px, py, pz);

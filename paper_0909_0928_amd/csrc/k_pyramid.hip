@@ -214,11 +214,12 @@ __global__ __launch_bounds__(256) void k_compose(const void *__restrict__ h, int
     const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
     const __amdgpu_buffer_rsrc_t H = make_rsrc(h, 3u * E * N);
     // p = (x, y, z) - (hx, hy, hz): the position is kept as the displacement.
-    // K updates of p, then h at the last p: K + 1 samples.  A sample equal to
-    // the one before is a fixed point of the FP32 map, which every later
-    // sample repeats, so the loop ends there with the same result.
+    // The first sample, at p = z, gives the starting point p = z - h(z); K
+    // updates of p follow, then h at the last p: K + 2 samples.  A sample
+    // equal to the one before is a fixed point of the FP32 map, which every
+    // later sample repeats, so the loop ends there with the same result.
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-    for (int k = 0; k <= K; ++k) {
+    for (int k = 0; k <= K + 1; ++k) {
         float sx, sy, sz;
         bsample3<St>(H, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz), E * N, sx, sy, sz);
         const bool fixed = sx == hx && sy == hy && sz == hz;

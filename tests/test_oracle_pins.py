@@ -371,6 +371,23 @@ def test_inverse_consistent_antisymmetry_bitwise():
     assert np.array_equal(hist1, hist2, equal_nan=True)
 
 
+def test_compose_starts_at_first_order_inverse():
+    """K = 0 gives w(z) = 2 h(z - h(z)); K = 1 one update more (closed forms on
+    a linear half field, whose trilinear samples are exact in the interior)."""
+    shape3 = (12, 13, 14)
+    gz, gy, gx = _grid(shape3)
+    A = np.array([[0.05, 0.02, 0.0], [0.0, -0.04, 0.03], [0.01, 0.0, 0.06]])
+    b = np.array([0.2, -0.1, 0.3])
+    X = np.stack([gx, gy, gz])
+    lin = lambda p: np.einsum("ij,j...->i...", A, p) + b[:, None, None, None]
+    h = lin(X)
+    p0 = X - lin(X)
+    p1 = X - lin(p0)
+    inner = (slice(None),) + (slice(2, -2),) * 3
+    np.testing.assert_allclose(O.compose(h, K=0)[inner], 2 * lin(p0)[inner], atol=1e-12)
+    np.testing.assert_allclose(O.compose(h, K=1)[inner], 2 * lin(p1)[inner], atol=1e-12)
+
+
 def test_compose_constant_and_linear_half_fields():
     shape3 = (12, 13, 14)
     h = np.zeros((3,) + shape3)
@@ -399,23 +416,92 @@ def test_subvoxel_translation_recovery():
         assert abs(field[c][inner].mean() - t[c]) < 0.02
 
 
-def test_stopping_rule_matches_history():
+def decoupled_ramp_history(nx, ny, nz, t, alpha, iters):
+    """Closed-form history of the passive force (Eq 1 with alpha) on S = x,
+    M = x + t (0 < t <= 1), with a smoothing so narrow that it is the identity
+    (sigma 0.05, R 1: the side weights are about 1e-87).  Every voxel then
+    evolves on its own, and only its x position matters:
+      - interior x: grad S = 1, D = t - v, so e = t - v obeys
+        e' = e - e / (alpha^2 e^2 + 1);
+      - x = 0: grad S = 1/2 (clamped neighbour) and the sample x - v < 0
+        clamps onto M(0) = t, so D = t for ever and v grows by
+        (t / 2) / (alpha^2 t^2 + 1/4) per iteration;
+      - x = nx - 1: grad S = 1/2, D = t - v = e, so
+        e' = e - (e / 2) / (alpha^2 e^2 + 1/4).
+    Returns the rows (sum|dr|, sum|v| before the update, mean D^2, l) of
+    Sec 2.4's relative norm over the whole volume."""
+    a2 = alpha * alpha
+    e_int, e_end, v0 = t, t, 0.0
+    rows = []
+    for _ in range(iters):
+        dr0 = 0.5 * t / (a2 * t * t + 0.25)
+        dri = e_int / (a2 * e_int * e_int + 1.0)
+        dre = 0.5 * e_end / (a2 * e_end * e_end + 0.25)
+        s1 = ny * nz * (abs(dr0) + (nx - 2) * abs(dri) + abs(dre))
+        s2 = ny * nz * (abs(v0) + (nx - 2) * abs(t - e_int) + abs(t - e_end))
+        mse = (t * t + (nx - 2) * e_int * e_int + e_end * e_end) / nx
+        rows.append((s1, s2, mse, s1 / s2 if s2 > 0 else math.nan))
+        v0, e_int, e_end = v0 + dr0, e_int - dri, e_end - dre
+    return np.array(rows)
+
+
+def decoupled_ramp(nx, ny, nz, t):
+    gx = np.broadcast_to(np.arange(nx, dtype=float), (nz, ny, nx)).copy()
+    return gx, gx + t
+
+
+def stop_eps(l, n_stop):
+    """An eps for which the rule l(n-10) - l(n) <= eps first holds at
+    iteration n_stop (midway between that drop and the one before, which the
+    closed form shows to decrease monotonically)."""
+    d = {n: l[n - 10] - l[n] for n in range(11, len(l))}
+    assert all(d[n] > d[n + 1] for n in range(11, len(l) - 1))
+    return 0.5 * (d[n_stop] + d[n_stop - 1])
+
+
+@pytest.mark.parametrize("variant,alpha", [(O.PASSIVE, 1.0), (O.PASSIVE, 0.4), (O.EVOLVED, 1.0)])
+def test_history_columns_closed_form(variant, alpha):
+    """Every history column (sum|dr|, sum|v|, mean D^2, l) against the closed
+    form of the decoupled ramp; Eq 2 equals Eq 1 there (|grad M0| = |grad S|)."""
+    nx, ny, nz, t, iters = 12, 3, 2, 0.8, 40
+    S, M = decoupled_ramp(nx, ny, nz, t)
+    _, hist = O.iterate(variant, S, M, np.zeros((3,) + S.shape), iters, sigma=0.05, radius=1, alpha=alpha)
+    expect = decoupled_ramp_history(nx, ny, nz, t, alpha, iters)
+    assert np.isnan(hist[0, 3]) and np.isnan(expect[0, 3])
+    np.testing.assert_allclose(hist[:, :3], expect[:, :3], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(hist[1:, 3], expect[1:, 3], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("alpha,n_stop", [(1.0, 15), (1.0, 27), (0.4, 20)])
+def test_stopping_rule_closed_form(alpha, n_stop):
+    """Sec 2.4 as read: the level stops after the first iteration n >= 10 with
+    l(n-10) - l(n) <= eps (undefined l skipped), so it runs n + 1 iterations.
+    The stop is predicted from the closed-form l(n), not from the oracle's own
+    history."""
+    nx, ny, nz, t, cap = 12, 3, 2, 0.8, 40
+    S, M = decoupled_ramp(nx, ny, nz, t)
+    l = decoupled_ramp_history(nx, ny, nz, t, alpha, cap)[:, 3]
+    eps = stop_eps(l, n_stop)
+    field, hist, runs, rc = O.register(S, M, O.PASSIVE, [cap], sigma=0.05, radius=1, alpha=alpha, eps=eps)
+    assert runs == [n_stop + 1]
+    np.testing.assert_allclose(hist[1:, 3], l[1:n_stop + 1], rtol=1e-12)
+    # eps = 0 runs the fixed count; the rule restarts at every level
+    _, _, runs0, _ = O.register(S, M, O.PASSIVE, [cap], sigma=0.05, radius=1, alpha=alpha, eps=0.0)
+    assert runs0 == [cap]
+
+
+def test_stopping_rule_restarts_per_level():
+    """Two levels, each with its own history: the coarse level (its own closed
+    form on the restricted ramp is not needed) runs its count when the rule
+    cannot fire within it, and the fine level's rule only looks at fine-level
+    l values."""
     t = (0.6, -0.4, 0.5)
     S, M = P.smooth_translation_pair((20, 20, 20), t, seed=4)
     eps = 2e-3
-    field, hist, runs, rc = O.register(S, M, O.PASSIVE, [80], sigma=1.0, radius=3, eps=eps)
-    l = hist[:, 3]
-    stop = None
-    for n in range(10, 80):
-        if not np.isnan(l[n]) and not np.isnan(l[n - 10]) and l[n - 10] - l[n] <= eps:
-            stop = n + 1
-            break
-    assert stop is not None and 10 < stop < 80
-    assert runs == [stop]
-    _, hist_full, runs_full, _ = O.register(S, M, O.PASSIVE, [80], sigma=1.0, radius=3, eps=0.0)
-    assert runs_full == [80]
-    np.testing.assert_array_equal(hist_full[:stop], hist)
-    assert np.isnan(hist_full[0, 3])  # sum|v| = 0 on the first coarse iteration
+    _, hist, runs, _ = O.register(S, M, O.PASSIVE, [9, 80], sigma=1.0, radius=3, eps=eps)
+    assert runs[0] == 9                      # fewer than 11 iterations: the rule cannot fire
+    assert 10 < runs[1] < 80
+    assert np.isnan(hist[0, 3]) and not np.isnan(hist[9, 3])  # the fine level starts from the prolonged field
 
 
 def test_nan_input_reports_numeric_error():
