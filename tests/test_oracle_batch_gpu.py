@@ -1,0 +1,148 @@
+"""Registrations run through a lockstep batch, a batching request pool and
+concurrent asynchronous handles, each field compared with the FP64 oracle's
+registration of the same pair, voxel by voxel.
+
+The end-to-end bound is the RMS over voxels of the field difference:
+0.01 voxel, or three times the oracle's own movement when its inputs are
+perturbed by one FP32 rounding (relative +-6e-8), for the settings where the
+iteration amplifies rounding (the alpha = 0.4 forces: up to 1.25 voxel per
+step).  16-bit storage is compared with the oracle run on the images rounded
+to the format, inside the body, as for single registrations."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_0909_0928_amd import phantom as P
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+RMS_TOL_VOX = 0.01
+ITERS = [6, 4]
+SIGMA, RADIUS = 1.0, 3
+# (variant, alpha, shape xyz): every force kind and pre-warp kind, ragged
+# sizes that take three force tile widths
+CASES = [("passive", 1.0, (40, 36, 20)), ("active", 1.0, (33, 29, 17)), ("double", 1.0, (67, 45, 19)),
+         ("passive", 0.4, (48, 40, 12)), ("inverse_consistent", 1.0, (40, 36, 20)), ("double", 0.4, (130, 33, 21)),
+         ("evolved", 1.0, (36, 28, 14))]
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_0909_0928_amd import binding
+    return binding
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).cuda()
+
+
+def rms_vox(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum(axis=0).mean()))
+
+
+@pytest.fixture(scope="module")
+def cases():
+    """Per case: FP32 images (as float64), the oracle field, and the oracle's
+    rounding envelope."""
+    out = []
+    rng = np.random.default_rng(77)
+    for k, (variant, alpha, shape) in enumerate(CASES):
+        ph = P.make_phantom(shape, seed=950 + k, max_u=2.5)
+        S = ph.static.astype(np.float32).astype(np.float64)
+        M = ph.moving.astype(np.float32).astype(np.float64)
+        ref, _, runs, _ = O.register(S, M, O.VARIANTS[variant], ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha)
+        Sp = S * (1 + rng.uniform(-6e-8, 6e-8, S.shape))
+        Mp = M * (1 + rng.uniform(-6e-8, 6e-8, M.shape))
+        pert, _, _, _ = O.register(Sp, Mp, O.VARIANTS[variant], ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha)
+        out.append({"variant": variant, "alpha": alpha, "S": S, "M": M, "ref": ref, "env": rms_vox(pert, ref),
+                    "runs": runs})
+    return out
+
+
+def _params(B, c, storage="f32"):
+    return B.make_params(c["variant"], ITERS, sigma=SIGMA, radius=RADIUS, alpha=c["alpha"], storage=storage)
+
+
+def _check(c, field, stats, how):
+    got = field.double().cpu().numpy()
+    d = rms_vox(got, c["ref"])
+    worst = float(np.sqrt(((got - c["ref"]) ** 2).sum(axis=0)).max())
+    bound = max(RMS_TOL_VOX, 3.0 * c["env"])
+    print(f"{how} {c['variant']} alpha {c['alpha']} {c['S'].shape}: RMS vs oracle {d:.2e} vox "
+          f"(bound {bound:.2e}, oracle envelope {c['env']:.2e}), worst voxel {worst:.2e}", flush=True)
+    assert np.isfinite(got).all()
+    assert d <= bound
+    assert stats["iters_run"] == c["runs"]
+
+
+def test_batch_against_oracle(B, cases):
+    """One mixed lockstep batch of seven registrations of different sizes."""
+    with B.dir_create(0) as h:
+        res = B.dir_register_batch(h, [_dev(c["S"]) for c in cases], [_dev(c["M"]) for c in cases],
+                                   [_params(B, c) for c in cases])
+        for c, (f, st) in zip(cases, res):
+            _check(c, f, st, "batch")
+
+
+def test_batching_pool_against_oracle(B, cases):
+    """A two-slot pool admitting up to four compatible requests per slot as a
+    lockstep batch, every request submitted before any is collected."""
+    with B.Pool(slots=2, max_bytes=0, max_batch=4) as pool:
+        tickets = [pool.submit(_dev(c["S"]), _dev(c["M"]), _params(B, c)) for c in cases]
+        for c, t in zip(cases, tickets):
+            f, st = pool.wait(t)
+            _check(c, f, st, "pool")
+        assert pool.stats()["peak_running"] >= 2
+
+
+def test_concurrent_async_against_oracle(B, cases):
+    """Registrations enqueued at once on separate handles and streams."""
+    streams = [torch.cuda.Stream() for _ in cases]
+    handles = [B.dir_create(0, stream=s) for s in streams]
+    try:
+        outs = [B.dir_register_async(hh, _dev(c["S"]), _dev(c["M"]), _params(B, c)) for hh, c in zip(handles, cases)]
+        for hh, c, o in zip(handles, cases, outs):
+            f, st = B.dir_wait(hh)
+            _check(c, f, st, "async")
+    finally:
+        for hh in handles:
+            B.dir_destroy(hh)
+
+
+def _round16(a, fmt):
+    a = np.asarray(a, dtype=np.float64)
+    if fmt == "f16":
+        return a.astype(np.float16).astype(np.float64)
+    u = np.ascontiguousarray(a.astype(np.float32)).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("fmt,body_tol", [("f16", 0.02), ("bf16", 0.1)])
+def test_batching_pool_16bit_against_oracle(B, fmt, body_tol):
+    """16-bit storage through a batching pool: each field against the oracle
+    on the images rounded to the format, inside the body (the bounds of the
+    single-registration storage test)."""
+    reqs = [("passive", 1.0, (48, 40, 20), 960), ("inverse_consistent", 1.0, (40, 36, 20), 961),
+            ("double", 0.4, (33, 29, 17), 962)]
+    with B.Pool(slots=1, max_bytes=0, max_batch=4) as pool:
+        work = []
+        for variant, alpha, shape, seed in reqs:
+            ph = P.make_phantom(shape, seed=seed, max_u=2.5)
+            p = B.make_params(variant, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha, storage=fmt)
+            work.append((variant, alpha, ph, pool.submit(_dev(ph.static), _dev(ph.moving), p)))
+        for variant, alpha, ph, t in work:
+            f, st = pool.wait(t)
+            got = f.double().cpu().numpy()
+            S64 = ph.static.astype(np.float32).astype(np.float64)
+            M64 = ph.moving.astype(np.float32).astype(np.float64)
+            ref, _, _, _ = O.register(_round16(S64, fmt), _round16(M64, fmt), O.VARIANTS[variant], ITERS,
+                                      sigma=SIGMA, radius=RADIUS, alpha=alpha)
+            d2 = ((got - ref) ** 2).sum(axis=0)
+            body = float(np.sqrt(d2[ph.body].mean()))
+            print(f"pool {fmt} {variant} alpha {alpha}: RMS vs oracle on rounded images, body {body:.2e} vox, "
+                  f"all {float(np.sqrt(d2.mean())):.2e}", flush=True)
+            assert np.isfinite(got).all()
+            assert body <= body_tol

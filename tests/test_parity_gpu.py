@@ -57,6 +57,17 @@ def rel(a, b):
     return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
 
 
+def assert_close(a, b, tol=REL_TOL, elem=10 * REL_TOL):
+    """Normwise relative error below tol, and every element within elem of
+    max|b|: a wrong border plane or tile edge can hide under the norm of a
+    large volume, not under the per-element bound."""
+    r = rel(a, b)
+    scale = float(np.abs(b).max()) if b.size else 0.0
+    m = float(np.abs(a - b).max()) / (scale if scale > 0 else 1.0) if b.size else 0.0
+    assert r < tol and m <= elem, f"normwise {r:.2e} (bound {tol:.0e}), worst element {m:.2e} of max|ref| " \
+                                  f"(bound {elem:.0e})"
+
+
 def rms_vox(a, b):
     return float(np.sqrt(((a - b) ** 2).sum(axis=0).mean()))
 
@@ -79,14 +90,14 @@ def _fld(shape3, seed, amp=2.5):
 def test_warp(B, h, shape3):
     I, v = _img(shape3, 1), _fld(shape3, 2, amp=4.0)
     got = host(B.dir_warp(h, dev(I), dev(v)))
-    assert rel(got, O.warp(I, v)) < REL_TOL
+    assert_close(got, O.warp(I, v))
 
 
 @pytest.mark.parametrize("shape3", SHAPES)
 def test_gradient(B, h, shape3):
     I = _img(shape3, 3)
     got = host(B.dir_gradient(h, dev(I)))
-    assert rel(got, O.gradient(I)) < REL_TOL
+    assert_close(got, O.gradient(I))
 
 
 @pytest.mark.parametrize("shape3", SHAPES)
@@ -95,16 +106,16 @@ def test_smooth(B, h, shape3, sigma, radius):
     u = np.stack([_img(shape3, 4 + c) for c in range(3)])
     got = host(B.dir_smooth(h, dev(u), sigma, radius))
     R = radius if radius > 0 else O.default_radius(sigma)
-    assert rel(got, O.smooth(u, sigma, R)) < REL_TOL
+    assert_close(got, O.smooth(u, sigma, R))
     one = host(B.dir_smooth(h, dev(u[0]), sigma, radius))
-    assert rel(one, O.smooth(u[0], sigma, R)) < REL_TOL
+    assert_close(one, O.smooth(u[0], sigma, R))
 
 
 @pytest.mark.parametrize("shape3", SHAPES)
 def test_restrict(B, h, shape3):
     I = _img(shape3, 7)
     got = host(B.dir_restrict(h, dev(I)))
-    assert rel(got, O.restrict(I)) < REL_TOL
+    assert_close(got, O.restrict(I))
 
 
 @pytest.mark.parametrize("coarse,fine", [((6, 7, 9), (11, 13, 17)), ((3, 17, 33), (5, 33, 65)), ((1, 4, 35), (1, 7, 70)),
@@ -112,7 +123,7 @@ def test_restrict(B, h, shape3):
 def test_prolong(B, h, coarse, fine):
     vc = _fld(coarse, 8)
     got = host(B.dir_prolong(h, dev(vc), fine))
-    assert rel(got, O.prolong(vc, fine)) < REL_TOL
+    assert_close(got, O.prolong(vc, fine))
 
 
 @pytest.mark.parametrize("shape3", [(11, 13, 17), (9, 33, 65), (3, 4, 530)])
@@ -148,7 +159,7 @@ def test_force(B, h, shape3, variant, alpha):
     S, M, v = _pair(shape3, 11)
     u_gpu, sums_gpu = B.dir_force(h, variant, alpha, dev(S), dev(M), dev(v))
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=alpha)
-    assert rel(host(u_gpu) - v, u_ref - v) < REL_TOL
+    assert_close(host(u_gpu) - v, u_ref - v)
     for k in range(3):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
@@ -162,13 +173,13 @@ def test_degenerate_volumes(B, h, shape3, variant):
     v = _fld(shape3, 82)
     u_gpu, sums_gpu = B.dir_force(h, variant, 1.0, dev(S), dev(M), dev(v))
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v)
-    assert rel(host(u_gpu) - v, u_ref - v) < REL_TOL
+    assert_close(host(u_gpu) - v, u_ref - v)
     for k in range(3):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
     out, _ = B.dir_step(h, variant, 1.0, dev(S), dev(M), dev(v), 1.5, 5)
     # the update is often zero here (no gradient along a one-voxel axis), so
     # the error is taken relative to the field itself
-    assert rel(host(out), O.smooth(u_ref, 1.5, 5)) < REL_TOL
+    assert_close(host(out), O.smooth(u_ref, 1.5, 5))
     mse, _ = B.dir_similarity(h, dev(S), dev(M), dev(v))
     d = O.warp(M, v) - S
     assert abs(mse - float((d * d).mean())) <= 1e-9 * float((d * d).mean())
@@ -187,7 +198,7 @@ def test_step(B, h, shape3, variant, sigma, radius):
     out, sums_gpu = B.dir_step(h, variant, alpha, dev(S), dev(M), dev(v), sigma, radius)
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=alpha)
     ref = O.smooth(u_ref, sigma, radius)
-    assert rel(host(out) - v, ref - v) < REL_TOL
+    assert_close(host(out) - v, ref - v)
     for k in range(3):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
@@ -200,7 +211,7 @@ def test_step_widest_radius(B, h, shape3, variant):
     out, sums_gpu = B.dir_step(h, variant, 1.0, dev(S), dev(M), dev(v), 4.0, 16)
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=1.0)
     ref = O.smooth(u_ref, 4.0, 16)
-    assert rel(host(out) - v, ref - v) < REL_TOL
+    assert_close(host(out) - v, ref - v)
     for k in range(3):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
@@ -228,7 +239,7 @@ def test_register_equals_iterated_step(B, h, variant, shape3):
 def test_compose(B, h, shape3, K):
     hf = _fld(shape3, 12, amp=0.8)
     got = host(B.dir_compose(h, dev(hf), K))
-    assert rel(got, O.compose(hf, K)) < REL_TOL
+    assert_close(got, O.compose(hf, K))
 
 
 # --------------------------------------------------------------------------
@@ -246,9 +257,9 @@ def full_pair():
 def test_full_size_warp_smooth(B, h, full_pair):
     S, M, v = full_pair
     _say("full-size warp 256x256x100")
-    assert rel(host(B.dir_warp(h, dev(M), dev(v))), O.warp(M, v)) < REL_TOL
+    assert_close(host(B.dir_warp(h, dev(M), dev(v))), O.warp(M, v))
     _say("full-size smooth 256x256x100 sigma 1.5 R 5")
-    assert rel(host(B.dir_smooth(h, dev(v), 1.5, 5)), O.smooth(v, 1.5, 5)) < REL_TOL
+    assert_close(host(B.dir_smooth(h, dev(v), 1.5, 5)), O.smooth(v, 1.5, 5))
 
 
 @pytest.mark.slow
@@ -259,7 +270,7 @@ def test_full_size_step(B, h, full_pair, variant):
     out, sums_gpu = B.dir_step(h, variant, 1.0, dev(S), dev(M), dev(v), 1.5, 5)
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v)
     ref = O.smooth(u_ref, 1.5, 5)
-    assert rel(host(out) - v, ref - v) < REL_TOL
+    assert_close(host(out) - v, ref - v)
     for k in range(3):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k])
 
@@ -271,7 +282,7 @@ def test_full_size_force(B, h, full_pair, variant):
     _say(f"full-size force {variant} 256x256x100")
     u_gpu, sums_gpu = B.dir_force(h, variant, 1.0, dev(S), dev(M), dev(v))
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v)
-    assert rel(host(u_gpu) - v, u_ref - v) < REL_TOL
+    assert_close(host(u_gpu) - v, u_ref - v)
     for k in range(3):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k])
 
@@ -450,3 +461,21 @@ def test_nan_input_reports_numeric_error(B, h):
     with pytest.raises(B.DemonsError) as ei:
         B.dir_register(h, dev(S), dev(M), params)
     assert ei.value.code == B.DIR_ENUMERIC
+
+
+@pytest.mark.parametrize("alpha,n_stop", [(1.0, 15), (0.4, 20)])
+def test_stopping_rule_closed_form(B, h, alpha, n_stop):
+    """The stopping rule and every history column on the decoupled ramp, whose
+    relative norm l(n) has a closed form (a smoothing so narrow that its FP32
+    taps are exactly 1 and 0): the level stops after iteration n_stop."""
+    from closed_forms import decoupled_ramp, decoupled_ramp_history, stop_eps
+    nx, ny, nz, t, cap = 12, 3, 2, 0.75, 40
+    S, M = decoupled_ramp(nx, ny, nz, t)
+    expect = decoupled_ramp_history(nx, ny, nz, t, alpha, cap)
+    eps = stop_eps(expect[:, 3], n_stop)
+    params = B.make_params("passive", [cap], sigma=0.05, radius=1, alpha=alpha, eps=eps)
+    _, stats = B.dir_register(h, dev(S), dev(M), params)
+    assert stats["iters_run"] == [n_stop + 1]
+    hg = np.array(stats["history"])
+    np.testing.assert_allclose(hg[:, :3], expect[:n_stop + 1, :3], rtol=1e-5, atol=0)
+    np.testing.assert_allclose(hg[1:, 3], expect[1:n_stop + 1, 3], rtol=1e-5)

@@ -65,6 +65,12 @@ def rel(a, b):
     return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
 
 
+def worst(a, b):
+    """Largest element error relative to max|b| (the per-element bound beside
+    the normwise one)."""
+    return float(np.abs(a - b).max()) / float(np.abs(b).max())
+
+
 def test_round_to_matches_definition():
     # bfloat16 keeps the upper 16 bits of binary32, ties to even
     x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, -1000.5])
@@ -85,7 +91,10 @@ def test_step_stored(B, h, fmt, shape3, variant):
     out, sums = B.dir_step_stored(h, fmt, variant, alpha, dev(S), dev(M), dev(v), 1.5, 5)
     u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=alpha)
     ref = O.smooth(u_ref, 1.5, 5)
-    assert rel(host(out), ref) <= 2.5 * UNIT_ROUNDOFF[fmt]
+    got = host(out)
+    assert rel(got, ref) <= 2.5 * UNIT_ROUNDOFF[fmt]
+    # per element: the two stored roundings of at most max|ref| each
+    assert worst(got, ref) <= 4 * UNIT_ROUNDOFF[fmt]
     # Passive and evolved form D from the stored images inside the force
     # kernel: their sums see exactly the oracle's inputs.  The other variants
     # read D back from the pre-warp, stored in the format: D's
@@ -149,3 +158,51 @@ def test_end_to_end_storage(B, h, small_pair, variant):
         # oracle on the same rounded images by the format's rounding, not more
         # (measured: f16 <= 0.009, bf16 <= 0.05 voxel RMS)
         assert rms(f, ref_q, body) <= (0.02 if fmt == "f16" else 0.1)
+
+
+# The y/z smoothing of 16-bit fields with even nx runs two columns per lane
+# (one 4-byte access per column pair) when a launch has at least 1,024
+# workgroups of 128 columns x 16 rows x 4 planes per component.
+# 256 x 128 x 96 gives 2 * 8 * 24 * 3 = 1152 such workgroups.
+TWO_COLUMN_SHAPE = (96, 128, 256)   # nz, ny, nx
+
+
+@on_gpu
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("variant", ["passive", "inverse_consistent"])
+def test_step_stored_two_column_smoothing(B, h, fmt, variant):
+    """The two-column 16-bit smoothing against the oracle (force + smoothing on
+    the same rounded inputs), normwise and per element."""
+    nz, ny, nx = TWO_COLUMN_SHAPE
+    ph = P.make_phantom((nx, ny, nz), seed=35, max_u=3.0)
+    S, M = round_to(ph.static, fmt), round_to(ph.moving, fmt)
+    v = round_to(P.random_field((nx, ny, nz), 36, amp=2.5), fmt)
+    out, sums = B.dir_step_stored(h, fmt, variant, 1.0, dev(S), dev(M), dev(v), 1.5, 5)
+    u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v)
+    ref = O.smooth(u_ref, 1.5, 5)
+    got = host(out)
+    assert rel(got, ref) <= 2.5 * UNIT_ROUNDOFF[fmt]
+    assert worst(got, ref) <= 4 * UNIT_ROUNDOFF[fmt]
+    tol = 1e-5 if variant == "passive" else 2.0 * UNIT_ROUNDOFF[fmt]
+    for k in range(3):
+        assert abs(sums[k] - sums_ref[k]) <= tol * abs(sums_ref[k]) + 1e-12
+
+
+@on_gpu
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_two_column_smoothing_equals_one_column(B, h, fmt):
+    """Bitwise: a registration of the two-column shape alone (its smoothing
+    launches take two columns per lane) against the same registration in a
+    lockstep batch with an odd-nx companion of the same z-chunk depth (4), whose
+    shared launches then take one column per lane for both."""
+    B.dir_autotune_clear()   # untuned depths: 4 for both registrations
+    nz, ny, nx = TWO_COLUMN_SHAPE
+    a = P.make_phantom((nx, ny, nz), seed=37, max_u=3.0)
+    b = P.make_phantom((255, 128, 24), seed=38, max_u=3.0)
+    p = B.make_params("inverse_consistent", [3], sigma=1.5, radius=5, storage=fmt)
+    q = B.make_params("passive", [3], sigma=1.5, radius=5, storage=fmt)
+    alone, st_alone = B.dir_register(h, dev(a.static), dev(a.moving), p)
+    res = B.dir_register_batch(h, [dev(a.static), dev(b.static)], [dev(a.moving), dev(b.moving)], [p, q])
+    (in_batch, st_batch), _ = res
+    assert torch.equal(alone, in_batch)
+    assert np.array_equal(np.array(st_alone["history"]), np.array(st_batch["history"]), equal_nan=True)
