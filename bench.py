@@ -22,9 +22,17 @@ Prints one JSON line:
   - roofline: the kernel that takes the most device time, its algorithmic
     bytes per launch over its average launch time, from a separate pass of
     batch steps in which its launches carry dispatch-stamped HIP events;
-  - cpu_baseline: the FP64 CPU oracle on a bounded sample of the workload;
-  - parity: each setting's whole-registration field against the oracle's
-    (RMS over voxels of the difference), from the same oracle runs.
+  - roofline_hbm: the same for the force kernel on 512x512x160 FP32
+    registrations, a working set far beyond the 256 MB last-level cache;
+  - cpu_baseline: the FP64 CPU oracle on the workload (median of three
+    full steps, plus a one-thread sample), with the host's CPU model;
+  - extra_settings: the paper's evolved passive force (Eq 2), the adjusted
+    double force with its alpha = 2 (Eq 5) and active force with alpha 0.4,
+    each registered alone (latency, ground-truth error);
+  - parity: every setting's whole-registration field against the oracle's
+    (RMS and worst voxel of the difference), with the oracle's own movement
+    under one FP32 rounding of its inputs (the bound's envelope) and under
+    FP32 rounding of its field every iteration.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -51,7 +59,19 @@ SPACING = (1.1, 1.1, 2.5)
 SETTINGS = [("passive", "passive", 1.0), ("active", "active", 1.0), ("double", "double", 1.0),
             ("passive_alpha0.4", "passive", 0.4), ("inverse_consistent", "inverse_consistent", 1.0),
             ("double_alpha0.4", "double", 0.4)]
+# The paper's own variants not among the six (Eq 2; Eq 5 with the paper's
+# alpha = 2.0) and the other reading of the combined setting: reported with
+# parity beside the step, outside its timed region.
+EXTRA_SETTINGS = [("evolved", "evolved", 1.0), ("double_alpha2.0", "double", 2.0),
+                  ("active_alpha0.4", "active", 0.4)]
 METRIC = "voxel-iters/s + HBM GB/s fraction; p50/p99 per-registration latency"
+# Parity reading at this size: the RMS of the field difference against the
+# FP64 oracle must be at most 0.01 voxel, or ENVELOPE_FACTOR times the
+# oracle's own movement when its inputs are perturbed by one FP32 rounding
+# (relative +-PERTURB_REL, the largest over PERTURB_SEEDS).
+ENVELOPE_FACTOR = 3.0
+PERTURB_REL = 6e-8
+PERTURB_SEEDS = (99, 100)
 
 # Algorithmic HBM bytes per voxel of one launch (each operand read or written
 # once; stencil neighbours and gather re-reads are not counted), for stored
@@ -121,27 +141,126 @@ def measured_traffic(kernel):
     return rec["traffic_bytes_per_launch"], "profiles/" + os.path.basename(path)
 
 
-def cpu_baseline(S, M, gpu_fields=None):
-    """The FP64 oracle on one full step of the same workload (all six settings).
+def cpu_model():
+    """The host CPU's model name (as lscpu prints it), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
-    With gpu_fields (setting -> the GPU's FP32 field of that registration),
-    also the RMS over voxels of |GPU field - oracle field| per setting, taken
-    outside the timed calls."""
+
+def perturbed_pair(S, M, seed):
+    """S and M with every value scaled by 1 + U(-PERTURB_REL, PERTURB_REL):
+    one FP32 rounding's worth of input noise."""
+    rng = np.random.default_rng(seed)
+    return (S * (1 + rng.uniform(-PERTURB_REL, PERTURB_REL, S.shape)),
+            M * (1 + rng.uniform(-PERTURB_REL, PERTURB_REL, M.shape)))
+
+
+def register_f32_field(O, S, M, variant, iters, sigma, radius, alpha, round_field=True):
+    """The oracle's registration, level by level and iteration by iteration
+    from its own primitives, with the field rounded to FP32 after every
+    iteration and every prolongation when round_field is set (the storage
+    rounding the GPU's FP32 field undergoes, with FP64 arithmetic in between).
+    Without rounding it is bitwise O.register."""
+    rnd = (lambda a: a.astype(np.float32).astype(np.float64)) if round_field else (lambda a: a)
+    Sk, Mk = [S], [M]
+    for _ in range(len(iters) - 1):
+        Sk.append(O.restrict(Sk[-1]))
+        Mk.append(O.restrict(Mk[-1]))
+    v = np.zeros((3,) + Sk[-1].shape)
+    for li, k in enumerate(range(len(iters) - 1, -1, -1)):
+        if k < len(iters) - 1:
+            v = rnd(O.prolong(v, Sk[k].shape))
+        for _ in range(iters[li]):
+            v, _ = O.iterate(O.VARIANTS[variant], Sk[k], Mk[k], v, 1, sigma, radius, alpha=alpha)
+            v = rnd(v)
+    return O.compose(v) if variant == "inverse_consistent" else v
+
+
+def rms_vox(a, b):
+    d = np.asarray(a, np.float64) - b
+    return float(np.sqrt((d * d).sum(axis=0).mean()))
+
+
+def cpu_baseline(S, M, gpu_fields=None, threads_sample=True):
+    """The FP64 oracle on the same workload.
+
+    value: voxel-iterations per second of one full step (the six settings),
+    the median of three timed steps (on the pair and on two copies perturbed
+    by one FP32 rounding, the same work).  With threads_sample, also a
+    one-thread sample: five finest-level passive iterations.
+
+    With gpu_fields (setting -> the GPU's FP32 field), the parity of every
+    setting (the six and EXTRA_SETTINGS): RMS and worst voxel of GPU minus
+    oracle, the oracle's movement under the perturbations (envelope_input) and
+    under FP32 rounding of its field every iteration (envelope_f32_field), and
+    whether the documented bound holds.  Oracle runs of the extra settings and
+    the rounded-field runs are not timed."""
     import oracle as O
-    dt = 0.0
-    rms = {}
-    for name, var, alpha in SETTINGS:
-        t0 = time.perf_counter()
-        f, _, _, _ = O.register(S, M, O.VARIANTS[var], ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha)
-        dt += time.perf_counter() - t0
-        if gpu_fields is not None and name in gpu_fields:
-            d = gpu_fields[name].astype(np.float64) - f
-            rms[name] = float(np.sqrt((d * d).sum(axis=0).mean()))
+    pairs = [(S, M)] + [perturbed_pair(S, M, sd) for sd in PERTURB_SEEDS]
+    step_s = [0.0] * len(pairs)
+    fields = {}
+    settings = SETTINGS + (EXTRA_SETTINGS if gpu_fields else [])
+    for name, var, alpha in settings:
+        timed_setting = (name, var, alpha) in SETTINGS
+        for j, (Sj, Mj) in enumerate(pairs):
+            if not timed_setting and gpu_fields is None:
+                continue
+            print(f"[bench] oracle {name} run {j}", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            f, _, _, _ = O.register(Sj, Mj, O.VARIANTS[var], ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha)
+            dt = time.perf_counter() - t0
+            if timed_setting:
+                step_s[j] += dt
+            fields[(name, j)] = f
     vi = voxel_iters(SHAPE, ITERS) * len(SETTINGS)
-    out = {"value": vi / dt, "unit": "voxel-iter/s", "cores": O.max_threads(), "kind": "oracle",
-           "sample": f"one step: the 256x256x100 pair registered with all six settings, {ITERS} iterations "
-                     f"coarse to fine ({vi} voxel-iterations, {dt:.1f} s, FP64)", "seconds": dt}
-    return out, rms
+    med = float(np.median(step_s))
+    out = {"value": vi / med, "unit": "voxel-iter/s", "cores": O.max_threads(), "kind": "oracle",
+           "cpu_model": cpu_model(), "runs": len(step_s), "seconds_per_step_runs": step_s,
+           "sample": f"one full step, the 256x256x100 pair registered with all six settings, {ITERS} iterations "
+                     f"coarse to fine ({vi} voxel-iterations, FP64), median of {len(step_s)} timed steps "
+                     f"({med:.1f} s)", "seconds": med}
+    if threads_sample:
+        O.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            O.iterate(O.PASSIVE, S, M, np.zeros((3,) + S.shape), 5, SIGMA, RADIUS)
+            dt1 = time.perf_counter() - t0
+        finally:
+            O.set_threads(out["cores"])
+        vi1 = 5 * SHAPE[0] * SHAPE[1] * SHAPE[2]
+        out["one_thread"] = {"value": vi1 / dt1, "unit": "voxel-iter/s", "cores": 1, "seconds": dt1,
+                             "sample": f"five passive iterations at 256x256x100 from a zero field ({vi1} "
+                                       f"voxel-iterations)"}
+    parity = None
+    if gpu_fields:
+        rows = {}
+        for name, var, alpha in settings:
+            if name not in gpu_fields:
+                continue
+            ref = fields[(name, 0)]
+            g = gpu_fields[name].astype(np.float64)
+            env = max(rms_vox(fields[(name, j)], ref) for j in range(1, len(pairs)))
+            print(f"[bench] oracle {name} with FP32-rounded field", file=sys.stderr, flush=True)
+            f32f = register_f32_field(O, S, M, var, ITERS, SIGMA, RADIUS, alpha)
+            d = rms_vox(g, ref)
+            bound = max(RMS_BOUND_VOX, ENVELOPE_FACTOR * env)
+            rows[name] = {"rms_vs_oracle_vox": d,
+                          "worst_voxel_vox": float(np.sqrt(((g - ref) ** 2).sum(axis=0)).max()),
+                          "envelope_input_vox": env, "envelope_f32_field_vox": rms_vox(f32f, ref),
+                          "bound_vox": bound, "pass": bool(d <= bound)}
+        parity = {"per_setting": rows, "all_pass": all(r["pass"] for r in rows.values()),
+                  "rule": f"RMS over voxels of the GPU field minus the FP64 oracle's <= max({RMS_BOUND_VOX}, "
+                          f"{ENVELOPE_FACTOR} x envelope_input); envelope_input = the oracle's own RMS movement when "
+                          f"S and M are scaled by 1 + U(-{PERTURB_REL}, {PERTURB_REL}) (largest of "
+                          f"{len(PERTURB_SEEDS)} seeds); envelope_f32_field = its movement when its field is "
+                          f"rounded to FP32 after every iteration"}
+    return out, parity
 
 
 # Reduced-precision study: 512x512x160 phantoms (max displacement 20
@@ -471,15 +590,70 @@ def serve(args):
                       "pool": pst, "results_equal_alone": same, "checked": len(checked)}))
 
 
+HBM_SHAPE = (512, 512, 160)
+HBM_ITERS = [100, 100, 50, 25]
+
+
+def hbm_roofline(args):
+    """The force kernel's roofline on a working set far beyond the 256 MB
+    last-level cache: 512x512x160 FP32 phantoms (max displacement 20 voxels),
+    4 levels, passive and inverse-consistent registrations.  Every finest-level
+    force launch is timed with dispatch-stamped events over `reps`
+    registrations; achieved = algorithmic bytes (32 B per voxel) per launch
+    over the average launch."""
+    import torch
+    from paper_0909_0928_amd import binding as B
+    from paper_0909_0928_amd import phantom as P
+    print(f"[bench] HBM roofline: building phantom {HBM_SHAPE}", file=sys.stderr, flush=True)
+    ph = P.make_phantom(HBM_SHAPE, seed=STUDY_SEED, max_u=STUDY_MAX_U, spacing_mm=SPACING)
+    dev = torch.device("cuda:0")
+    S = torch.from_numpy(ph.static.astype(np.float32)).to(dev)
+    M = torch.from_numpy(ph.moving.astype(np.float32)).to(dev)
+    del ph
+    out = torch.empty((3,) + tuple(S.shape), dtype=torch.float32, device=dev)
+    h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))
+    n0 = HBM_SHAPE[0] * HBM_SHAPE[1] * HBM_SHAPE[2]
+    abpv = algo_bytes_per_voxel("force", 4)
+    rows, tot_b, tot_ms = {}, 0.0, 0.0
+    reps = 2
+    for variant in ("passive", "inverse_consistent"):
+        p = B.make_params(variant, HBM_ITERS, sigma=SIGMA, radius=RADIUS)
+        B.dir_register(h, S, M, p, field_out=out, history=False)            # warm-up
+        B.dir_timing_enable(h, ["force", "smooth_yz"])
+        for _ in range(reps):
+            B.dir_register(h, S, M, p, field_out=out, history=False)
+        ms, n = B.dir_timing_read(h, "force", level=0)
+        ms_s, n_s = B.dir_timing_read(h, "smooth_yz", level=0)
+        B.dir_timing_enable(h, ())
+        gbs = abpv * n0 * n / (ms * 1e-3) / 1e9
+        rows[variant] = {"launches": n, "avg_launch_us": ms * 1e3 / n, "bytes_per_launch": abpv * n0,
+                         "achieved": gbs, "frac": gbs / HBM_PEAK_GBS,
+                         "smooth_yz_avg_launch_us": ms_s * 1e3 / max(n_s, 1),
+                         "smooth_yz_frac": algo_bytes_per_voxel("smooth_yz", 4) * n0 * n_s / (ms_s * 1e-3) / 1e9
+                         / HBM_PEAK_GBS if n_s else None}
+        tot_b += abpv * n0 * n
+        tot_ms += ms
+    B.dir_destroy(h)
+    achieved = tot_b / (tot_ms * 1e-3) / 1e9
+    return {"kernel": "force", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "algo_bytes_per_voxel": abpv, "per_variant": rows,
+            "workload": f"{HBM_SHAPE[0]}x{HBM_SHAPE[1]}x{HBM_SHAPE[2]} FP32 phantom pair (max displacement "
+                        f"{STUDY_MAX_U:g} voxels), 4 levels {HBM_ITERS} coarse to fine, finest-level force launches "
+                        f"of {reps} passive and {reps} inverse-consistent registrations; working set about 1.9 GB, "
+                        f"beyond the 256 MB last-level cache"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--latency-steps", type=int, default=3,
+    ap.add_argument("--latency-steps", type=int, default=10,
                     help="sequential steps for the latency and for the roofline pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gt", action="store_true", help="skip the ground-truth error pass (profiling runs)")
+    ap.add_argument("--no-hbm-roofline", action="store_true",
+                    help="skip the 512x512x160 force-kernel roofline (working set beyond the last-level cache)")
     ap.add_argument("--roofline-kernel", default=None, help="kernel to time for the roofline (default: largest)")
     ap.add_argument("--storage", choices=("f32", "f16", "bf16"), default="f32",
                     help="storage format of images and fields inside the registrations (arithmetic stays FP32)")
@@ -691,28 +865,47 @@ def main():
     gt = {}
     want_cpu = not args.no_cpu_baseline and compare
     gpu_fields = {}
+    extra = {}
+    sample_dev = torch.from_numpy(sample).to(dev)
+
+    def gt_of(field):
+        f = field.view(3, -1)[:, sample_dev].cpu().numpy().astype(np.float64)
+        d = f - vt
+        mm = np.sqrt((d[0] * SPACING[0]) ** 2 + (d[1] * SPACING[1]) ** 2 + (d[2] * SPACING[2]) ** 2)
+        return {"mean_vox": float(np.sqrt((d ** 2).sum(axis=0)).mean()), "mean_mm": float(mm.mean())}
+
     for name, _, _ in ([] if (args.no_gt or not compare) else SETTINGS):
         B.dir_register(h, S, M, params[name], field_out=outs[0], history=False)
         if want_cpu:
             gpu_fields[name] = outs[0].cpu().numpy()
-        f = outs[0].view(3, -1)[:, torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.float64)
-        d = f - vt
-        mm = np.sqrt((d[0] * SPACING[0]) ** 2 + (d[1] * SPACING[1]) ** 2 + (d[2] * SPACING[2]) ** 2)
-        gt[name] = {"mean_vox": float(np.sqrt((d ** 2).sum(axis=0)).mean()), "mean_mm": float(mm.mean())}
+        gt[name] = gt_of(outs[0])
+    # the paper's other variants, each alone (latency, ground truth, parity)
+    for name, var, alpha in ([] if (args.no_gt or not compare) else EXTRA_SETTINGS):
+        p = B.make_params(var, ITERS, sigma=SIGMA, radius=RADIUS, alpha=alpha, storage=args.storage)
+        B.dir_register(h, S, M, p, field_out=outs[0], history=False)        # warm-up
+        ms = []
+        for _ in range(args.latency_steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.dir_register(h, S, M, p, field_out=outs[0], history=False)
+            ms.append((time.perf_counter() - t0) * 1e3)
+        if want_cpu:
+            gpu_fields[name] = outs[0].cpu().numpy()
+        extra[name] = {"variant": var, "alpha": alpha, "latency_ms_p50": float(np.median(ms)),
+                       "voxel_iter_per_s_alone": vi_reg / (float(np.median(ms)) * 1e-3), "gt_error": gt_of(outs[0])}
     B.dir_destroy(h)
     B.dir_destroy(hb)
     for hh in handles:
         B.dir_destroy(hh)
 
+    roof_hbm = None
+    if compare and not args.no_hbm_roofline and args.storage == "f32":
+        roof_hbm = hbm_roofline(args)
+
     cpu, parity = None, None
     if want_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu, rms = cpu_baseline(S64, M64, gpu_fields or None)
-        if rms:
-            parity = {"rms_vs_oracle_vox": rms, "bound_vox": RMS_BOUND_VOX,
-                      "note": "whole registrations of this step against the FP64 oracle on the same inputs; "
-                              "the alpha 0.4 settings are ill-conditioned: perturbing the oracle's own inputs "
-                              "by one FP32 rounding moves its result by more than the bound"}
+        cpu, parity = cpu_baseline(S64, M64, gpu_fields or None)
 
     line = {
         "metric": METRIC, "value": value, "unit": "voxel-iter/s", "n_gpus": 1, "steps": args.steps,
@@ -731,7 +924,9 @@ def main():
         "streams": streams_res,
         "sequential": seq_res,
         "roofline": roof,
+        "roofline_hbm": roof_hbm,
         "cpu_baseline": cpu,
+        "extra_settings": extra,
         "gt_error": gt,
         "parity": parity,
         "per_kernel_ms_one_step": {k: v[0] for k, v in per_kernel.items() if v[1]},

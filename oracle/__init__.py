@@ -53,6 +53,7 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         i64 = ctypes.c_int64
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_trilerp.restype = ctypes.c_double
         L.orc_trilerp.argtypes = [dp, i64, i64, i64, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_warp.argtypes = [dp, dp, i64, i64, i64, ctypes.c_double, dp]
@@ -74,6 +75,12 @@ def lib():
 def max_threads() -> int:
     """OpenMP threads the oracle's element-wise loops use."""
     return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's element-wise loops on n threads from now on (its sums
+    are serial, so results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 def _p(a):

@@ -60,6 +60,17 @@ int orc_max_threads(void)
 #endif
 }
 
+/* Run the element-wise loops on n threads from now on (n >= 1; no effect
+ * without OpenMP).  Sums stay serial, so results do not change. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Trilinear interpolation (Sec 2.5, interpolation kernel).  The paper uses
  * its own full-precision trilinear code rather than hardware filtering.  The

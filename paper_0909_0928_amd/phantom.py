@@ -23,6 +23,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -36,6 +38,7 @@ LIPSCHITZ_LIMIT = 0.8
 REDRAW_SEED_STEP = 10 ** 6
 MAX_REDRAWS = 100
 MIN_WIDTH_AXIS = 16           # axes shorter than this do not set the field's width
+SLAB_VOXELS = 1 << 21         # analytic volumes are evaluated in z slabs of at most this many voxels
 
 
 @dataclasses.dataclass
@@ -85,6 +88,36 @@ class Phantom:
                 break
         res = np.stack(self.g_at(px - v[0], py - v[1], pz - v[2])) - v
         return v, float(np.max(np.abs(res))) if res.size else 0.0
+
+
+def _by_slabs(fn, px, py, pz, ncomp=0, workers=None):
+    """fn(px, py, pz) evaluated over z slabs of the coordinate grids, on
+    threads (numpy's element-wise loops release the interpreter lock).  The
+    slabs depend only on the grid's shape, so the values do not depend on the
+    number of threads.  fn returns one array of the slab's shape, or (ncomp > 0)
+    a tuple of ncomp of them, stacked on a new first axis."""
+    nz = px.shape[0]
+    per = max(1, SLAB_VOXELS // max(1, px[0].size))
+    out = np.empty(((ncomp,) if ncomp else ()) + px.shape)
+
+    def run(z0):
+        sl = slice(z0, z0 + per)
+        r = fn(px[sl], py[sl], pz[sl])
+        if ncomp:
+            for c in range(ncomp):
+                out[c, sl] = r[c]
+        else:
+            out[sl] = r
+
+    starts = range(0, nz, per)
+    workers = workers or min(16, os.cpu_count() or 1)
+    if len(starts) == 1 or workers == 1:
+        for z0 in starts:
+            run(z0)
+    else:
+        with ThreadPoolExecutor(max_workers=min(workers, len(starts))) as ex:
+            list(ex.map(run, starts))
+    return out
 
 
 def _grid(shape):
@@ -179,7 +212,7 @@ def make_phantom(shape, seed, max_u, spacing_mm=(1.0, 1.0, 1.0), noise_hu=10.0) 
             a = field_rng.normal(size=3)
             bumps.append((c, a))
         params = {"s": width, "A": 1.0, "bumps": bumps}
-        g = np.stack(_field_analytic(params, px, py, pz))
+        g = _by_slabs(lambda x, y, z: _field_analytic(params, x, y, z), px, py, pz, ncomp=3)
         gmax = float(np.sqrt((g * g).sum(axis=0)).max())
         params["A"] = max_u / gmax if gmax > 0 else 0.0
         g = g * params["A"]
@@ -195,15 +228,17 @@ def make_phantom(shape, seed, max_u, spacing_mm=(1.0, 1.0, 1.0), noise_hu=10.0) 
     full = {"body_c": centre, "body_a": body_a, "lung_c": lung_c, "lung_a": lung_a, "blobs": blobs}
     full.update(params)
 
-    static = _static_analytic(full, px, py, pz)
-    moving = _static_analytic(full, px + g[0], py + g[1], pz + g[2])
+    static = _by_slabs(lambda x, y, z: _static_analytic(full, x, y, z), px, py, pz)
+    qx, qy, qz = px + g[0], py + g[1], pz + g[2]
+    moving = _by_slabs(lambda x, y, z: _static_analytic(full, x, y, z), qx, qy, qz)
+    del qx, qy, qz
     # 3) noise, drawn from the generator that drew the field
     moving = moving + field_rng.normal(0.0, noise_hu, size=moving.shape)
 
-    body = _soft_inside(px, py, pz, centre, body_a) > 0.5
+    body = _by_slabs(lambda x, y, z: _soft_inside(x, y, z, centre, body_a), px, py, pz) > 0.5
     lung = np.zeros_like(body)
     for c in lung_c:
-        lung |= _soft_inside(px, py, pz, c, lung_a) > 0.5
+        lung |= _by_slabs(lambda x, y, z: _soft_inside(x, y, z, c, lung_a), px, py, pz) > 0.5
     return Phantom(shape=(nx, ny, nz), seed=seed, max_u=float(max_u), spacing_mm=tuple(spacing_mm),
                    static=static, moving=moving, field_g=g, body=body, lung=lung,
                    redraws=redraws, lipschitz=lip, _params=full)

@@ -87,3 +87,26 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     assert r["fetch_factor"] == pytest.approx(2.0) and r["write_factor"] == pytest.approx(1.0)
     assert r["traffic_bytes_per_launch"] == pytest.approx(100.0 * 1024 * 2 + 40.0 * 1024)
     assert r["source_sha256"] == PS.source_fingerprint("force")
+
+
+def test_rounded_field_oracle_is_the_oracle_without_rounding():
+    """The parity envelope's rounded-field registration, run without rounding,
+    is bitwise the oracle's registration (same primitives in the same order)."""
+    import numpy as np
+    import oracle as O
+    from paper_0909_0928_amd import phantom as P
+    ph = P.make_phantom((20, 18, 10), seed=5, max_u=2.0)
+    for variant in ("passive", "inverse_consistent"):
+        ref, _, _, _ = O.register(ph.static, ph.moving, O.VARIANTS[variant], [3, 2], sigma=1.0, radius=3,
+                                  alpha=0.4)
+        got = bench.register_f32_field(O, ph.static, ph.moving, variant, [3, 2], 1.0, 3, 0.4, round_field=False)
+        assert np.array_equal(got, ref)
+        r = bench.register_f32_field(O, ph.static, ph.moving, variant, [3, 2], 1.0, 3, 0.4)
+        assert 0 < bench.rms_vox(r, ref) < 1e-4
+
+
+def test_perturbed_pair_is_one_rounding():
+    import numpy as np
+    S = np.full((4, 5, 6), -1000.0)
+    Sp, Mp = bench.perturbed_pair(S, S + 1.0, 99)
+    assert 0 < np.abs(Sp / S - 1).max() <= bench.PERTURB_REL
