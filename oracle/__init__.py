@@ -68,6 +68,12 @@ def lib():
         L.orc_compose.argtypes = [dp, i64, i64, i64, ctypes.c_int, dp]
         L.orc_register.argtypes = [dp, dp, i64, i64, i64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_int, ip, ctypes.c_double, ctypes.c_int, dp, dp, ip]
+        L.orc_register_ex.argtypes = [dp, dp, i64, i64, i64, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ip,
+                                      ctypes.c_double, ctypes.c_int, dp, dp, ip]
+        L.orc_smooth3.argtypes = [dp, ctypes.c_int, i64, i64, i64, dp, ip, dp]
+        L.orc_iterate_mm.argtypes = [ctypes.c_int, ctypes.c_double, dp, ip, dp, dp, i64, i64, i64, dp, dp,
+                                     ctypes.c_int, ctypes.c_double, dp]
         _lib = L
     return _lib
 
@@ -148,6 +154,37 @@ def smooth(a, sigma, radius=None):
     return out if a.ndim == 4 else out[0]
 
 
+def smooth3(a, sigma3, radius3):
+    """Per-axis Gaussian smoothing (sigma and radius per axis x, y, z) of a
+    volume or a stack."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    stack = a if a.ndim == 4 else a[None]
+    out = np.empty_like(stack)
+    sg = np.ascontiguousarray(sigma3, dtype=np.float64)
+    rd = (ctypes.c_int * 3)(*[int(r) for r in radius3])
+    rc = lib().orc_smooth3(_p(stack), stack.shape[0], *_dims(stack), _p(sg), rd, _p(out))
+    if rc != OK:
+        raise OracleError(rc)
+    return out if a.ndim == 4 else out[0]
+
+
+def iterate_mm(variant, S, M, v_mm, iters, sigma3, radius3, h_mm, alpha=1.0, eps=0.0):
+    """iterate() in physical units: field in mm, voxel size h_mm, per-axis
+    Gaussian widths sigma3 (voxels) and radii radius3."""
+    S = _vol(S)
+    M = _vol(M)
+    v = np.array(_field(v_mm, S.shape), copy=True)
+    hist = np.zeros((max(iters, 1), 4))
+    sg = np.ascontiguousarray(sigma3, dtype=np.float64)
+    hh = np.ascontiguousarray(h_mm, dtype=np.float64)
+    rd = (ctypes.c_int * 3)(*[int(r) for r in radius3])
+    n = lib().orc_iterate_mm(int(variant), float(alpha), _p(sg), rd, _p(S), _p(M), *_dims(S), _p(hh), _p(v),
+                             int(iters), float(eps), _p(hist))
+    if n < 0:
+        raise OracleError(n)
+    return v, hist[:n]
+
+
 def coarse_shape(shape3):
     """[nz, ny, nx] -> ceil(n / 2) per dimension."""
     return tuple((n + 1) // 2 for n in shape3)
@@ -203,12 +240,17 @@ def compose(h, K=DEFAULT_COMPOSE_ITERS):
 
 
 def register(S, M, variant, iters, sigma, radius=None, alpha=1.0, eps=0.0, compose_iters=DEFAULT_COMPOSE_ITERS,
-             raise_on_error=True):
+             raise_on_error=True, spacing=None, physical=False, image_sigma=0.0):
     """Multi-scale registration.  iters lists levels coarse -> fine.
 
-    Returns (field [3,nz,ny,nx], history [sum(iters_run), 4], iters_run list, rc).
+    spacing: None or the voxel sizes (x, y, z) in mm; physical=True works in
+    mm (sigma and image_sigma in mm); image_sigma > 0 pre-smooths every
+    level's images.  radius None (or <= 0) selects ceil(3 sigma) per axis.
+
+    Returns (field [3,nz,ny,nx] in voxels, history [sum(iters_run), 4],
+    iters_run list, rc).
     """
-    radius = default_radius(sigma) if radius is None else int(radius)
+    radius = 0 if radius is None else int(radius)
     S = _vol(S)
     M = _vol(M)
     if S.shape != M.shape:
@@ -219,8 +261,10 @@ def register(S, M, variant, iters, sigma, radius=None, alpha=1.0, eps=0.0, compo
     run = (ctypes.c_int * max(levels, 1))()
     field = np.zeros((3,) + S.shape)
     hist = np.zeros((max(sum(iters), 1), 4))
-    rc = lib().orc_register(_p(S), _p(M), *_dims(S), int(variant), float(alpha), float(sigma), radius, levels, it,
-                            float(eps), int(compose_iters), _p(field), _p(hist), run)
+    sp = np.ascontiguousarray(spacing, dtype=np.float64) if spacing is not None else None
+    rc = lib().orc_register_ex(_p(S), _p(M), *_dims(S), _p(sp) if sp is not None else None, int(bool(physical)),
+                               float(image_sigma), int(variant), float(alpha), float(sigma), radius, levels, it,
+                               float(eps), int(compose_iters), _p(field), _p(hist), run)
     if rc != OK and raise_on_error:
         raise OracleError(rc)
     runs = list(run)[:levels]

@@ -478,31 +478,262 @@ void orc_compose(const double *h, int64_t nx, int64_t ny, int64_t nz, int K, dou
             }
 }
 
-/* Multi-scale registration (Sec 2.3, Fig 1a).
+/* ------------------------------------------------------------------------
+ * Physical units.  The paper states the method in voxel units (its Gaussian
+ * has unit standard deviation, Sec 2.5) while its images have anisotropic
+ * voxels (Table 1: about 1.1 x 1.1 x 2.5 mm).  In the physical mode below the
+ * same iteration is written in millimetres:
+ *   - the gradient is in intensity per mm (central difference over 2 h_a);
+ *   - the field, its increment and the norms of Sec 2.4 are in mm; a sample
+ *     of the deformed image lies at x - v(x) / h (voxel coordinates);
+ *   - the force carries the squared intensity difference over a squared
+ *     length, the mean squared voxel size K = (h_x^2 + h_y^2 + h_z^2) / 3 of
+ *     the level (the normaliser of the demons force in physical units), so
+ *     Eq 1 becomes dr = D G K / (alpha^2 D^2 + K |G|^2) and Eq 2
+ *     e = 4 D G |G| a K / ((2 D^2 + K |G|^2 + K a^2) (|G|^2 + a^2))
+ *     (a = |grad Im0| per mm);
+ *     the zero-force floor applies to the first factor of each denominator
+ *     as in voxel units (there K = 1);
+ *   - the Gaussian's sigma (and the image pre-smoothing's) is in mm of the
+ *     input grid: sigma / h_a voxels along axis a on every level, as the
+ *     voxel mode uses sigma voxels on every level; the radius is
+ *     ceil(3 sigma / h_a) per axis unless given;
+ *   - level k has voxels of 2^k h (2x down-sampling, Sec 2.3), and the field
+ *     is carried to the finer level by the same cell-centred interpolation
+ *     without the factor 2 (a length in mm does not change with the grid).
+ * With h = (1, 1, 1) every step reduces to the voxel-unit one.
+ * ------------------------------------------------------------------------ */
+
+/* Per-axis Gaussian smoothing: x pass with sigma[0], radius[0], then y, then
+ * z, clamped borders. */
+int orc_smooth3(const double *in, int ncomp, int64_t nx, int64_t ny, int64_t nz, const double *sigma,
+                const int *radius, double *out)
+{
+    double w[3][2 * ORC_MAX_RADIUS + 1];
+    for (int a = 0; a < 3; ++a) {
+        if (!(sigma[a] > 0.0) || radius[a] < 0 || radius[a] > ORC_MAX_RADIUS) return ORC_EINVAL;
+        orc_gauss_weights(sigma[a], radius[a], w[a]);
+    }
+    const int64_t N = nx * ny * nz;
+    double *t1 = (double *)malloc(sizeof(double) * N);
+    double *t2 = (double *)malloc(sizeof(double) * N);
+    if (!t1 || !t2) { free(t1); free(t2); return ORC_ENOMEM; }
+    for (int c = 0; c < ncomp; ++c) {
+        smooth_pass(in + c * N, nx, ny, nz, 0, w[0], radius[0], t1);
+        smooth_pass(t1, nx, ny, nz, 1, w[1], radius[1], t2);
+        smooth_pass(t2, nx, ny, nz, 2, w[2], radius[2], out + c * N);
+    }
+    free(t1);
+    free(t2);
+    return ORC_OK;
+}
+
+/* Gradient in intensity per mm, voxel size h (mm). */
+static void gradient_mm(const double *I, int64_t nx, int64_t ny, int64_t nz, const double *h, double *g)
+{
+    const int64_t N = nx * ny * nz;
+    orc_gradient(I, nx, ny, nz, g);
+    for (int a = 0; a < 3; ++a)
+        for (int64_t i = 0; i < N; ++i) g[a * N + i] /= h[a];
+}
+
+/* Deformed image with a field in mm: out(x) = I(x - sign * v(x) / h). */
+static void warp_mm(const double *I, const double *v, int64_t nx, int64_t ny, int64_t nz, const double *h, double sign,
+                    double *out)
+{
+    const int64_t N = nx * ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < nz; ++z)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t i = at(x, y, z, nx, ny);
+                out[i] = orc_trilerp(I, nx, ny, nz, (double)x - sign * v[i] / h[0], (double)y - sign * v[N + i] / h[1],
+                                     (double)z - sign * v[2 * N + i] / h[2]);
+            }
+}
+
+/* Eq 1 / Eq 3 / Eq 5 in mm (see above). */
+static void force_term_mm(double D, const double *G, double alpha, double K, double *f)
+{
+    const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    const double den = alpha * alpha * D * D + K * G2;
+    if (den <= ORC_DENOM_FLOOR) { f[0] = f[1] = f[2] = 0.0; return; }
+    for (int a = 0; a < 3; ++a) f[a] = D * G[a] * K / den;
+}
+
+/* Eq 2 in mm (see above, numerator and denominator multiplied by K once
+ * more); a = |grad Im0| in intensity per mm. */
+static void evolved_term_mm(double D, const double *G, double am, double K, double *f)
+{
+    const double G2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    const double den = (2.0 * D * D + K * G2 + K * am * am) * (K * G2 + K * am * am);
+    if (den <= ORC_DENOM_FLOOR) { f[0] = f[1] = f[2] = 0.0; return; }
+    const double s = 4.0 * D * sqrt(G2) * am * K * K / den;
+    for (int a = 0; a < 3; ++a) f[a] = s * G[a];
+}
+
+/* One force evaluation in mm at a level of voxel size h: u = v + dr (mm),
+ * sums as in force_step with the norms in mm. */
+static int force_step_mm(int variant, double alpha, const double *S, const double *M, const double *v, int64_t nx,
+                         int64_t ny, int64_t nz, const double *h, const double *gs, const double *am, double *u,
+                         double *sums)
+{
+    const int64_t N = nx * ny * nz;
+    const double K = (h[0] * h[0] + h[1] * h[1] + h[2] * h[2]) / 3.0;
+    const int need_gm = (variant == ORC_ACTIVE || variant == ORC_DOUBLE || variant == ORC_INVERSE_CONSISTENT);
+    const int is_ic = (variant == ORC_INVERSE_CONSISTENT);
+    double *Im = (double *)malloc(sizeof(double) * N);
+    double *D = (double *)malloc(sizeof(double) * N);
+    double *dr = (double *)malloc(sizeof(double) * 3 * N);
+    double *gm = need_gm ? (double *)malloc(sizeof(double) * 3 * N) : NULL;
+    double *Is = is_ic ? (double *)malloc(sizeof(double) * N) : NULL;
+    double *gsn = is_ic ? (double *)malloc(sizeof(double) * 3 * N) : NULL;
+    int rc = ORC_OK;
+    if (!Im || !D || !dr || (need_gm && !gm) || (is_ic && (!Is || !gsn))) { rc = ORC_ENOMEM; goto done; }
+    warp_mm(M, v, nx, ny, nz, h, +1.0, Im);
+    if (need_gm) gradient_mm(Im, nx, ny, nz, h, gm);
+    if (is_ic) {
+        warp_mm(S, v, nx, ny, nz, h, -1.0, Is);
+        gradient_mm(Is, nx, ny, nz, h, gsn);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double f[3] = {0, 0, 0}, b[3] = {0, 0, 0}, G[3];
+        if (is_ic) {
+            D[i] = Im[i] - Is[i];
+            for (int a = 0; a < 3; ++a) G[a] = gm[a * N + i] + gsn[a * N + i];
+            force_term_mm(D[i], G, alpha, K, f);
+        } else {
+            D[i] = Im[i] - S[i];
+            for (int a = 0; a < 3; ++a) G[a] = gs ? gs[a * N + i] : 0.0;
+            if (variant == ORC_PASSIVE || variant == ORC_DOUBLE) force_term_mm(D[i], G, alpha, K, f);
+            if (variant == ORC_ACTIVE || variant == ORC_DOUBLE) {
+                double Gm[3] = {gm[i], gm[N + i], gm[2 * N + i]};
+                force_term_mm(D[i], Gm, alpha, K, b);
+            }
+            if (variant == ORC_EVOLVED) evolved_term_mm(D[i], G, am[i], K, f);
+        }
+        for (int a = 0; a < 3; ++a) {
+            dr[a * N + i] = f[a] + b[a];
+            u[a * N + i] = v[a * N + i] + dr[a * N + i];
+        }
+    }
+    {
+        double s1 = 0.0, s2 = 0.0, sse = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
+            s1 += sqrt(dr[i] * dr[i] + dr[N + i] * dr[N + i] + dr[2 * N + i] * dr[2 * N + i]);
+            s2 += sqrt(v[i] * v[i] + v[N + i] * v[N + i] + v[2 * N + i] * v[2 * N + i]);
+            sse += D[i] * D[i];
+        }
+        sums[0] = s1;
+        sums[1] = s2;
+        sums[2] = sse;
+    }
+done:
+    free(Im);
+    free(D);
+    free(dr);
+    free(gm);
+    free(Is);
+    free(gsn);
+    return rc;
+}
+
+/* Iterations at one level in mm (orc_iterate in physical units): v in mm,
+ * voxel size h, Gaussian widths sigma[a] voxels with radius[a]. */
+int orc_iterate_mm(int variant, double alpha, const double *sigma, const int *radius, const double *S, const double *M,
+                   int64_t nx, int64_t ny, int64_t nz, const double *h, double *v, int iters, double eps,
+                   double *history)
+{
+    if (!valid_variant(variant) || !(alpha > 0.0) || iters < 0 || !(eps >= 0.0)) return ORC_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!(h[a] > 0.0) || !(sigma[a] > 0.0) || radius[a] < 0 || radius[a] > ORC_MAX_RADIUS) return ORC_EINVAL;
+    const int64_t N = nx * ny * nz;
+    double *u = (double *)malloc(sizeof(double) * 3 * N);
+    double *gs = uses_static_gradient(variant) ? (double *)malloc(sizeof(double) * 3 * N) : NULL;
+    double *am = variant == ORC_EVOLVED ? (double *)malloc(sizeof(double) * N) : NULL;
+    double *gm0 = variant == ORC_EVOLVED ? (double *)malloc(sizeof(double) * 3 * N) : NULL;
+    int rc = ORC_OK, n = 0;
+    if (!u || (uses_static_gradient(variant) && !gs) || (variant == ORC_EVOLVED && (!am || !gm0))) rc = ORC_ENOMEM;
+    if (rc == ORC_OK && gs) gradient_mm(S, nx, ny, nz, h, gs);
+    if (rc == ORC_OK && am) {
+        gradient_mm(M, nx, ny, nz, h, gm0);
+        for (int64_t i = 0; i < N; ++i)
+            am[i] = sqrt(gm0[i] * gm0[i] + gm0[N + i] * gm0[N + i] + gm0[2 * N + i] * gm0[2 * N + i]);
+    }
+    for (; rc == ORC_OK && n < iters; ++n) {
+        double sums[3];
+        rc = force_step_mm(variant, alpha, S, M, v, nx, ny, nz, h, gs, am, u, sums);
+        if (rc != ORC_OK) break;
+        rc = orc_smooth3(u, 3, nx, ny, nz, sigma, radius, v);
+        if (rc != ORC_OK) break;
+        double l = sums[1] > 0.0 ? sums[0] / sums[1] : NAN;
+        history[4 * n + 0] = sums[0];
+        history[4 * n + 1] = sums[1];
+        history[4 * n + 2] = sums[2] / (double)N;
+        history[4 * n + 3] = l;
+        if (eps > 0.0 && n >= 10) {
+            double l10 = history[4 * (n - 10) + 3];
+            if (!isnan(l) && !isnan(l10) && l10 - l <= eps) { ++n; break; }
+        }
+    }
+    free(u);
+    free(gs);
+    free(am);
+    free(gm0);
+    return rc == ORC_OK ? n : rc;
+}
+
+/* Multi-scale registration (Sec 2.3, Fig 1a), with the optional physical
+ * units above and the optional Gaussian pre-smoothing of the images (Sec 2.5:
+ * the low-pass filter kernel smooths images as well as displacement
+ * vectors).
  *
  * levels >= 1 resolution levels, level 0 the input grid and level k of size
  * ceil(n / 2^k) per dimension; iters[] lists the iteration counts from the
  * coarsest level to the finest.  The field starts at 0 on the coarsest level
- * and is prolonged (values times 2) to each finer level.  compose_iters is K
- * of orc_compose for the inverse-consistent variant (ignored otherwise).
+ * and is carried to each finer level by cell-centred interpolation (values
+ * times 2 in voxel units).  compose_iters is K of orc_compose for the
+ * inverse-consistent variant (ignored otherwise).
+ *
+ * spacing: NULL or the three voxel sizes in mm; physical != 0 selects the
+ * physical units (spacing required), sigma then in mm.  image_sigma > 0
+ * smooths every level's S and M (restricted from the unsmoothed finer level)
+ * with a Gaussian of that width (voxels, or mm in the physical mode; radius
+ * ceil(3 width) per axis) before the level's iterations; 0 disables it.
  *
  * field receives 3 * nx*ny*nz doubles (voxel units, M(x - v(x)) = S(x));
  * history must hold 4 doubles per iteration of sum(iters); iters_run[] gets
  * the iterations run per level (coarse to fine); the history of the levels is
- * packed in that order.  Returns ORC_OK, ORC_EINVAL, ORC_ENOMEM or
- * ORC_ENUMERIC (a non-finite sum in the history). */
-int orc_register(const double *S, const double *M, int64_t nx, int64_t ny, int64_t nz, int variant, double alpha,
-                 double sigma, int radius, int levels, const int *iters, double eps, int compose_iters,
-                 double *field, double *history, int *iters_run)
+ * packed in that order (sums in mm in the physical mode).  Returns ORC_OK,
+ * ORC_EINVAL, ORC_ENOMEM or ORC_ENUMERIC (a non-finite sum in the history). */
+int orc_register_ex(const double *S, const double *M, int64_t nx, int64_t ny, int64_t nz, const double *spacing,
+                    int physical, double image_sigma, int variant, double alpha, double sigma, int radius, int levels,
+                    const int *iters, double eps, int compose_iters, double *field, double *history, int *iters_run)
 {
     if (nx < 1 || ny < 1 || nz < 1 || levels < 1 || levels > ORC_MAX_LEVELS || !valid_variant(variant) ||
-        compose_iters < 0)
+        compose_iters < 0 || !(image_sigma >= 0.0) || !(sigma > 0.0))
         return ORC_EINVAL;
+    if (physical && !spacing) return ORC_EINVAL;
+    if (spacing)
+        for (int a = 0; a < 3; ++a)
+            if (!(spacing[a] > 0.0)) return ORC_EINVAL;
     for (int l = 0; l < levels; ++l)
         if (iters[l] < 0) return ORC_EINVAL;
+    /* Gaussian widths in voxels per axis */
+    double sv[3], si[3];
+    int rv[3], ri[3];
+    for (int a = 0; a < 3; ++a) {
+        sv[a] = physical ? sigma / spacing[a] : sigma;
+        rv[a] = radius > 0 ? radius : (int)ceil(3.0 * sv[a]);
+        si[a] = physical ? image_sigma / spacing[a] : image_sigma;
+        ri[a] = (int)ceil(3.0 * si[a]);
+        if (rv[a] > ORC_MAX_RADIUS || (image_sigma > 0.0 && ri[a] > ORC_MAX_RADIUS)) return ORC_EINVAL;
+    }
 
     int64_t dims[ORC_MAX_LEVELS][3];
     double *Sk[ORC_MAX_LEVELS] = {0}, *Mk[ORC_MAX_LEVELS] = {0};
+    double *Ss[ORC_MAX_LEVELS] = {0}, *Ms[ORC_MAX_LEVELS] = {0};  /* pre-smoothed levels */
     dims[0][0] = nx;
     dims[0][1] = ny;
     dims[0][2] = nz;
@@ -524,31 +755,66 @@ int orc_register(const double *S, const double *M, int64_t nx, int64_t ny, int64
         orc_restrict(Sk[k - 1], dims[k - 1][0], dims[k - 1][1], dims[k - 1][2], Sk[k]);
         orc_restrict(Mk[k - 1], dims[k - 1][0], dims[k - 1][1], dims[k - 1][2], Mk[k]);
     }
+    for (int k = 0; k < levels && rc == ORC_OK && image_sigma > 0.0; ++k) {
+        const int64_t *d = dims[k];
+        int64_t Nk = d[0] * d[1] * d[2];
+        Ss[k] = (double *)malloc(sizeof(double) * Nk);
+        Ms[k] = (double *)malloc(sizeof(double) * Nk);
+        if (!Ss[k] || !Ms[k]) { rc = ORC_ENOMEM; break; }
+        rc = orc_smooth3(Sk[k], 1, d[0], d[1], d[2], si, ri, Ss[k]);
+        if (rc == ORC_OK) rc = orc_smooth3(Mk[k], 1, d[0], d[1], d[2], si, ri, Ms[k]);
+    }
 
     int64_t hist_off = 0;
     for (int k = levels - 1; k >= 0 && rc == ORC_OK; --k) {
         const int li = levels - 1 - k; /* coarse-to-fine position */
         const int64_t *d = dims[k];
+        const double *Sl = image_sigma > 0.0 ? Ss[k] : Sk[k], *Ml = image_sigma > 0.0 ? Ms[k] : Mk[k];
         if (k < levels - 1) {
             const int64_t *dc = dims[k + 1];
             orc_prolong(v, dc[0], dc[1], dc[2], vt, d[0], d[1], d[2]);
-            memcpy(v, vt, sizeof(double) * 3 * d[0] * d[1] * d[2]);
+            const int64_t n3 = 3 * d[0] * d[1] * d[2];
+            if (physical) /* a length in mm: undo the voxel-unit factor 2 */
+                for (int64_t i = 0; i < n3; ++i) vt[i] *= 0.5;
+            memcpy(v, vt, sizeof(double) * n3);
         }
-        int n = orc_iterate(variant, alpha, sigma, radius, Sk[k], Mk[k], d[0], d[1], d[2], v, iters[li], eps,
+        int n;
+        if (physical) {
+            double h[3];
+            for (int a = 0; a < 3; ++a) h[a] = ldexp(spacing[a], k);  /* 2^k h */
+            n = orc_iterate_mm(variant, alpha, sv, rv, Sl, Ml, d[0], d[1], d[2], h, v, iters[li], eps,
+                               history + 4 * hist_off);
+        } else {
+            n = orc_iterate(variant, alpha, sigma, rv[0], Sl, Ml, d[0], d[1], d[2], v, iters[li], eps,
                             history + 4 * hist_off);
+        }
         if (n < 0) { rc = n; break; }
         iters_run[li] = n;
         hist_off += n;
     }
 
     if (rc == ORC_OK) {
+        if (physical) /* mm -> voxels of the input grid */
+            for (int a = 0; a < 3; ++a)
+                for (int64_t i = 0; i < N0; ++i) v[a * N0 + i] /= spacing[a];
         if (variant == ORC_INVERSE_CONSISTENT) orc_compose(v, nx, ny, nz, compose_iters, field);
         else memcpy(field, v, sizeof(double) * 3 * N0);
         for (int64_t i = 0; i < 4 * hist_off; ++i)
             if ((i % 4) != 3 && !isfinite(history[i])) { rc = ORC_ENUMERIC; break; }
     }
     for (int k = 1; k < levels; ++k) { free(Sk[k]); free(Mk[k]); }
+    for (int k = 0; k < levels; ++k) { free(Ss[k]); free(Ms[k]); }
     free(v);
     free(vt);
     return rc;
+}
+
+/* Multi-scale registration in voxel units without pre-smoothing (the paper's
+ * form); see orc_register_ex. */
+int orc_register(const double *S, const double *M, int64_t nx, int64_t ny, int64_t nz, int variant, double alpha,
+                 double sigma, int radius, int levels, const int *iters, double eps, int compose_iters,
+                 double *field, double *history, int *iters_run)
+{
+    return orc_register_ex(S, M, nx, ny, nz, NULL, 0, 0.0, variant, alpha, sigma, radius, levels, iters, eps,
+                           compose_iters, field, history, iters_run);
 }

@@ -477,3 +477,116 @@ def test_register_single_level_equals_iterate():
         v, hist = O.iterate(variant, S, M, z, 5, sigma=1.5, radius=4, alpha=0.4)
         field, hist2, runs, rc = O.register(S, M, variant, [5], sigma=1.5, radius=4, alpha=0.4)
         assert np.array_equal(v, field) and np.array_equal(hist, hist2, equal_nan=True)
+
+
+# --------------------------------------------------------------------------
+# Physical units (field, gradient, sigma in mm) and image pre-smoothing
+# --------------------------------------------------------------------------
+def test_smooth3_equals_scipy_gaussian_filter():
+    a = RNG.normal(size=(9, 10, 11))
+    sig, rad = (1.3, 0.7, 2.0), (4, 2, 6)   # x, y, z
+    ref = ndimage.gaussian_filter(a, sigma=sig[::-1], mode="nearest", radius=rad[::-1])
+    np.testing.assert_allclose(O.smooth3(a, sig, rad), ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("variant", ["passive", "evolved", "active", "double", "inverse_consistent"])
+def test_physical_mode_with_voxels_of_two_mm_is_the_voxel_mode(variant):
+    """Isotropic 2 mm voxels and sigma in mm = 2 x sigma in voxels: every mm
+    quantity is a power-of-two multiple of the voxel one, so the field is
+    bitwise the voxel-unit registration's and the sums are scaled by the
+    level's voxel size 2^k * 2 mm (the relative norm and the mean D^2 equal)."""
+    ph = P.make_phantom((30, 26, 14), seed=31, max_u=2.0)
+    iters = [4, 3]
+    ref, hist, runs, _ = O.register(ph.static, ph.moving, O.VARIANTS[variant], iters, sigma=1.0, alpha=0.7,
+                                    image_sigma=0.8)
+    got, hist_mm, runs_mm, _ = O.register(ph.static, ph.moving, O.VARIANTS[variant], iters, sigma=2.0, alpha=0.7,
+                                          spacing=(2.0, 2.0, 2.0), physical=True, image_sigma=1.6)
+    assert np.array_equal(got, ref) and runs == runs_mm
+    scale = np.array([4.0] * iters[0] + [2.0] * iters[1])   # level 1: 4 mm voxels, level 0: 2 mm
+    np.testing.assert_array_equal(hist_mm[:, 0], hist[:, 0] * scale)
+    np.testing.assert_array_equal(hist_mm[:, 1], hist[:, 1] * scale)
+    np.testing.assert_array_equal(hist_mm[:, 2], hist[:, 2])
+    np.testing.assert_array_equal(hist_mm[:, 3], hist[:, 3])
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.4])
+def test_physical_ramp_along_the_thick_axis(alpha):
+    """S = z, M = z + t on 1.1 x 1.1 x 2.5 mm voxels.  In mm, G = (0, 0, 1/h_z)
+    and D = t - v_z (voxels), so Eq 1 with the normaliser K = mean h^2 moves the
+    voxel-unit error e = t - v_z by e' = e - e c / (alpha^2 e^2 + c), with
+    c = K / h_z^2, at voxels the border has not reached."""
+    h = (1.1, 1.1, 2.5)
+    nz, t, n = 120, 1.3, 8
+    S = np.broadcast_to(np.arange(nz, dtype=float)[:, None, None], (nz, 5, 6)).copy()
+    field, _, _, _ = O.register(S, S + t, O.PASSIVE, [n], sigma=1.0, alpha=alpha, spacing=h, physical=True)
+    c = (sum(x * x for x in h) / 3.0) / (h[2] * h[2])
+    e = t
+    for _ in range(n):
+        e = e - e * c / (alpha * alpha * e * e + c)
+    assert abs((t - field[2][nz // 2, 2, 3]) - e) < 1e-12
+    assert abs(field[0][nz // 2, 2, 3]) < 1e-15 and abs(field[1][nz // 2, 2, 3]) < 1e-15
+
+
+def test_physical_mode_smooths_with_per_axis_widths():
+    """One iteration from a zero field: the mm force field, smoothed with
+    sigma / h_a voxels (radius ceil(3 sigma / h_a)) per axis (scipy's Gaussian),
+    then expressed in voxels of the input grid."""
+    h = (1.1, 0.9, 2.5)
+    ph = P.make_phantom((24, 22, 12), seed=32, max_u=2.0)
+    S, M = ph.static, ph.moving
+    field, hist, _, _ = O.register(S, M, O.PASSIVE, [1], sigma=1.5, spacing=h, physical=True)
+    G = O.gradient(S) / np.array(h)[:, None, None, None]
+    D = M - S
+    K = sum(x * x for x in h) / 3.0
+    den = D * D + K * (G * G).sum(axis=0)
+    dr = D * G * K / den
+    sig = [1.5 / x for x in h]
+    rad = [int(np.ceil(3 * s)) for s in sig]
+    expect = np.stack([ndimage.gaussian_filter(dr[c], sigma=sig[::-1], mode="nearest", radius=rad[::-1]) / h[c]
+                       for c in range(3)])
+    np.testing.assert_allclose(field, expect, rtol=0, atol=1e-12)
+    assert math.isclose(hist[0, 0], float(np.sqrt((dr * dr).sum(axis=0)).sum()), rel_tol=1e-12)
+    assert math.isclose(hist[0, 2], float((D * D).mean()), rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("physical", [False, True])
+def test_presmoothing_is_a_gaussian_of_each_level(physical):
+    """Two levels with image pre-smoothing equal the same levels run by hand on
+    images smoothed with scipy's Gaussian (per axis, clamped borders): level 1
+    from the restricted unsmoothed image, level 0 from the input."""
+    h = (1.1, 1.1, 2.5) if physical else (1.0, 1.0, 1.0)
+    ph = P.make_phantom((28, 24, 16), seed=33, max_u=2.0)
+    S, M = ph.static, ph.moving
+    isig, sig, iters = 1.2, 1.0, [3, 2]
+    field, _, _, _ = O.register(S, M, O.ACTIVE, iters, sigma=sig, spacing=h if physical else None,
+                                physical=physical, image_sigma=isig)
+
+    def pre(I):
+        s = [isig / x for x in h]
+        return ndimage.gaussian_filter(I, sigma=s[::-1], mode="nearest", radius=[int(np.ceil(3 * q)) for q in s[::-1]])
+
+    S1, M1 = O.restrict(S), O.restrict(M)
+    sv = [sig / x for x in h]
+    rv = [int(np.ceil(3 * q)) for q in sv]
+    if physical:
+        v, _ = O.iterate_mm(O.ACTIVE, pre(S1), pre(M1), np.zeros((3,) + S1.shape), iters[0], sv, rv,
+                            [2 * x for x in h])
+        v = O.prolong(v, S.shape) / 2.0
+        v, _ = O.iterate_mm(O.ACTIVE, pre(S), pre(M), v, iters[1], sv, rv, h)
+        v = v / np.array(h)[:, None, None, None]
+    else:
+        v, _ = O.iterate(O.ACTIVE, pre(S1), pre(M1), np.zeros((3,) + S1.shape), iters[0], sig)
+        v = O.prolong(v, S.shape)
+        v, _ = O.iterate(O.ACTIVE, pre(S), pre(M), v, iters[1], sig)
+    np.testing.assert_allclose(field, v, rtol=0, atol=1e-10)
+
+
+def test_physical_mode_needs_spacing_and_radius_within_bounds():
+    S = np.zeros((6, 7, 8))
+    _, _, _, rc = O.register(S, S, O.PASSIVE, [1], sigma=1.0, physical=True, raise_on_error=False)
+    assert rc == O.EINVAL
+    # sigma 6 mm on 1 mm voxels: ceil(18) taps per side exceed 16
+    _, _, _, rc = O.register(S, S, O.PASSIVE, [1], sigma=6.0, spacing=(1, 1, 1), physical=True, raise_on_error=False)
+    assert rc == O.EINVAL
+    _, _, _, rc = O.register(S, S, O.PASSIVE, [1], sigma=1.0, image_sigma=6.0, raise_on_error=False)
+    assert rc == O.EINVAL
