@@ -71,18 +71,49 @@ typedef enum {
     DIR_INVERSE_CONSISTENT = 4   /* Eq 6: both images deformed toward each other */
 } dir_variant;
 
-/* Registration parameters.  Set struct_size = sizeof(dir_params). */
+/* Units the iteration is written in.  The paper states the method in voxel
+ * units (its Gaussian has unit standard deviation, Sec 2.5) while its images
+ * have anisotropic voxels (Table 1: about 1.1 x 1.1 x 2.5 mm).  DIR_UNITS_MM
+ * writes the same iteration in millimetres, from the voxel sizes spacing_mm
+ * (h_x, h_y, h_z) of the input grid (level k has voxels of 2^k h):
+ *   - gradients are in intensity per mm;
+ *   - the force carries the squared intensity difference over K, the mean
+ *     squared voxel size of the level: Eq 1 becomes
+ *     dr = D G K / (alpha^2 D^2 + K |G|^2) (Eqs 2-6 likewise, Eq 2 with K
+ *     against every squared gradient), dr in mm;
+ *   - sigma (and image_sigma) are in mm: the Gaussian has sigma / h_a voxels
+ *     along axis a on every level, radius ceil(3 sigma / h_a) per axis unless
+ *     `radius` is given;
+ *   - the norms of the relative norm (Sec 2.4) are in mm.
+ * The output field is in voxels of the input grid either way.  With
+ * h = (1, 1, 1) the two units give the same registration. */
+typedef enum {
+    DIR_UNITS_VOXELS = 0,
+    DIR_UNITS_MM = 1
+} dir_units;
+
+/* Registration parameters.  Set struct_size = sizeof(dir_params) and zero
+ * what is not used (make the struct with = {0}). */
 typedef struct {
     int32_t struct_size;
     int32_t variant;                 /* dir_variant */
     double alpha;                    /* > 0; 1.0 = paper form */
-    double sigma;                    /* Gaussian standard deviation in voxels, > 0 (Sec 2.5: 1 voxel) */
-    int32_t radius;                  /* taps 2R+1 per axis; <= 0 selects ceil(3 sigma); at most DIR_MAX_RADIUS */
+    double sigma;                    /* Gaussian standard deviation in voxels (mm with DIR_UNITS_MM), > 0
+                                        (Sec 2.5: 1 voxel) */
+    int32_t radius;                  /* taps 2R+1 per axis; <= 0 selects ceil(3 sigma) (per axis in mm);
+                                        at most DIR_MAX_RADIUS */
     int32_t levels;                  /* 1..DIR_MAX_LEVELS; level k has ceil(n / 2^k) voxels per axis */
     int32_t iters[DIR_MAX_LEVELS];   /* iterations per level, COARSEST FIRST; each >= 0 */
     double eps;                      /* 0: fixed counts; > 0: stop a level once l(n-10) - l(n) <= eps (Sec 2.4) */
     int32_t compose_iters;           /* fixed-point steps of the IC output composition; < 0 selects 10 */
     int32_t storage;                 /* dir_storage of images and fields inside the registration */
+    int32_t units;                   /* dir_units; DIR_UNITS_MM needs spacing_mm */
+    int32_t reserved;                /* 0 */
+    double image_sigma;              /* > 0: every level's static and moving images (each restricted from the
+                                        unsmoothed finer level) are smoothed with a Gaussian of this width
+                                        (voxels, or mm) and radius ceil(3 width) per axis before the level
+                                        runs (Sec 2.5: the low-pass filter kernel smooths images as well as
+                                        displacements); 0: no pre-smoothing */
 } dir_params;
 
 /* Storage format of the image pyramids, fields and deformed-image buffers
@@ -153,8 +184,9 @@ int32_t dir_set_graphs(dir_handle *h, int32_t enable);
 
 /* Multi-scale demons registration of d_moving onto d_static (Sec 2.1-2.4).
  * d_static, d_moving: nx*ny*nz floats each.  spacing_mm: host array of three
- * voxel sizes (> 0) or NULL; the algorithm works in voxel units as the paper
- * does, so spacing is only validated.  d_field_out: 3*nx*ny*nz floats,
+ * voxel sizes (> 0) or NULL; in voxel units (params->units =
+ * DIR_UNITS_VOXELS, the paper's form) it is only validated, in DIR_UNITS_MM
+ * it is required and sets the physical units.  d_field_out: 3*nx*ny*nz floats,
  * receives v with M(x - v(x)) ~= S(x) for every variant (for
  * DIR_INVERSE_CONSISTENT the composed full field, see dir_compose).
  * Blocks until complete. */
@@ -252,8 +284,9 @@ int32_t dir_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, const dir_params
  * d_field_out[r], their sizes dims[3r], dims[3r+1], dims[3r+2] (nx, ny, nz;
  * they may differ), spacing_mm (NULL, or three values per registration, only
  * validated as in dir_register) and params[r].  The registrations must agree
- * in levels, iterations per level, sigma, radius and storage; size, variant,
- * alpha, eps and compose_iters may differ.
+ * in levels, iterations per level, sigma, radius, storage, units and
+ * image_sigma (and, in DIR_UNITS_MM, spacing); size, variant, alpha, eps and
+ * compose_iters may differ.
  *
  * On a pyramid level whose images and fields, over all `count`
  * registrations, fit the device's 256 MB last-level cache (about 8 stored

@@ -22,6 +22,8 @@ DIR_MAX_LEVELS = 8
 DIR_MAX_RADIUS = 16
 DIR_MAX_BATCH = 8
 DIR_STORE_F32, DIR_STORE_F16, DIR_STORE_BF16 = 0, 1, 2
+DIR_UNITS_VOXELS, DIR_UNITS_MM = 0, 1
+UNITS = {"voxels": DIR_UNITS_VOXELS, "mm": DIR_UNITS_MM}
 STORAGE = {"f32": DIR_STORE_F32, "f16": DIR_STORE_F16, "bf16": DIR_STORE_BF16}
 VARIANTS = {"passive": DIR_PASSIVE, "evolved": DIR_EVOLVED_PASSIVE, "active": DIR_ACTIVE, "double": DIR_DOUBLE,
             "inverse_consistent": DIR_INVERSE_CONSISTENT}
@@ -41,7 +43,8 @@ class dir_params(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("variant", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("sigma", ctypes.c_double), ("radius", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("iters", ctypes.c_int32 * DIR_MAX_LEVELS), ("eps", ctypes.c_double),
-                ("compose_iters", ctypes.c_int32), ("storage", ctypes.c_int32)]
+                ("compose_iters", ctypes.c_int32), ("storage", ctypes.c_int32), ("units", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("image_sigma", ctypes.c_double)]
 
 
 class dir_stats(ctypes.Structure):
@@ -229,8 +232,10 @@ def dir_synchronize(h):
     _check(lib().dir_synchronize(h.ptr), "dir_synchronize")
 
 
-def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_iters=-1, storage="f32"):
-    """dir_params; `iters` lists the levels coarsest first."""
+def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_iters=-1, storage="f32", units="voxels",
+                image_sigma=0.0):
+    """dir_params; `iters` lists the levels coarsest first.  units "mm"
+    (sigma and image_sigma in mm) needs spacing_mm in the registration call."""
     if isinstance(variant, str):
         variant = VARIANTS[variant]
     iters = [int(i) for i in iters]
@@ -248,6 +253,8 @@ def make_params(variant, iters, sigma, radius=0, alpha=1.0, eps=0.0, compose_ite
     p.eps = float(eps)
     p.compose_iters = int(compose_iters)
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.units = UNITS[units] if isinstance(units, str) else int(units)
+    p.image_sigma = float(image_sigma)
     return p
 
 

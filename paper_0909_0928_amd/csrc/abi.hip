@@ -59,12 +59,13 @@ struct DevBuf {
 // Laid out without implicit padding, so keys compare with memcmp.
 struct GraphKey {
     const void *S, *M, *out;
-    const void *ws[12];
+    const void *ws[14];
     dir_params params;
+    double spacing[3];
     int32_t nx, ny, nz, pad;
 };
 static_assert(kMaxBatch == DIR_MAX_BATCH, "batch limit of the ABI and of the kernels");
-static_assert(sizeof(GraphKey) == 15 * sizeof(void *) + sizeof(dir_params) + 16, "GraphKey has padding");
+static_assert(sizeof(GraphKey) == 17 * sizeof(void *) + sizeof(dir_params) + 40, "GraphKey has padding");
 
 // A registration enqueued by dir_register_async (or dir_register) whose
 // statistics have not been collected yet.
@@ -86,6 +87,7 @@ struct dir_handle {
     DevBuf field[3];               // fields, 3 planes each: v and x-smoothed u; scratch for dir_smooth
     DevBuf img_a, img_b;           // pre-warped D (active, double, IC) and P = Im + Is (IC)
     DevBuf img0_s, img0_m;         // finest-level S and M in a 16-bit storage format
+    DevBuf pre_s, pre_m;           // every level of S and M pre-smoothed (image_sigma > 0)
     DevBuf partials;               // 3 doubles per force workgroup
     DevBuf history;                // 4 doubles per iteration, per-level fixed offsets
     DevBuf state;                  // one LevelState per level
@@ -144,11 +146,28 @@ GaussTaps make_taps(double sigma, int radius)
         w[j + radius] = exp(-(double)(j * j) / (2.0 * sigma * sigma));
         sum += w[j + radius];
     }
-    for (int j = 0; j <= 2 * radius; ++j) t.w[j] = (float)(w[j] / sum);
+    for (int j = 0; j <= 2 * radius; ++j) t.w[j] = t.wz[j] = (float)(w[j] / sum);
+    return t;
+}
+
+// Taps of the y/z smoothing kernel for per-axis widths: y's in w, z's in wz,
+// the narrower padded with zero taps to the common radius (a zero tap adds
+// an exact zero, so the sums are those of the narrower stencil).
+GaussTaps make_taps_yz(double sy, int ry, double sz, int rz)
+{
+    const GaussTaps ty = make_taps(sy, ry), tz = make_taps(sz, rz);
+    GaussTaps t;
+    memset(&t, 0, sizeof t);
+    t.radius = std::max(ry, rz);
+    for (int j = -ry; j <= ry; ++j) t.w[j + t.radius] = ty.w[j + ry];
+    for (int j = -rz; j <= rz; ++j) t.wz[j + t.radius] = tz.w[j + rz];
     return t;
 }
 
 Dims coarser(Dims d) { return Dims{(d.nx + 1) / 2, (d.ny + 1) / 2, (d.nz + 1) / 2}; }
+
+// Round a byte count up to a 256-byte boundary.
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 int enter(dir_handle *h)
 {
@@ -325,6 +344,8 @@ int32_t dir_destroy(dir_handle *h)
     h->img_b.release();
     h->img0_s.release();
     h->img0_m.release();
+    h->pre_s.release();
+    h->pre_m.release();
     h->partials.release();
     h->history.release();
     h->state.release();
@@ -489,7 +510,7 @@ GaussTaps identity_taps()
     GaussTaps t;
     memset(&t, 0, sizeof t);
     t.radius = 0;
-    t.w[0] = 1.0f;
+    t.w[0] = t.wz[0] = 1.0f;
     return t;
 }
 
@@ -506,6 +527,7 @@ struct ForceHalf {
     void *out[kMaxBatch];
     double *partials[kMaxBatch];
     const int *stop_at[kMaxBatch];
+    const Metric *metric = nullptr;     // physical units (the level's), or NULL
 };
 
 // The force half of one iteration: one pre-warp launch for the registrations
@@ -558,6 +580,7 @@ hipError_t force_half(Ctx &c, const ForceHalf &b, const GaussTaps &taps, int n)
     }
     f.storage = b.storage;
     f.taps = &taps;
+    f.metric = b.metric;
     f.n = n;
     return launch_force(c, f);
 }
@@ -576,24 +599,94 @@ SumsReduce sums_reduce_one(double *partials, Dims d, double *hist, LevelState *s
     return r;
 }
 
-// dir_force, dir_step and dir_step_stored: one iteration outside a
-// registration, sums out.  With a 16-bit storage format the FP32 inputs are
-// converted first (S, M, v into the workspace) and the result converted back.
-int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, const float *M, const float *v,
-                int32_t nx, int32_t ny, int32_t nz, const GaussTaps *taps, float *out, double *sums,
-                int storage = kStoreF32)
+// Buffers one iteration outside a registration works in: the pre-warped
+// images D and P, the per-workgroup sums, one history entry, the level state
+// and (with taps, or with a 16-bit format) the x-smoothed field u.
+struct StepBufs {
+    void *D = nullptr, *P = nullptr, *u = nullptr;
+    double *partials = nullptr, *history = nullptr;
+    LevelState *st = nullptr;
+};
+
+// Arguments of one iteration outside a registration (dir_force, dir_step,
+// dir_step_stored).
+int check_step_args(int32_t variant, double alpha, const float *S, const float *M, const float *v, int32_t nx,
+                    int32_t ny, int32_t nz, float *out, int storage)
 {
     if (!S || !M || !v || !out || !dims_ok(nx, ny, nz)) return DIR_EINVAL;
     if (variant < kPassive || variant > kInverseConsistent || !(alpha > 0.0) || !isfinite(alpha)) return DIR_EINVAL;
     if (storage < kStoreF32 || storage > kStoreBF16) return DIR_EINVAL;
+    const size_t bytes = sizeof(float) * 3 * (size_t)Dims{nx, ny, nz}.n();
+    const char *vb = reinterpret_cast<const char *>(v), *ob = reinterpret_cast<const char *>(out);
+    if (vb < ob + bytes && ob < vb + bytes) return DIR_EINVAL;  // out must not overlap the field
+    return DIR_OK;
+}
+
+// The kernels of one iteration in FP32 storage on c's stream: force (with the
+// pre-warp its variant needs), then the y/z smoothing and the reduction of the
+// sums into b.history (or, without taps, the force alone and the reduction).
+hipError_t enqueue_step(Ctx &c, const StepBufs &b, int32_t variant, double alpha, const void *S, const void *M,
+                        const void *v, Dims d, const GaussTaps *taps, void *fout, int storage)
+{
+    hipError_t e = launch_level_reset(c, b.st);
+    if (e != hipSuccess) return e;
+    SumsReduce red = sums_reduce_one(b.partials, d, b.history, b.st, 0.0);
+    red.inv_n[0] = 1.0;  // report the plain sum of D^2
+    ForceHalf fh;
+    fh.storage = storage;
+    fh.d[0] = d;
+    fh.variant[0] = variant;
+    fh.alpha2[0] = (float)(alpha * alpha);
+    fh.S[0] = S;
+    fh.M[0] = M;
+    fh.v[0] = v;
+    fh.D[0] = b.D;
+    fh.P[0] = b.P;
+    fh.partials[0] = b.partials;
+    fh.stop_at[0] = nullptr;
+    if (taps) {
+        fh.out[0] = b.u;
+        e = force_half(c, fh, *taps, 0);
+        if (e != hipSuccess) return e;
+        return launch_smooth_yz(c, b.u, 3, d, *taps, fout, storage, nullptr, 0, red);
+    }
+    const GaussTaps id = identity_taps();
+    fh.out[0] = fout;
+    e = force_half(c, fh, id, 0);
+    if (e != hipSuccess) return e;
+    return launch_finalize(c, red, 0);
+}
+
+// Copy the three sums of the history entry to the host (the stream must be
+// complete).
+int read_step_sums(dir_handle *h, const double *history, double *sums)
+{
+    if (!sums) return DIR_OK;
+    double e[4];
+    const int rc = copy_to_host(h, e, history, sizeof e);
+    if (rc != DIR_OK) return rc;
+    sums[0] = e[0];
+    sums[1] = e[1];
+    sums[2] = e[2];  // inv_n = 1: the plain sum of D^2
+    return DIR_OK;
+}
+
+// dir_force, dir_step and dir_step_stored: one iteration outside a
+// registration in the handle's workspace, sums out.  With a 16-bit storage
+// format the FP32 inputs are converted first (S, M, v into the workspace) and
+// the result converted back.
+int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, const float *M, const float *v,
+                int32_t nx, int32_t ny, int32_t nz, const GaussTaps *taps, float *out, double *sums,
+                int storage = kStoreF32)
+{
+    int rc = check_step_args(variant, alpha, S, M, v, nx, ny, nz, out, storage);
+    if (rc != DIR_OK) return rc;
     const Dims d{nx, ny, nz};
     const size_t n = (size_t)d.n();
     const size_t bytes = sizeof(float) * 3 * n;
-    const char *vb = reinterpret_cast<const char *>(v), *ob = reinterpret_cast<const char *>(out);
-    if (vb < ob + bytes && ob < vb + bytes) return DIR_EINVAL;  // out must not overlap the field
     const bool conv = storage != kStoreF32;
     const size_t es = storage_bytes(storage);
-    int rc = ensure_force_workspace(h, d, variant, storage);
+    rc = ensure_force_workspace(h, d, variant, storage);
     if (rc != DIR_OK) return rc;
     DIR_TRY(h->history.ensure(sizeof(double) * 4));
     DIR_TRY(h->state.ensure(sizeof(LevelState)));
@@ -616,44 +709,18 @@ int single_step(dir_handle *h, int32_t variant, double alpha, const float *S, co
         vx = h->field[0].p;
         fout = h->field[1].p;
     }
-    LevelState *st = h->state.as<LevelState>();
-    DIR_TRY(launch_level_reset(c, st));
-    SumsReduce red = sums_reduce_one(h->partials.as<double>(), d, h->history.as<double>(), st, 0.0);
-    red.inv_n[0] = 1.0;  // report the plain sum of D^2
-    ForceHalf fh;
-    fh.storage = storage;
-    fh.d[0] = d;
-    fh.variant[0] = variant;
-    fh.alpha2[0] = (float)(alpha * alpha);
-    fh.S[0] = Sx;
-    fh.M[0] = Mx;
-    fh.v[0] = vx;
-    fh.D[0] = h->img_a.p;
-    fh.P[0] = h->img_b.p;
-    fh.partials[0] = h->partials.as<double>();
-    fh.stop_at[0] = nullptr;
-    if (taps) {
-        fh.out[0] = h->field[2].p;
-        DIR_TRY(force_half(c, fh, *taps, 0));
-        DIR_TRY(launch_smooth_yz(c, h->field[2].p, 3, d, *taps, fout, storage, nullptr, 0, red));
-    } else {
-        const GaussTaps id = identity_taps();
-        fh.out[0] = fout;
-        DIR_TRY(force_half(c, fh, id, 0));
-        DIR_TRY(launch_finalize(c, red, 0));
-    }
+    StepBufs b;
+    b.D = h->img_a.p;
+    b.P = h->img_b.p;
+    b.u = h->field[2].p;
+    b.partials = h->partials.as<double>();
+    b.history = h->history.as<double>();
+    b.st = h->state.as<LevelState>();
+    DIR_TRY(enqueue_step(c, b, variant, alpha, Sx, Mx, vx, d, taps, fout, storage));
     if (conv) DIR_TRY(launch_convert(c, fout, storage, out, kStoreF32, 3 * (int64_t)n));
     rc = finish(h);
     if (rc != DIR_OK) return rc;
-    if (sums) {
-        double e[4];
-        rc = copy_to_host(h, e, h->history.p, sizeof e);
-        if (rc != DIR_OK) return rc;
-        sums[0] = e[0];
-        sums[1] = e[1];
-        sums[2] = e[2];  // inv_n = 1: the plain sum of D^2
-    }
-    return DIR_OK;
+    return read_step_sums(h, b.history, sums);
 }
 
 }  // namespace
@@ -729,8 +796,11 @@ namespace {
 // registration), the history layout and the workspace strides between
 // registrations.
 struct RegSizes {
-    size_t pyr, img0, field, img_a, img_b, partials, history, state;
-    size_t total() const { return 2 * pyr + 2 * img0 + 2 * field + img_a + img_b + partials + history + state; }
+    size_t pyr, img0, pre, field, img_a, img_b, partials, history, state;
+    size_t total() const
+    {
+        return 2 * pyr + 2 * img0 + 2 * pre + 2 * field + img_a + img_b + partials + history + state;
+    }
 };
 
 struct RegPlan {
@@ -742,7 +812,12 @@ struct RegPlan {
     double eps[kMaxBatch];
     Dims dims[kMaxBatch][DIR_MAX_LEVELS];  // level sizes, finest first
     int storage, L;
-    GaussTaps taps;
+    GaussTaps taps, taps_yz;           // field smoothing: x pass (force kernel), y and z passes
+    bool mm;                           // physical units (DIR_UNITS_MM)
+    double h[3];                       // voxel sizes of the input grid, mm (1 in voxel units)
+    Metric metric[DIR_MAX_LEVELS];     // physical units, per level (finest first)
+    bool presmooth;                    // image_sigma > 0
+    GaussTaps img_x, img_yz;           // the images' pre-smoothing Gaussian
     int iters[DIR_MAX_LEVELS];
     int64_t total_iters;
     int64_t hist_off[DIR_MAX_LEVELS];
@@ -761,8 +836,15 @@ int check_register_params(int32_t nx, int32_t ny, int32_t nz, const dir_params *
     if (p->levels < 1 || p->levels > DIR_MAX_LEVELS) return DIR_EINVAL;
     for (int l = 0; l < p->levels; ++l)
         if (p->iters[l] < 0) return DIR_EINVAL;
-    const int R = resolve_radius(p->sigma, p->radius);
-    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+    if (p->units != DIR_UNITS_VOXELS && p->units != DIR_UNITS_MM) return DIR_EINVAL;
+    if (!(p->image_sigma >= 0.0) || !isfinite(p->image_sigma)) return DIR_EINVAL;
+    if (p->units == DIR_UNITS_VOXELS) {  // in mm the radii depend on the spacing (checked with it)
+        const int R = resolve_radius(p->sigma, p->radius);
+        if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+        if (p->image_sigma > 0.0 && resolve_radius(p->image_sigma, 0) > DIR_MAX_RADIUS) return DIR_EINVAL;
+    } else if (p->radius > DIR_MAX_RADIUS) {
+        return DIR_EINVAL;
+    }
     return DIR_OK;
 }
 
@@ -787,6 +869,7 @@ RegSizes register_sizes(int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
     const bool pre = p->variant == kActive || p->variant == kDouble || p->variant == kInverseConsistent;
     z.pyr = L > 1 ? es * pyr : 0;                     // S and M, levels 1..
     z.img0 = p->storage != kStoreF32 ? es * n0 : 0;   // S and M, finest level, 16-bit copies
+    z.pre = p->image_sigma > 0.0 ? es * (n0 + pyr) : 0;  // S and M pre-smoothed, every level
     z.field = es * 3 * n0;                            // v and the x-smoothed u
     z.img_a = pre ? es * n0 : 0;                      // D
     z.img_b = p->variant == kInverseConsistent ? sizeof(float) * n0 : 0;  // P, FP32
@@ -795,9 +878,6 @@ RegSizes register_sizes(int32_t nx, int32_t ny, int32_t nz, const dir_params *p)
     z.state = sizeof(LevelState) * DIR_MAX_LEVELS;
     return z;
 }
-
-// Round a per-registration byte count up to a 256-byte boundary.
-size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Workspace strides of a batch (validated parameters): per buffer, the
 // largest registration's size rounded up to 256 bytes.
@@ -808,6 +888,7 @@ RegSizes batch_strides(int count, const int32_t *dims, const dir_params *p)
         const RegSizes zr = register_sizes(dims[3 * r], dims[3 * r + 1], dims[3 * r + 2], &p[r]);
         z.pyr = std::max(z.pyr, align256(zr.pyr));
         z.img0 = std::max(z.img0, align256(zr.img0));
+        z.pre = std::max(z.pre, align256(zr.pre));
         z.field = std::max(z.field, align256(zr.field));
         z.img_a = std::max(z.img_a, align256(zr.img_a));
         z.img_b = std::max(z.img_b, align256(zr.img_b));
@@ -825,7 +906,8 @@ namespace dir {
 size_t workspace_now(const dir_handle *h)
 {
     size_t b = h->pyr_s.bytes + h->pyr_m.bytes + h->img_a.bytes + h->img_b.bytes + h->img0_s.bytes +
-               h->img0_m.bytes + h->partials.bytes + h->history.bytes + h->state.bytes;
+               h->img0_m.bytes + h->pre_s.bytes + h->pre_m.bytes + h->partials.bytes + h->history.bytes +
+               h->state.bytes;
     for (const auto &f : h->field) b += f.bytes;
     return b;
 }
@@ -835,9 +917,10 @@ size_t workspace_after(const dir_handle *h, int32_t nx, int32_t ny, int32_t nz, 
     const RegSizes z = register_sizes(nx, ny, nz, p);
     auto mx = [](size_t a, size_t b) { return a > b ? a : b; };
     return mx(h->pyr_s.bytes, z.pyr) + mx(h->pyr_m.bytes, z.pyr) + mx(h->img0_s.bytes, z.img0) +
-           mx(h->img0_m.bytes, z.img0) + mx(h->field[0].bytes, z.field) + mx(h->field[1].bytes, z.field) +
-           h->field[2].bytes + mx(h->img_a.bytes, z.img_a) + mx(h->img_b.bytes, z.img_b) +
-           mx(h->partials.bytes, z.partials) + mx(h->history.bytes, z.history) + mx(h->state.bytes, z.state);
+           mx(h->img0_m.bytes, z.img0) + mx(h->pre_s.bytes, z.pre) + mx(h->pre_m.bytes, z.pre) +
+           mx(h->field[0].bytes, z.field) + mx(h->field[1].bytes, z.field) + h->field[2].bytes +
+           mx(h->img_a.bytes, z.img_a) + mx(h->img_b.bytes, z.img_b) + mx(h->partials.bytes, z.partials) +
+           mx(h->history.bytes, z.history) + mx(h->state.bytes, z.state);
 }
 
 size_t workspace_after_batch(const dir_handle *h, int32_t count, const int32_t *dims, const dir_params *p)
@@ -846,9 +929,10 @@ size_t workspace_after_batch(const dir_handle *h, int32_t count, const int32_t *
     const size_t c = (size_t)count;
     auto mx = [c](size_t a, size_t b) { return a > c * b ? a : c * b; };
     return mx(h->pyr_s.bytes, z.pyr) + mx(h->pyr_m.bytes, z.pyr) + mx(h->img0_s.bytes, z.img0) +
-           mx(h->img0_m.bytes, z.img0) + mx(h->field[0].bytes, z.field) + mx(h->field[1].bytes, z.field) +
-           h->field[2].bytes + mx(h->img_a.bytes, z.img_a) + mx(h->img_b.bytes, z.img_b) +
-           mx(h->partials.bytes, z.partials) + mx(h->history.bytes, z.history) + mx(h->state.bytes, z.state);
+           mx(h->img0_m.bytes, z.img0) + mx(h->pre_s.bytes, z.pre) + mx(h->pre_m.bytes, z.pre) +
+           mx(h->field[0].bytes, z.field) + mx(h->field[1].bytes, z.field) + h->field[2].bytes +
+           mx(h->img_a.bytes, z.img_a) + mx(h->img_b.bytes, z.img_b) + mx(h->partials.bytes, z.partials) +
+           mx(h->history.bytes, z.history) + mx(h->state.bytes, z.state);
 }
 
 void workspace_release(dir_handle *h)
@@ -860,6 +944,8 @@ void workspace_release(dir_handle *h)
     h->img_b.release();
     h->img0_s.release();
     h->img0_m.release();
+    h->pre_s.release();
+    h->pre_m.release();
     h->partials.release();
     h->history.release();
     h->state.release();
@@ -896,12 +982,45 @@ void plan_entry(RegPlan &pl, int r, const float *S, const float *M, float *out, 
     pl.eps[r] = p->eps;
 }
 
-// The parts of a plan every registration of a batch shares (from p).
-void plan_shared(RegPlan &pl, const dir_params *p)
+// The parts of a plan every registration of a batch shares (from p and the
+// voxel sizes `spacing`, NULL in voxel units): the Gaussians of the field and
+// of the images' pre-smoothing per axis, and in physical units the metric of
+// every level.  DIR_EINVAL for a radius beyond DIR_MAX_RADIUS.
+int plan_shared(RegPlan &pl, const dir_params *p, const double *spacing)
 {
     pl.storage = p->storage;
     pl.L = p->levels;
-    pl.taps = make_taps(p->sigma, resolve_radius(p->sigma, p->radius));
+    pl.mm = p->units == DIR_UNITS_MM;
+    if (pl.mm && !spacing) return DIR_EINVAL;
+    double sv[3], si[3];
+    int rv[3], ri[3];
+    for (int a = 0; a < 3; ++a) {
+        pl.h[a] = pl.mm ? spacing[a] : 1.0;
+        sv[a] = p->sigma / pl.h[a];
+        rv[a] = resolve_radius(sv[a], p->radius);
+        si[a] = p->image_sigma / pl.h[a];
+        ri[a] = p->image_sigma > 0.0 ? resolve_radius(si[a], 0) : 0;
+        if (rv[a] > DIR_MAX_RADIUS || ri[a] > DIR_MAX_RADIUS) return DIR_EINVAL;
+    }
+    pl.taps = make_taps(sv[0], rv[0]);
+    pl.taps_yz = pl.mm ? make_taps_yz(sv[1], rv[1], sv[2], rv[2]) : pl.taps;
+    pl.presmooth = p->image_sigma > 0.0;
+    if (pl.presmooth) {
+        pl.img_x = make_taps(si[0], ri[0]);
+        pl.img_yz = make_taps_yz(si[1], ri[1], si[2], ri[2]);
+    }
+    if (pl.mm) {
+        // s_a = sqrt(K) / h_a with K the mean squared voxel size; norms in mm
+        // with the level's voxel sizes 2^k h_a
+        const double K = (pl.h[0] * pl.h[0] + pl.h[1] * pl.h[1] + pl.h[2] * pl.h[2]) / 3.0;
+        for (int k = 0; k < pl.L; ++k)
+            for (int a = 0; a < 3; ++a) {
+                const double sa = sqrt(K) / pl.h[a], hk = ldexp(pl.h[a], k);
+                pl.metric[k].gs[a] = (float)(0.5 * sa);
+                pl.metric[k].os[a] = (float)sa;
+                pl.metric[k].nw[a] = (float)(hk * hk);
+            }
+    }
     int64_t off = 0;
     for (int k = 0; k < pl.L; ++k) {
         pl.iters[k] = p->iters[k];  // coarsest first
@@ -909,6 +1028,7 @@ void plan_shared(RegPlan &pl, const dir_params *p)
         off += p->iters[k];
     }
     pl.total_iters = off;
+    return DIR_OK;
 }
 
 // Whether two float ranges of na and nb elements share memory.
@@ -946,6 +1066,8 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     if (rc != DIR_OK) return rc;
     if (!spacing_ok(spacing_mm)) return DIR_EINVAL;
     if (!disjoint_io(d_static, d_moving, d_field_out, (size_t)((int64_t)nx * ny * nz))) return DIR_EINVAL;
+    rc = plan_shared(pl, p, spacing_mm);
+    if (rc != DIR_OK) return rc;
 
     const RegSizes z = register_sizes(nx, ny, nz, p);
     if (z.pyr) {
@@ -956,6 +1078,10 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
         DIR_TRY(h->img0_s.ensure(z.img0));
         DIR_TRY(h->img0_m.ensure(z.img0));
     }
+    if (z.pre) {
+        DIR_TRY(h->pre_s.ensure(z.pre));
+        DIR_TRY(h->pre_m.ensure(z.pre));
+    }
     DIR_TRY(h->field[0].ensure(z.field));
     DIR_TRY(h->field[1].ensure(z.field));
     if (z.img_a) DIR_TRY(h->img_a.ensure(z.img_a));
@@ -965,7 +1091,6 @@ int plan_register(dir_handle *h, const float *d_static, const float *d_moving, i
     DIR_TRY(h->state.ensure(z.state));
 
     pl.count = 1;
-    plan_shared(pl, p);
     plan_entry(pl, 0, d_static, d_moving, d_field_out, Dims{nx, ny, nz}, p);
     pl.stride = z;
     return DIR_OK;
@@ -989,8 +1114,15 @@ int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float 
         if (rc != DIR_OK) return rc;
         if (spacing_mm && !spacing_ok(spacing_mm + 3 * r)) return DIR_EINVAL;
         if (p[r].levels != p[0].levels || p[r].sigma != p[0].sigma || p[r].storage != p[0].storage ||
-            resolve_radius(p[r].sigma, p[r].radius) != resolve_radius(p[0].sigma, p[0].radius))
+            p[r].units != p[0].units || p[r].image_sigma != p[0].image_sigma)
             return DIR_EINVAL;
+        if (p[0].units == DIR_UNITS_VOXELS ? resolve_radius(p[r].sigma, p[r].radius) !=
+                                                 resolve_radius(p[0].sigma, p[0].radius)
+                                           : p[r].radius != p[0].radius)
+            return DIR_EINVAL;
+        if (p[0].units == DIR_UNITS_MM &&
+            (!spacing_mm || memcmp(spacing_mm + 3 * r, spacing_mm, 3 * sizeof(double)) != 0))
+            return DIR_EINVAL;  // one metric and one Gaussian per launch
         for (int l = 0; l < p[0].levels; ++l)
             if (p[r].iters[l] != p[0].iters[l]) return DIR_EINVAL;
         n[r] = (size_t)((int64_t)nx * ny * nz);
@@ -1002,6 +1134,8 @@ int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float 
                 return DIR_EINVAL;
         }
     }
+    const int prc = plan_shared(pl, &p[0], spacing_mm);
+    if (prc != DIR_OK) return prc;
     const RegSizes z = batch_strides(count, dims, p);
     const size_t c = (size_t)count;
     if (z.pyr) {
@@ -1012,6 +1146,10 @@ int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float 
         DIR_TRY(h->img0_s.ensure(c * z.img0));
         DIR_TRY(h->img0_m.ensure(c * z.img0));
     }
+    if (z.pre) {
+        DIR_TRY(h->pre_s.ensure(c * z.pre));
+        DIR_TRY(h->pre_m.ensure(c * z.pre));
+    }
     DIR_TRY(h->field[0].ensure(c * z.field));
     DIR_TRY(h->field[1].ensure(c * z.field));
     if (z.img_a) DIR_TRY(h->img_a.ensure(c * z.img_a));
@@ -1021,7 +1159,6 @@ int plan_batch(dir_handle *h, int32_t count, const float *const *S, const float 
     DIR_TRY(h->state.ensure(c * z.state));
 
     pl.count = count;
-    plan_shared(pl, &p[0]);
     for (int r = 0; r < count; ++r)
         plan_entry(pl, r, S[r], M[r], out[r], Dims{dims[3 * r], dims[3 * r + 1], dims[3 * r + 2]}, &p[r]);
     pl.stride = z;
@@ -1115,6 +1252,7 @@ ForceHalf one_of(const ForceHalf &b, int r)
     o.out[0] = b.out[r];
     o.partials[0] = b.partials[r];
     o.stop_at[0] = b.stop_at[r];
+    o.metric = b.metric;
     return o;
 }
 
@@ -1141,7 +1279,7 @@ SumsReduce one_of(const SumsReduce &b, int r)
 int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
 {
     const int L = pl.L, st_fmt = pl.storage, B = pl.count;
-    const GaussTaps &taps = pl.taps;
+    const GaussTaps &taps = pl.taps, &taps_yz = pl.taps_yz;
     const RegSizes &zs = pl.stride;
     const size_t es = storage_bytes(st_fmt);
     const bool f32 = st_fmt == kStoreF32;
@@ -1189,6 +1327,49 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
     {
         int rc = pyramid(pl.S, Sk, h->pyr_s, h->img0_s);
         if (rc == DIR_OK) rc = pyramid(pl.M, Mk, h->pyr_m, h->img0_m);
+        if (rc != DIR_OK) return rc;
+    }
+
+    // ---- optional pre-smoothing of every level's images (Sec 2.5 low-pass
+    // filter on images): from the unsmoothed level into pre_buf's part r, in
+    // the storage format; the fields' buffers serve as FP32 scratch (they
+    // are set up after this).  Shared images are smoothed once.
+    auto presmooth = [&](const float *const *img, const void *(*pyr)[DIR_MAX_LEVELS], const DevBuf &pre_buf) -> int {
+        const void *done[kMaxBatch][DIR_MAX_LEVELS];
+        for (int r = 0; r < B; ++r) {
+            int same = -1;
+            for (int q = 0; q < r && same < 0; ++q)
+                if (img[q] == img[r] && pl.dims[q][0].nx == pl.dims[r][0].nx &&
+                    pl.dims[q][0].ny == pl.dims[r][0].ny && pl.dims[q][0].nz == pl.dims[r][0].nz)
+                    same = q;
+            if (same >= 0) {
+                for (int k = 0; k < L; ++k) done[r][k] = pyr[r][k] = done[same][k];
+                continue;
+            }
+            float *ta = part<float>(h->field[0], zs.field, r), *tb = part<float>(h->field[1], zs.field, r);
+            size_t off = 0;
+            for (int k = 0; k < L; ++k) {
+                const Dims d = pl.dims[r][k];
+                h->timer.level = k;
+                char *dst = part<char>(pre_buf, zs.pre, r) + es * off;
+                off += (size_t)d.n();
+                if (f32) {
+                    DIR_TRY(launch_smooth_x(c, static_cast<const float *>(pyr[r][k]), 1, d, pl.img_x, ta));
+                    DIR_TRY(launch_smooth_yz(c, ta, 1, d, pl.img_yz, dst, kStoreF32, nullptr, 0, SumsReduce{}));
+                } else {
+                    DIR_TRY(launch_convert(c, pyr[r][k], st_fmt, ta, kStoreF32, d.n()));
+                    DIR_TRY(launch_smooth_x(c, ta, 1, d, pl.img_x, tb));
+                    DIR_TRY(launch_smooth_yz(c, tb, 1, d, pl.img_yz, ta, kStoreF32, nullptr, 0, SumsReduce{}));
+                    DIR_TRY(launch_convert(c, ta, kStoreF32, dst, st_fmt, d.n()));
+                }
+                done[r][k] = pyr[r][k] = dst;
+            }
+        }
+        return DIR_OK;
+    };
+    if (pl.presmooth) {
+        int rc = presmooth(pl.S, Sk, h->pre_s);
+        if (rc == DIR_OK) rc = presmooth(pl.M, Mk, h->pre_m);
         if (rc != DIR_OK) return rc;
     }
 
@@ -1246,6 +1427,7 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
         fh.M[r] = Mk[r][k];
         fh.v[r] = v[r];
         fh.out[r] = xs[r];
+        fh.metric = pl.mm ? &pl.metric[k] : nullptr;
         return DIR_OK;
     };
     // The iterations of level k on cr for the registrations of `f` and `rd`
@@ -1257,7 +1439,7 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
             // v -> xs = x-smoothed (v + dr) -> v = y,z-smoothed xs; the
             // smoothing kernel also reduces the sums of this iteration
             DIR_TRY(force_half(cr, f, taps, n));
-            DIR_TRY(launch_smooth_yz(cr, f.count, xsv, 3, f.d, taps, vv, st_fmt, f.stop_at, n, rd));
+            DIR_TRY(launch_smooth_yz(cr, f.count, xsv, 3, f.d, taps_yz, vv, st_fmt, f.stop_at, n, rd));
             if (poll && B == 1 && pl.eps[0] > 0.0 && (n + 1) % 10 == 0 && n + 1 < iters) {
                 int stop_at = kNeverStopped;
                 DIR_TRY(hipMemcpyAsync(&stop_at, &states[0][li].stop_at, sizeof(int), hipMemcpyDeviceToHost,
@@ -1328,9 +1510,11 @@ GraphKey graph_key(dir_handle *h, const RegPlan &pl, const dir_params *p)
     k.ny = pl.dims[0][0].ny;
     k.nz = pl.dims[0][0].nz;
     memcpy(&k.params, p, sizeof k.params);
-    const DevBuf *bufs[12] = {&h->pyr_s, &h->pyr_m,  &h->field[0], &h->field[1], &h->field[2],  &h->img_a,
-                              &h->img_b, &h->img0_s, &h->img0_m,   &h->partials, &h->history, &h->state};
-    for (int i = 0; i < 12; ++i) k.ws[i] = bufs[i]->p;
+    for (int a = 0; a < 3; ++a) k.spacing[a] = pl.h[a];
+    const DevBuf *bufs[14] = {&h->pyr_s,  &h->pyr_m,  &h->field[0], &h->field[1], &h->field[2],
+                              &h->img_a,  &h->img_b,  &h->img0_s,   &h->img0_m,   &h->pre_s,
+                              &h->pre_m,  &h->partials, &h->history, &h->state};
+    for (int i = 0; i < 14; ++i) k.ws[i] = bufs[i]->p;
     return k;
 }
 

@@ -53,9 +53,25 @@ struct Dims {
 };
 
 // Normalised Gaussian taps w[j + radius], j in [-radius, radius], in FP32.
+// wz: the taps of the z pass in the y/z smoothing kernel (equal to w for an
+// isotropic Gaussian; for per-axis widths, w holds y's and wz z's, the
+// shorter one padded with zero taps to the common radius).
 struct GaussTaps {
     float w[2 * kMaxRadius + 1];
+    float wz[2 * kMaxRadius + 1];
     int radius;
+};
+
+// The force in physical units, written on the voxel grid.  With voxel sizes
+// h_a (mm) of the input grid and K = (h_x^2 + h_y^2 + h_z^2) / 3, the force in
+// mm (gradients per mm, the squared intensity difference over K) converts to
+// voxel units as dr_a = s_a f(D, s * g)_a with s_a = sqrt(K) / h_a, the same on
+// every level (both K and h_a^2 scale by 4 per level); g is the voxel central
+// difference.  The kernels therefore take gs[a] = s_a / 2 in place of the 1/2
+// of the central difference, scale the force component a by s_a, and weight
+// the norms behind the relative norm by nw[a] = h_a^2 of the level (mm^2).
+struct Metric {
+    float gs[3], os[3], nw[3];
 };
 
 constexpr int kNeverStopped = 0x7fffffff;
@@ -135,6 +151,7 @@ struct ForceLaunch {
     const void *D[kMaxBatch], *P[kMaxBatch];  // from the pre-warp: D (active, double, IC), P = Im + Is (IC)
     Dims d[kMaxBatch];
     const GaussTaps *taps;
+    const Metric *metric = nullptr;  // NULL: voxel units (the paper's form); else physical units
     void *out[kMaxBatch];
     double *partials[kMaxBatch];     // 3 * force_blocks(d) doubles each
     const int *stop_at[kMaxBatch];   // skip when *stop_at < n (NULL: never)

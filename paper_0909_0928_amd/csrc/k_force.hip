@@ -50,6 +50,7 @@ struct ForceArgs {
     int first[kMaxBatch + 1];       // logical workgroups of registration r: first[r] .. first[r + 1] - 1
     int count;
     int n;                          // iteration index within the level
+    Metric metric;                  // physical units (instances with MM = true only)
 };
 
 // Byte offsets of one wave-uniform row (y, z) and of its stencil neighbour
@@ -63,14 +64,15 @@ struct LaneOffsets {
     unsigned c, xm, xp;          // x, x - 1, x + 1 (clamped)
 };
 
-// Central difference (Sec 2.5 gradient kernel) from a buffer.
-template <class St>
-__device__ __forceinline__ void cdiff(__amdgpu_buffer_rsrc_t I, const LaneOffsets &lo, const RowOffsets &ro, float &gx,
-                                      float &gy, float &gz)
+// Central difference (Sec 2.5 gradient kernel) from a buffer; in physical
+// units (MM) each component is scaled by s_a as well (gs = s / 2).
+template <class St, bool MM>
+__device__ __forceinline__ void cdiff(__amdgpu_buffer_rsrc_t I, const LaneOffsets &lo, const RowOffsets &ro,
+                                      const Metric &m, float &gx, float &gy, float &gz)
 {
-    gx = 0.5f * (St::load(I, lo.xp, ro.c) - St::load(I, lo.xm, ro.c));
-    gy = 0.5f * (St::load(I, lo.c, ro.yp) - St::load(I, lo.c, ro.ym));
-    gz = 0.5f * (St::load(I, lo.c, ro.zp) - St::load(I, lo.c, ro.zm));
+    gx = (MM ? m.gs[0] : 0.5f) * (St::load(I, lo.xp, ro.c) - St::load(I, lo.xm, ro.c));
+    gy = (MM ? m.gs[1] : 0.5f) * (St::load(I, lo.c, ro.yp) - St::load(I, lo.c, ro.ym));
+    gz = (MM ? m.gs[2] : 0.5f) * (St::load(I, lo.c, ro.zp) - St::load(I, lo.c, ro.zm));
 }
 
 // Hardware square root and reciprocal (about 1 ulp): the force's parity
@@ -106,11 +108,13 @@ struct Bufs {
     __amdgpu_buffer_rsrc_t S, M, v, Dd, P, out;
 };
 
-// u = v + dr at voxel (x, y, z) and its contributions |dr|, |v|, D^2.
-template <int V, class St>
+// u = v + dr at voxel (x, y, z) and its contributions |dr|, |v|, D^2.  MM:
+// the force in physical units on the voxel grid (see Metric): gradients
+// scaled by s, the force component a by s_a, and the norms in mm.
+template <int V, class St, bool MM>
 __device__ __forceinline__ void force_point(const Geo &q, float alpha2, const Bufs &b, int x, int y, int z,
-                                            const RowOffsets &ro, unsigned nbytes, float &u0, float &u1, float &u2,
-                                            double &adr, double &av, double &d2)
+                                            const RowOffsets &ro, unsigned nbytes, const Metric &m, float &u0,
+                                            float &u1, float &u2, double &adr, double &av, double &d2)
 {
     const int nx = q.nx, ny = q.ny, nz = q.nz;
     constexpr unsigned ES = St::kBytes;
@@ -137,16 +141,16 @@ __device__ __forceinline__ void force_point(const Geo &q, float alpha2, const Bu
         const LaneOffsets l4{K4 * lo.c, K4 * lo.xm, K4 * lo.xp};
         const RowOffsets r4{K4 * ro.c, K4 * ro.ym, K4 * ro.yp, K4 * ro.zm, K4 * ro.zp};
         float gx, gy, gz;
-        cdiff<StF32>(b.P, l4, r4, gx, gy, gz);
+        cdiff<StF32, MM>(b.P, l4, r4, m, gx, gy, gz);
         dterm(D, gx, gy, gz, alpha2, fx, fy, fz);
     } else {
         float sx, sy, sz;
-        cdiff<St>(b.S, lo, ro, sx, sy, sz);
+        cdiff<St, MM>(b.S, lo, ro, m, sx, sy, sz);
         if (V == kPassive || V == kDouble) dterm(D, sx, sy, sz, alpha2, fx, fy, fz);  // Eq 1
         if (V == kActive || V == kDouble) {                                             // Eq 3
             // grad Im = grad (Im - S) + grad S
             float dx, dy, dz, bx, by, bz;
-            cdiff<St>(b.Dd, lo, ro, dx, dy, dz);
+            cdiff<St, MM>(b.Dd, lo, ro, m, dx, dy, dz);
             dterm(D, dx + sx, dy + sy, dz + sz, alpha2, bx, by, bz);
             fx += bx;
             fy += by;
@@ -154,15 +158,25 @@ __device__ __forceinline__ void force_point(const Geo &q, float alpha2, const Bu
         }
         if (V == kEvolved) {                                                            // Eq 2
             float mx, my, mz;
-            cdiff<St>(b.M, lo, ro, mx, my, mz);
+            cdiff<St, MM>(b.M, lo, ro, m, mx, my, mz);
             eterm(D, sx, sy, sz, fast_sqrt(fmaf(mx, mx, fmaf(my, my, mz * mz))), fx, fy, fz);
         }
+    }
+    if (MM) {
+        fx *= m.os[0];
+        fy *= m.os[1];
+        fz *= m.os[2];
     }
     u0 = vx + fx;
     u1 = vy + fy;
     u2 = vz + fz;
-    adr = (double)fast_sqrt(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
-    av = (double)fast_sqrt(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    if (MM) {
+        adr = (double)fast_sqrt(fmaf(m.nw[0] * fx, fx, fmaf(m.nw[1] * fy, fy, m.nw[2] * fz * fz)));
+        av = (double)fast_sqrt(fmaf(m.nw[0] * vx, vx, fmaf(m.nw[1] * vy, vy, m.nw[2] * vz * vz)));
+    } else {
+        adr = (double)fast_sqrt(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+        av = (double)fast_sqrt(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    }
     d2 = D64 * D64;
 }
 
@@ -178,7 +192,7 @@ struct ForceTile {
 // RC >= 0: the smoothing radius is RC, known at compile time (taps from the
 // kernel arguments, LDS reads issued together); RC < 0: taps.radius, taps
 // from LDS.  St: storage format of every volume the kernel reads and writes.
-template <int V, int TX, int RC, class St>
+template <int V, int TX, int RC, class St, bool MM>
 __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &taps, int reg, int lid,
                                            typename ForceTile<TX>::Rows &ul, const float *wl)
 {
@@ -225,7 +239,7 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
                 const int xx = x0 - R + p;  // in [0, nx)
                 float u0, u1, u2;
                 double adr, av, d2;
-                force_point<V, St>(q, alpha2, b, xx, y, z, ro, nbytes, u0, u1, u2, adr, av, d2);
+                force_point<V, St, MM>(q, alpha2, b, xx, y, z, ro, nbytes, a.metric, u0, u1, u2, adr, av, d2);
                 ul[0][wrow][p] = u0;
                 ul[1][wrow][p] = u1;
                 ul[2][wrow][p] = u2;
@@ -288,7 +302,7 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
 // One workgroup of a force launch.  Logical workgroup ids (XCD-contiguous)
 // run registration by registration (first[]); V = kMixedVariants takes each
 // registration's variant from the arguments (a uniform branch per workgroup).
-template <int V, int TX, int RC, class St>
+template <int V, int TX, int RC, class St, bool MM>
 __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
 {
     __shared__ typename ForceTile<TX>::Rows ul;
@@ -300,14 +314,14 @@ __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
     if (a.stop_at[reg] && *a.stop_at[reg] < a.n) return;
     if (threadIdx.x <= 2 * kMaxRadius) wl[threadIdx.x] = taps.w[threadIdx.x];  // ordered before use by the row barrier
     if constexpr (V != kMixedVariants) {
-        force_rows<V, TX, RC, St>(a, taps, reg, lid, ul, wl);
+        force_rows<V, TX, RC, St, MM>(a, taps, reg, lid, ul, wl);
     } else {
         switch (a.variant[reg]) {
-        case kPassive: force_rows<kPassive, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
-        case kEvolved: force_rows<kEvolved, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
-        case kActive: force_rows<kActive, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
-        case kDouble: force_rows<kDouble, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
-        default: force_rows<kInverseConsistent, TX, RC, St>(a, taps, reg, lid, ul, wl); break;
+        case kPassive: force_rows<kPassive, TX, RC, St, MM>(a, taps, reg, lid, ul, wl); break;
+        case kEvolved: force_rows<kEvolved, TX, RC, St, MM>(a, taps, reg, lid, ul, wl); break;
+        case kActive: force_rows<kActive, TX, RC, St, MM>(a, taps, reg, lid, ul, wl); break;
+        case kDouble: force_rows<kDouble, TX, RC, St, MM>(a, taps, reg, lid, ul, wl); break;
+        default: force_rows<kInverseConsistent, TX, RC, St, MM>(a, taps, reg, lid, ul, wl); break;
         }
     }
 }
@@ -360,22 +374,26 @@ ForceGrid force_grid(Dims d)
     return g;
 }
 
-template <int V, int RC, class St>
+template <int V, int RC, class St, bool MM = false>
 void launch_force_vr(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
 {
     const dim3 grid((unsigned)g.blocks), block(256);
-    if (g.tx == 64) go(c, ev, (k_force_x<V, 64, RC, St>), grid, block, a, taps);
-    else if (g.tx == 128) go(c, ev, (k_force_x<V, 128, RC, St>), grid, block, a, taps);
-    else if (g.tx == 256) go(c, ev, (k_force_x<V, 256, RC, St>), grid, block, a, taps);
-    else go(c, ev, (k_force_x<V, 512, RC, St>), grid, block, a, taps);
+    if (g.tx == 64) go(c, ev, (k_force_x<V, 64, RC, St, MM>), grid, block, a, taps);
+    else if (g.tx == 128) go(c, ev, (k_force_x<V, 128, RC, St, MM>), grid, block, a, taps);
+    else if (g.tx == 256) go(c, ev, (k_force_x<V, 256, RC, St, MM>), grid, block, a, taps);
+    else go(c, ev, (k_force_x<V, 512, RC, St, MM>), grid, block, a, taps);
 }
 
 // Radii with their own kernels: 0 (the force alone, FP32 only), and
 // ceil(3 sigma) for sigma = 1 and 1.5 voxels; others take the runtime-radius
-// kernel.
+// kernel, and so does every force in physical units (mm).
 template <int V, class St>
-void launch_force_vs(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps)
+void launch_force_vs(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps, bool mm)
 {
+    if (mm) {
+        launch_force_vr<V, -1, St, true>(c, ev, g, a, taps);
+        return;
+    }
     switch (taps.radius) {
     case 0:
         if constexpr (St::kBytes == 4) launch_force_vr<V, 0, St>(c, ev, g, a, taps);
@@ -388,11 +406,12 @@ void launch_force_vs(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &
 }
 
 template <int V>
-void launch_force_v(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps, int storage)
+void launch_force_v(Ctx &c, const Ev &ev, const ForceGrid &g, const ForceArgs &a, const GaussTaps &taps, int storage,
+                    bool mm)
 {
-    if (storage == kStoreF16) launch_force_vs<V, StF16>(c, ev, g, a, taps);
-    else if (storage == kStoreBF16) launch_force_vs<V, StBF16>(c, ev, g, a, taps);
-    else launch_force_vs<V, StF32>(c, ev, g, a, taps);
+    if (storage == kStoreF16) launch_force_vs<V, StF16>(c, ev, g, a, taps, mm);
+    else if (storage == kStoreBF16) launch_force_vs<V, StBF16>(c, ev, g, a, taps, mm);
+    else launch_force_vs<V, StF32>(c, ev, g, a, taps, mm);
 }
 
 // One launch for the registrations `sel[0 .. k-1]` of f, which share a tile
@@ -423,16 +442,18 @@ hipError_t launch_force_group(Ctx &c, const ForceLaunch &f, const ForceGrid *g, 
     a.first[k] = (int)total;
     a.count = k;
     a.n = f.n;
+    const bool mm = f.metric != nullptr;
+    if (mm) a.metric = *f.metric;
     ForceGrid gl = g[sel[0]];
     gl.blocks = total;  // the launch: every registration's workgroups
     return timed(c, K_FORCE, [&](const Ev &ev) {
         switch (variant) {
-        case kPassive: launch_force_v<kPassive>(c, ev, gl, a, *f.taps, f.storage); break;
-        case kEvolved: launch_force_v<kEvolved>(c, ev, gl, a, *f.taps, f.storage); break;
-        case kActive: launch_force_v<kActive>(c, ev, gl, a, *f.taps, f.storage); break;
-        case kDouble: launch_force_v<kDouble>(c, ev, gl, a, *f.taps, f.storage); break;
-        case kInverseConsistent: launch_force_v<kInverseConsistent>(c, ev, gl, a, *f.taps, f.storage); break;
-        default: launch_force_v<kMixedVariants>(c, ev, gl, a, *f.taps, f.storage); break;
+        case kPassive: launch_force_v<kPassive>(c, ev, gl, a, *f.taps, f.storage, mm); break;
+        case kEvolved: launch_force_v<kEvolved>(c, ev, gl, a, *f.taps, f.storage, mm); break;
+        case kActive: launch_force_v<kActive>(c, ev, gl, a, *f.taps, f.storage, mm); break;
+        case kDouble: launch_force_v<kDouble>(c, ev, gl, a, *f.taps, f.storage, mm); break;
+        case kInverseConsistent: launch_force_v<kInverseConsistent>(c, ev, gl, a, *f.taps, f.storage, mm); break;
+        default: launch_force_v<kMixedVariants>(c, ev, gl, a, *f.taps, f.storage, mm); break;
         }
     });
 }

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_smooth_x(const float *__restrict__ in, 
 }
 
 // z then y within one workgroup: tile of 64 (x) x kTileY (y) x TZ (z) of one
-// field component.  Phase 1: every thread slides a register window of
+// field component, z taps taps.wz, y taps taps.w.  Phase 1: every thread slides a register window of
 // TZ + 2R samples along z for one (x, y) column of the tile plus its y halo
 // (rows clamped) and writes the TZ z-smoothed values to LDS.  Phase 2: every
 // thread forms 4 consecutive y outputs of one x column for each of the TZ
@@ -127,9 +127,12 @@ __global__ __launch_bounds__(256) void k_smooth_yz(YZArgs a, GaussTaps taps, Sum
     const __amdgpu_buffer_rsrc_t src = make_rsrc(static_cast<const char *>(in) + (size_t)c * ES * N, ES * N);
     const __amdgpu_buffer_rsrc_t dst = make_rsrc(static_cast<char *>(out) + (size_t)c * ES * N, ES * N);
     const unsigned xb = ES * (unsigned)x;
-    float w[2 * R + 1];
+    float w[2 * R + 1], wz[2 * R + 1];  // y and z taps (equal for an isotropic Gaussian)
 #pragma unroll
-    for (int j = 0; j <= 2 * R; ++j) w[j] = taps.w[j];
+    for (int j = 0; j <= 2 * R; ++j) {
+        w[j] = taps.w[j];
+        wz[j] = taps.wz[j];
+    }
     // byte offsets of the window's planes (clamped), wave-uniform
     unsigned zoff[TZ + 2 * R];
 #pragma unroll
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(256) void k_smooth_yz(YZArgs a, GaussTaps taps, Sum
         for (int k = 0; k < TZ; ++k) {
             float s = 0.0f;
 #pragma unroll
-            for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], wa[k + j], s);
+            for (int j = 0; j <= 2 * R; ++j) s = fmaf(wz[j], wa[k + j], s);
             zs[k][row][lane] = s;
         }
         if (two) {
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void k_smooth_yz(YZArgs a, GaussTaps taps, Sum
             for (int k = 0; k < TZ; ++k) {
                 float s = 0.0f;
 #pragma unroll
-                for (int j = 0; j <= 2 * R; ++j) s = fmaf(w[j], wb[k + j], s);
+                for (int j = 0; j <= 2 * R; ++j) s = fmaf(wz[j], wb[k + j], s);
                 zs[k][row2][lane] = s;
             }
         }
@@ -233,9 +236,12 @@ __global__ __launch_bounds__(256) void k_smooth_yz2(YZArgs a, GaussTaps taps, Su
     const __amdgpu_buffer_rsrc_t src = make_rsrc(static_cast<const char *>(in) + (size_t)c * ES * N, ES * N);
     const __amdgpu_buffer_rsrc_t dst = make_rsrc(static_cast<char *>(out) + (size_t)c * ES * N, ES * N);
     const unsigned xb = ES * (unsigned)x;  // 4-byte aligned: x and nx are even
-    float w[2 * R + 1];
+    float w[2 * R + 1], wz[2 * R + 1];
 #pragma unroll
-    for (int j = 0; j <= 2 * R; ++j) w[j] = taps.w[j];
+    for (int j = 0; j <= 2 * R; ++j) {
+        w[j] = taps.w[j];
+        wz[j] = taps.wz[j];
+    }
     unsigned zoff[TZ + 2 * R];
 #pragma unroll
     for (int k = 0; k < TZ + 2 * R; ++k) zoff[k] = planeb * (unsigned)clampi(z0 - R + k, nz);
@@ -251,8 +257,8 @@ __global__ __launch_bounds__(256) void k_smooth_yz2(YZArgs a, GaussTaps taps, Su
             float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
             for (int j = 0; j <= 2 * R; ++j) {
-                s0 = fmaf(w[j], St::from_bits(pk[k + j]), s0);
-                s1 = fmaf(w[j], St::from_bits(pk[k + j] >> 16), s1);
+                s0 = fmaf(wz[j], St::from_bits(pk[k + j]), s0);
+                s1 = fmaf(wz[j], St::from_bits(pk[k + j] >> 16), s1);
             }
             zs[k][row][lane] = make_float2(s0, s1);
         }

@@ -4,8 +4,8 @@
 // within a byte budget, so requests that arrive while others run overlap with
 // them on the device.  With a batch limit above 1, the request at the head of
 // the queue is admitted together with the queued requests after it that can
-// run in lockstep with it (the same levels, iterations, sigma, radius and
-// storage), up to that limit, as one lockstep batch on one slot.  The pool is
+// run in lockstep with it (the same levels, iterations, sigma, radius,
+// storage, units and image pre-smoothing, and in mm the same spacing), up to that limit, as one lockstep batch on one slot.  The pool is
 // driven by the caller's calls (no thread of its own): every call first
 // collects finished registrations, without blocking, and admits queued ones.
 #include <hip/hip_runtime.h>
@@ -98,6 +98,8 @@ bool lockstep_with(const Request &a, const Request &b)
 {
     const dir_params &x = a.params, &y = b.params;
     if (x.levels != y.levels || x.sigma != y.sigma || x.radius != y.radius || x.storage != y.storage) return false;
+    if (x.units != y.units || x.image_sigma != y.image_sigma) return false;
+    if (x.units == DIR_UNITS_MM && memcmp(a.spacing, b.spacing, sizeof a.spacing) != 0) return false;
     for (int l = 0; l < x.levels; ++l)
         if (x.iters[l] != y.iters[l]) return false;
     return true;

@@ -62,14 +62,17 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_0909_0928_amd import binding as B
     src = tmp_path / "sizes.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "demons.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dir_params), sizeof(dir_stats),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dir_params), sizeof(dir_stats),'
                    'offsetof(dir_params, iters), offsetof(dir_params, eps), offsetof(dir_stats, history),'
-                   'offsetof(dir_stats, history_len)); return 0;}\n')
+                   'offsetof(dir_stats, history_len), offsetof(dir_params, units), offsetof(dir_params, image_sigma));'
+                   ' return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     sizes = [int(s) for s in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert sizes == [ctypes.sizeof(B.dir_params), ctypes.sizeof(B.dir_stats), B.dir_params.iters.offset,
-                     B.dir_params.eps.offset, B.dir_stats.history.offset, B.dir_stats.history_len.offset]
+                     B.dir_params.eps.offset, B.dir_stats.history.offset, B.dir_stats.history_len.offset,
+                     B.dir_params.units.offset, B.dir_params.image_sigma.offset]
+    assert sizes[0] == 96   # no implicit padding (graph keys compare parameters bytewise)
 
 
 def test_workspace_bytes_accounting():
@@ -88,10 +91,25 @@ def test_workspace_bytes_accounting():
     # pyramid levels: S and M at every coarser level (ceil halving)
     two = B.dir_workspace_bytes(shape, B.make_params("passive", [25, 25], sigma=1.0))
     assert two - one("passive", "f32") == 2 * 4 * (16 * 32 * 32)
+    # image pre-smoothing keeps a smoothed copy of every level of S and M
+    pre = B.dir_workspace_bytes(shape, B.make_params("passive", [25, 25], sigma=1.0, image_sigma=1.0))
+    assert pre - two == 2 * 4 * (n + 16 * 32 * 32)
+    pre16 = B.dir_workspace_bytes(shape, B.make_params("passive", [50], sigma=1.0, image_sigma=1.0, storage="f16"))
+    assert pre16 - one("passive", "f16") == 2 * 2 * n
+    # physical units need no extra buffers
+    assert B.dir_workspace_bytes(shape, B.make_params("passive", [50], sigma=1.0, units="mm")) == one("passive", "f32")
     bad = B.make_params("passive", [5], sigma=1.0)
     bad.sigma = -1.0
     with pytest.raises(B.DemonsError):
         B.dir_workspace_bytes(shape, bad)
+    for field, value in (("image_sigma", -0.5), ("image_sigma", float("nan")), ("units", 2), ("units", -1)):
+        bad = B.make_params("passive", [5], sigma=1.0)
+        setattr(bad, field, value)
+        with pytest.raises(B.DemonsError):
+            B.dir_workspace_bytes(shape, bad)
+    # voxel units: the pre-smoothing radius ceil(3 image_sigma) must stay within 16
+    with pytest.raises(B.DemonsError):
+        B.dir_workspace_bytes(shape, B.make_params("passive", [5], sigma=1.0, image_sigma=5.5))
 
 
 def test_size_limit_and_empty_volumes():
@@ -135,3 +153,4 @@ def test_autotune_argument_checks():
     p = B.make_params("passive", [2], sigma=1.0)
     assert L.dir_autotune(None, 8, 8, 8, ctypes.byref(p), 1, None) == B.DIR_EINVAL
     B.dir_autotune_clear()  # host only
+
