@@ -265,6 +265,29 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
                         const float *d_moving, const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma,
                         int32_t radius, float *d_field_out, double *sums);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dir_step
+ * (same arguments, same kernels and launch shapes, so bitwise the same
+ * d_field_out and sums, FP32 storage) with every intermediate (the
+ * x-smoothed field, the pre-warped images, the per-workgroup sums, the
+ * history entry and the level state) in a fixed array of
+ * DIR_NOALLOC_SCRATCH_BYTES in device memory that the library holds per
+ * device from its first dir_create on that device until the process ends,
+ * instead of the handle's workspace.  It calls no allocating routine, creates
+ * no timing events and leaves the handle's workspace untouched.  The array
+ * takes 12 bytes per voxel for DIR_PASSIVE and DIR_EVOLVED_PASSIVE, 16 for
+ * DIR_ACTIVE and DIR_DOUBLE and 20 for DIR_INVERSE_CONSISTENT, plus at most
+ * 197 KB of sums: 256x256x100 fits every variant.  A larger volume returns
+ * DIR_EINVAL (dir_last_error_message gives the bytes it needs) before any
+ * work is enqueued.  Every call on one device shares that device's array and
+ * it keeps the last call's contents (each call rewrites what it reads), so
+ * calls that overlap on one device (several threads, or handles on
+ * different streams) race and must be serialised by the caller.  Blocks. */
+#define DIR_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int32_t dir_step_noalloc(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
+                         const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma, int32_t radius,
+                         float *d_field_out, double *sums);
+
 /* Output field of the inverse-consistent variant from its half field h:
  * w(z) = 2 h(p) with p = z - h(p), p found by K fixed-point updates
  * p <- z - h(p) that start from the first-order inverse p = z - h(z)

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdemons.so")
 
 DIR_OK, DIR_EINVAL, DIR_ENOMEM, DIR_EDEVICE, DIR_ENUMERIC, DIR_EBUSY = 0, -1, -2, -3, -4, -5
+DIR_NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024   # include/demons.h
 DIR_PASSIVE, DIR_EVOLVED_PASSIVE, DIR_ACTIVE, DIR_DOUBLE, DIR_INVERSE_CONSISTENT = 0, 1, 2, 3, 4
 DIR_MAX_LEVELS = 8
 DIR_MAX_RADIUS = 16
@@ -83,6 +84,7 @@ def lib():
         L.dir_force.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, vp, ctypes.POINTER(f64)]
         L.dir_step.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_step_stored.argtypes = [vp, i32, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
+        L.dir_step_noalloc.argtypes = [vp, i32, f64, vp, vp, vp, i32, i32, i32, f64, i32, vp, ctypes.POINTER(f64)]
         L.dir_register_async.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.dir_register_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.dir_register_batch_async.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
@@ -114,6 +116,7 @@ def lib():
                      "dir_gradient", "dir_smooth", "dir_restrict", "dir_prolong", "dir_force", "dir_step", "dir_compose",
                      "dir_register_async", "dir_register_batch", "dir_register_batch_async", "dir_wait",
                      "dir_pool_set_max_batch", "dir_autotune", "dir_set_graphs", "dir_step_stored", "dir_similarity",
+                     "dir_step_noalloc",
                      "dir_workspace_bytes", "dir_pool_create", "dir_pool_destroy", "dir_pool_submit",
                      "dir_pool_progress", "dir_pool_poll", "dir_pool_wait", "dir_pool_stats",
                      "dir_timing_enable", "dir_timing_read", "dir_timing_read_level"):
@@ -499,6 +502,21 @@ def dir_step_stored(h, storage, variant, alpha, static, moving, field, sigma, ra
     sums = (ctypes.c_double * 3)()
     _check(lib().dir_step_stored(h.ptr, st, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
                                  *_dims(static), float(sigma), int(radius), _ptr(out), sums), "dir_step_stored")
+    return out, tuple(sums)
+
+
+def dir_step_noalloc(h, variant, alpha, static, moving, field, sigma, radius=0, out=None):
+    """dir_step with its intermediates in the library's fixed scratch array
+    (no allocation inside the call; `out` is allocated here when None)."""
+    if isinstance(variant, str):
+        variant = VARIANTS[variant]
+    _dev_f32(static, "static", 3)
+    _dev_f32(moving, "moving", 3)
+    _dev_f32(field, "field", 4)
+    out = torch.empty_like(field) if out is None else _dev_f32(out, "out", 4)
+    sums = (ctypes.c_double * 3)()
+    _check(lib().dir_step_noalloc(h.ptr, int(variant), float(alpha), _ptr(static), _ptr(moving), _ptr(field),
+                                  *_dims(static), float(sigma), int(radius), _ptr(out), sums), "dir_step_noalloc")
     return out, tuple(sums)
 
 

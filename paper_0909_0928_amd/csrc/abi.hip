@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <algorithm>
@@ -203,6 +204,39 @@ int finish(dir_handle *h)
     return DIR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of dir_step_noalloc: a fixed array in device memory, one copy per
+// device, held from the library's first use on that device until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host the
+// name is a stand-in, not a device address): dir_create looks up the array's
+// address on its device once, and the kernels take that address.
+static __device__ __align__(256) unsigned char scratch[DIR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxScratchDevices];  // device address of `scratch` per device (null: not set up)
+
+// With `device` current: look up the address of the device's copy of the
+// array, once per device.
+int setup_scratch(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return DIR_OK;  // dir_step_noalloc refuses such devices
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return DIR_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[device] = ptr;
+    return DIR_OK;
+}
+
+void *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+
 }  // namespace
 
 static_assert(dir::kTimerLevels >= DIR_MAX_LEVELS, "timer keeps one slot per pyramid level");
@@ -309,6 +343,8 @@ int32_t dir_create(dir_handle **out, int32_t device, void *stream)
     if (device < 0 || device >= count) return DIR_EINVAL;
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    const int rc = setup_scratch(device);
+    if (rc != DIR_OK) return rc;
     dir_handle *h = new (std::nothrow) dir_handle();
     if (!h) return DIR_ENOMEM;
     h->device = device;
@@ -609,7 +645,7 @@ struct StepBufs {
 };
 
 // Arguments of one iteration outside a registration (dir_force, dir_step,
-// dir_step_stored).
+// dir_step_stored, dir_step_noalloc).
 int check_step_args(int32_t variant, double alpha, const float *S, const float *M, const float *v, int32_t nx,
                     int32_t ny, int32_t nz, float *out, int storage)
 {
@@ -785,6 +821,57 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
     const GaussTaps taps = make_taps(sigma, R);
     return single_step(h, variant, alpha, d_static, d_moving, d_field, nx, ny, nz, &taps, d_field_out, sums,
                        storage);
+}
+
+// dir_step with its intermediates in the library's fixed scratch array: the
+// same kernels, launch shapes and reduction order, so the same results; no
+// device or host allocation and no timing events.
+int32_t dir_step_noalloc(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
+                         const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma, int32_t radius,
+                         float *d_field_out, double *sums)
+{
+    // arguments and the scratch size first (host arithmetic only, no device call)
+    if (!(sigma > 0.0) || !isfinite(sigma)) return DIR_EINVAL;
+    const int R = resolve_radius(sigma, radius);
+    if (R < 0 || R > DIR_MAX_RADIUS) return DIR_EINVAL;
+    int rc = check_step_args(variant, alpha, d_static, d_moving, d_field, nx, ny, nz, d_field_out, kStoreF32);
+    if (rc != DIR_OK) return rc;
+    const Dims d{nx, ny, nz};
+    // layout: level state, history entry, sums, u, then D and P as the variant needs them
+    const size_t n = (size_t)d.n();
+    const bool pre = variant == kActive || variant == kDouble || variant == kInverseConsistent;
+    const size_t off_hist = align256(sizeof(LevelState));
+    const size_t off_part = off_hist + align256(sizeof(double) * 4);
+    const size_t off_u = off_part + align256(sizeof(double) * 3 * (size_t)force_blocks(d));
+    const size_t off_D = off_u + align256(sizeof(float) * 3 * n);
+    const size_t off_P = off_D + (pre ? align256(sizeof(float) * n) : 0);
+    const size_t need = off_P + (variant == kInverseConsistent ? align256(sizeof(float) * n) : 0);
+    if (need > (size_t)DIR_NOALLOC_SCRATCH_BYTES) {
+        char buf[192];
+        snprintf(buf, sizeof buf, "dir_step_noalloc: %dx%dx%d needs %zu bytes of scratch, more than its %zu", nx, ny,
+                 nz, need, (size_t)DIR_NOALLOC_SCRATCH_BYTES);
+        g_last_error = buf;
+        return DIR_EINVAL;
+    }
+    rc = enter_idle(h);
+    if (rc != DIR_OK) return rc;
+    char *base = static_cast<char *>(scratch_of(h->device));
+    if (!base) {
+        g_last_error = "dir_step_noalloc: no scratch array on this device";
+        return DIR_EDEVICE;
+    }
+    StepBufs b;
+    b.st = reinterpret_cast<LevelState *>(base);
+    b.history = reinterpret_cast<double *>(base + off_hist);
+    b.partials = reinterpret_cast<double *>(base + off_part);
+    b.u = base + off_u;
+    b.D = pre ? base + off_D : nullptr;
+    b.P = variant == kInverseConsistent ? base + off_P : nullptr;
+    const GaussTaps taps = make_taps(sigma, R);
+    Ctx c{h->stream, nullptr};  // untimed: no events are created
+    DIR_TRY(enqueue_step(c, b, variant, alpha, d_static, d_moving, d_field, d, &taps, d_field_out, kStoreF32));
+    DIR_TRY(hipStreamSynchronize(h->stream));
+    return read_step_sums(h, b.history, sums);
 }
 
 }  // extern "C"
