@@ -274,6 +274,14 @@ STUDY_VARIANTS = ("passive", "inverse_consistent")
 
 
 def storage_study(args):
+    """FP32, F16 and BF16 storage of the 512x512x160 pair (passive and
+    inverse-consistent): speed, ground-truth error and the fields' RMS
+    against the FP32 run.  With --with-oracle, also every field against the
+    FP64 oracle run on the FP32 inputs ("raw") and on the inputs rounded to
+    the storage format ("rounded"), over the whole volume and over the body
+    sample; the oracle's own movement between raw and rounded inputs; and the
+    FP32 path run on the rounded inputs, which separates the rounding of the
+    inputs from the rounding of the stored fields and images."""
     import torch
     from paper_0909_0928_amd import binding as B
     from paper_0909_0928_amd import phantom as P
@@ -293,9 +301,18 @@ def storage_study(args):
     h = B.dir_create(0, stream=torch.cuda.Stream(device=dev))
     vi = voxel_iters(STUDY_SHAPE, STUDY_ITERS)
     n0 = STUDY_SHAPE[0] * STUDY_SHAPE[1] * STUDY_SHAPE[2]
+    tdtype = {"f16": torch.float16, "bf16": torch.bfloat16}
+    rounded = {st: (S.to(tdtype[st]).float(), M.to(tdtype[st]).float()) for st in tdtype}
+
+    def rms_pair(a, b):
+        """RMS of a - b (host fields [3, N]) over the volume and over the body sample."""
+        dd = ((a - b) ** 2).sum(axis=0)
+        return {"volume": float(np.sqrt(dd.mean())), "body": float(np.sqrt(dd[sample].mean()))}
+
     rows = []
     for variant in STUDY_VARIANTS:
         ref = None
+        fields = {}
         for st in ("f32", "f16", "bf16"):
             p = B.make_params(variant, STUDY_ITERS, sigma=SIGMA, radius=RADIUS, storage=st)
             B.dir_register(h, S, M, p, field_out=out, history=False)           # warm-up
@@ -327,20 +344,37 @@ def storage_study(args):
                 row["rms_vs_f32_vox"] = float(dd.mean().sqrt())
                 row["rms_vs_f32_body_sample_vox"] = float(dd.view(-1)[sample_dev].mean().sqrt())
                 row["gt_error_change_vox"] = gt - rows[-1 if st == "f16" else -2]["gt_error_vox"]
+            if args.with_oracle:
+                fields[st] = out.cpu().numpy().astype(np.float64).reshape(3, -1)
             rows.append(row)
             print(json.dumps(row), flush=True)
         if args.with_oracle:
             import oracle as O
-            print(f"[study] FP64 oracle, {variant}", file=sys.stderr, flush=True)
-            t0 = time.perf_counter()
-            of, _, _, _ = O.register(ph.static.astype(np.float32).astype(np.float64),
-                                     ph.moving.astype(np.float32).astype(np.float64), O.VARIANTS[variant],
-                                     STUDY_ITERS, sigma=SIGMA, radius=RADIUS)
-            dt = time.perf_counter() - t0
-            g = ref.cpu().numpy().astype(np.float64).reshape(3, -1)
-            orc = {"variant": variant, "oracle_seconds": dt,
-                   "rms_gpu_f32_vs_oracle_vox": float(np.sqrt(((g - of.reshape(3, -1)) ** 2).sum(axis=0).mean()))}
-            print(json.dumps(orc), flush=True)
+            # the FP32 path on the rounded inputs: storage rounding of the
+            # inputs alone, without that of the fields and images inside
+            p32 = B.make_params(variant, STUDY_ITERS, sigma=SIGMA, radius=RADIUS)
+            f32_on = {}
+            for st, (Sr, Mr) in rounded.items():
+                B.dir_register(h, Sr, Mr, p32, field_out=out, history=False)
+                f32_on[st] = out.cpu().numpy().astype(np.float64).reshape(3, -1)
+            orc = {}
+            for key, (Sa, Ma) in (("raw", (S, M)), ("f16", rounded["f16"]), ("bf16", rounded["bf16"])):
+                print(f"[study] FP64 oracle, {variant}, {key} inputs", file=sys.stderr, flush=True)
+                t0 = time.perf_counter()
+                of, _, _, _ = O.register(Sa.cpu().numpy().astype(np.float64), Ma.cpu().numpy().astype(np.float64),
+                                         O.VARIANTS[variant], STUDY_ITERS, sigma=SIGMA, radius=RADIUS)
+                orc[key] = (of.reshape(3, -1), time.perf_counter() - t0)
+            res = {"variant": variant, "oracle_seconds": {k: v[1] for k, v in orc.items()},
+                   "oracle_rounded_inputs_vs_raw_vox": {st: rms_pair(orc[st][0], orc["raw"][0])
+                                                        for st in ("f16", "bf16")},
+                   "gpu_vs_oracle_raw_vox": {st: rms_pair(fields[st], orc["raw"][0]) for st in fields},
+                   "gpu_vs_oracle_rounded_vox": {st: rms_pair(fields[st], orc[st][0]) for st in ("f16", "bf16")},
+                   "gpu_f32_on_rounded_inputs_vs_oracle_rounded_vox": {st: rms_pair(f32_on[st], orc[st][0])
+                                                                       for st in f32_on},
+                   "gpu_storage_vs_gpu_f32_on_rounded_inputs_vox": {st: rms_pair(fields[st], f32_on[st])
+                                                                    for st in f32_on}}
+            print(json.dumps(res), flush=True)
+            rows.append(res)
     B.dir_destroy(h)
     print(json.dumps({"study": "storage", "shape_xyz": list(STUDY_SHAPE), "iters_coarse_to_fine": STUDY_ITERS,
                       "sigma": SIGMA, "radius": RADIUS, "max_u": STUDY_MAX_U, "rows": rows}))
