@@ -821,13 +821,27 @@ def main():
     total_vi = vi_reg * len(SETTINGS) * args.steps
     value = total_vi / elapsed
 
-    streams_res = seq_res = None
+    streams_res = seq_res = graphs_res = None
     lats, per_var = np.array([np.nan]), {}
     if compare:
         print(f"[bench] streams {args.steps} steps", file=sys.stderr, flush=True)
         st_elapsed, _ = timed_steps(step_streams, args.steps)
         streams_res = {"value": total_vi / st_elapsed, "ms_per_step": st_elapsed * 1e3 / args.steps,
                        "steps": args.steps}
+        # the same batch step captured once into a HIP graph and replayed
+        hg = B.dir_create(0, stream=torch.cuda.Stream(device=dev))
+        B.dir_set_graphs(hg, True)
+
+        def step_graph():
+            B.dir_register_batch(hg, [S] * len(SETTINGS), [M] * len(SETTINGS), plist, field_outs=outs,
+                                 history=False)
+        for _ in range(max(args.warmup, 1)):
+            step_graph()
+        print(f"[bench] graph-replayed batch {args.steps} steps", file=sys.stderr, flush=True)
+        g_elapsed, g_ms = timed_steps(step_graph, args.steps)
+        graphs_res = {"value": total_vi / g_elapsed, "ms_per_step": g_elapsed * 1e3 / args.steps,
+                      "step_p50_ms": float(np.percentile(g_ms, 50)), "steps": args.steps}
+        B.dir_destroy(hg)
         # the same steps one registration at a time: per-registration latency
         print(f"[bench] sequential {args.latency_steps} steps", file=sys.stderr, flush=True)
         lat = []
@@ -956,6 +970,7 @@ def main():
                        "per_setting_p50": per_var, "alone": True,
                        "step_p50": float(np.percentile(step_ms, 50)), "step_p99": float(np.percentile(step_ms, 99))},
         "streams": streams_res,
+        "batch_graphs": graphs_res,
         "sequential": seq_res,
         "roofline": roof,
         "roofline_hbm": roof_hbm,

@@ -170,16 +170,17 @@ int32_t dir_destroy(dir_handle *h);
 /* Wait for all work enqueued by this handle. */
 int32_t dir_synchronize(dir_handle *h);
 
-/* Capture of whole registrations into HIP graphs (enable != 0; off by
- * default).  With it on, a registration that needs no host wait (eps = 0, or
- * any dir_register_async) on a handle with a non-null stream and no kernel
- * timing is captured on first use and replayed by later calls whose
- * arguments (pointers, sizes, parameters) and workspace are unchanged: one
- * graph launch instead of one launch per kernel, with the same kernels, so
- * results are bitwise those of enqueuing the kernels one by one.  It cuts the
- * host's submission time about 7x; on ROCm 7 the device time is not shorter
- * (a lone registration runs about 10% longer as a graph), hence the default.
- * The handle keeps the last captured graph; other calls capture anew. */
+/* Capture of whole registrations and lockstep batches into HIP graphs
+ * (enable != 0; off by default).  With it on, a registration or batch that
+ * needs no host wait (eps = 0, or any asynchronous call) on a handle with a
+ * non-null stream and no kernel timing is captured on first use and replayed
+ * by later calls whose arguments (pointers, sizes, parameters, spacing) and
+ * workspace are unchanged: one graph launch instead of one launch per kernel,
+ * with the same kernels, so results are bitwise those of enqueuing the
+ * kernels one by one.  It cuts the host's submission time about 7x; on ROCm 7
+ * the device time is not shorter (a lone registration runs about 10% longer
+ * as a graph), hence the default.  The handle keeps the last captured graph;
+ * other calls capture anew. */
 int32_t dir_set_graphs(dir_handle *h, int32_t enable);
 
 /* Multi-scale demons registration of d_moving onto d_static (Sec 2.1-2.4).

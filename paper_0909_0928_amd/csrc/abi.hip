@@ -55,18 +55,12 @@ struct DevBuf {
 
 }  // namespace
 
-// Key of a captured registration: the call's arguments and every workspace
-// address its kernels use.  Replaying the graph is only valid for an equal key.
-// Laid out without implicit padding, so keys compare with memcmp.
-struct GraphKey {
-    const void *S, *M, *out;
-    const void *ws[14];
-    dir_params params;
-    double spacing[3];
-    int32_t nx, ny, nz, pad;
-};
+// Key of a captured registration or lockstep batch: the bytes of the call's
+// arguments (pointers, sizes, parameters, voxel sizes) and of every workspace
+// and side-stream address its kernels use.  Replaying the graph is only valid
+// for an equal key.
+using GraphKey = std::vector<unsigned char>;
 static_assert(kMaxBatch == DIR_MAX_BATCH, "batch limit of the ABI and of the kernels");
-static_assert(sizeof(GraphKey) == 17 * sizeof(void *) + sizeof(dir_params) + 40, "GraphKey has padding");
 
 // A registration enqueued by dir_register_async (or dir_register) whose
 // statistics have not been collected yet.
@@ -95,13 +89,17 @@ struct dir_handle {
     InFlight inflight;             // registration enqueued and not yet collected
     bool graphs = false;           // capture registrations into HIP graphs (dir_set_graphs)
     hipGraphExec_t graph_exec = nullptr;  // the last captured registration
-    GraphKey graph_key;            // ... and what it was captured for
+    GraphKey graph_key;            // ... and what it was captured for (empty: nothing captured)
     // Side streams on which a batch runs registrations concurrently (created
     // on first use, default priority); the handle's stream forks to them
     // with fork_ev and joins them with side_done.
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_done;
     hipEvent_t fork_ev = nullptr;
+    // Pinned host buffer the level states and histories of a finished
+    // registration (or batch) are copied into, all at once.
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
 };
 
 namespace {
@@ -372,6 +370,7 @@ int32_t dir_destroy(dir_handle *h)
     for (hipEvent_t e : h->side_done) (void)hipEventDestroy(e);
     if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     h->timer.release();
+    if (h->stage) (void)hipHostFree(h->stage);
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     h->pyr_s.release();
     h->pyr_m.release();
@@ -405,6 +404,7 @@ int32_t dir_set_graphs(dir_handle *h, int32_t enable)
         rc = finish(h);
         (void)hipGraphExecDestroy(h->graph_exec);
         h->graph_exec = nullptr;
+        h->graph_key.clear();
     }
     return rc;
 }
@@ -1039,6 +1039,7 @@ void workspace_release(dir_handle *h)
     if (h->graph_exec) {
         (void)hipGraphExecDestroy(h->graph_exec);
         h->graph_exec = nullptr;
+        h->graph_key.clear();
     }
 }
 
@@ -1586,22 +1587,28 @@ int enqueue_register(dir_handle *h, const RegPlan &pl, bool poll)
     return rc != DIR_OK ? rc : jrc;
 }
 
+// p: the plan's dir_params, one per registration.
 GraphKey graph_key(dir_handle *h, const RegPlan &pl, const dir_params *p)
 {
     GraphKey k;
-    memset(&k, 0, sizeof k);
-    k.S = pl.S[0];
-    k.M = pl.M[0];
-    k.out = pl.out[0];
-    k.nx = pl.dims[0][0].nx;
-    k.ny = pl.dims[0][0].ny;
-    k.nz = pl.dims[0][0].nz;
-    memcpy(&k.params, p, sizeof k.params);
-    for (int a = 0; a < 3; ++a) k.spacing[a] = pl.h[a];
+    auto put = [&k](const void *x, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(x);
+        k.insert(k.end(), b, b + n);
+    };
+    put(&pl.count, sizeof pl.count);
+    for (int r = 0; r < pl.count; ++r) {
+        put(&pl.S[r], sizeof pl.S[r]);
+        put(&pl.M[r], sizeof pl.M[r]);
+        put(&pl.out[r], sizeof pl.out[r]);
+        put(&pl.dims[r][0], sizeof pl.dims[r][0]);
+        put(&p[r], sizeof p[r]);
+    }
+    put(pl.h, sizeof pl.h);
     const DevBuf *bufs[14] = {&h->pyr_s,  &h->pyr_m,  &h->field[0], &h->field[1], &h->field[2],
                               &h->img_a,  &h->img_b,  &h->img0_s,   &h->img0_m,   &h->pre_s,
                               &h->pre_m,  &h->partials, &h->history, &h->state};
-    for (int i = 0; i < 14; ++i) k.ws[i] = bufs[i]->p;
+    for (const DevBuf *b : bufs) put(&b->p, sizeof b->p);
+    for (hipStream_t sd : h->side) put(&sd, sizeof sd);
     return k;
 }
 
@@ -1642,34 +1649,55 @@ void note_inflight(dir_handle *h, const RegPlan &pl)
     f.state_stride = pl.stride.state;
 }
 
-int submit_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
-                    int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out, bool poll)
+// Enqueue a validated plan (p: its dir_params, one per registration) and
+// record it as in flight.  Without a host wait inside it (no polled stopping
+// rule) and without kernel timing, on a handle with graphs on and a non-null
+// stream, the launches are captured once into a HIP graph, which is replayed
+// while the key stays the same; otherwise they are enqueued one by one.
+int submit_plan(dir_handle *h, const RegPlan &pl, const dir_params *p, bool poll)
 {
-    RegPlan pl;
-    int rc = plan_register(h, d_static, d_moving, nx, ny, nz, spacing_mm, p, d_field_out, pl);
-    if (rc != DIR_OK) return rc;
-    const bool graph = h->graphs && h->stream != nullptr && h->timer.mask == 0 && !(poll && pl.eps[0] > 0.0);
+    bool polled = false;
+    for (int r = 0; r < pl.count; ++r) polled = polled || (poll && pl.eps[r] > 0.0);
+    const bool graph = h->graphs && h->stream != nullptr && h->timer.mask == 0 && !polled;
     if (graph) {
-        const GraphKey key = graph_key(h, pl, p);
-        if (!h->graph_exec || memcmp(&key, &h->graph_key, sizeof key) != 0) {
+        if (pl.count > 1) {  // the side streams a batch may fork to exist before the key is taken
+            int lanes = 1;
+            for (int k = 0; k < pl.L; ++k) lanes = std::max(lanes, concurrent_lanes(pl.count, pl, k, storage_bytes(pl.storage)));
+            while ((int)h->side.size() < lanes - 1) {
+                const int rc = fork_lanes(h, (int)h->side.size() + 2);
+                if (rc != DIR_OK) return rc;
+            }
+        }
+        GraphKey key = graph_key(h, pl, p);
+        if (!h->graph_exec || key != h->graph_key) {
             if (h->graph_exec) {
                 (void)hipGraphExecDestroy(h->graph_exec);
                 h->graph_exec = nullptr;
+                h->graph_key.clear();
             }
-            rc = capture_register(h, pl, &h->graph_exec);
+            const int rc = capture_register(h, pl, &h->graph_exec);
             if (rc != DIR_OK) {
                 h->graph_exec = nullptr;
                 return rc;
             }
-            memcpy(&h->graph_key, &key, sizeof key);
+            h->graph_key.swap(key);
         }
         DIR_TRY(hipGraphLaunch(h->graph_exec, h->stream));
     } else {
-        rc = enqueue_register(h, pl, poll);
+        const int rc = enqueue_register(h, pl, poll);
         if (rc != DIR_OK) return rc;
     }
     note_inflight(h, pl);
     return DIR_OK;
+}
+
+int submit_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
+                    int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out, bool poll)
+{
+    RegPlan pl;
+    const int rc = plan_register(h, d_static, d_moving, nx, ny, nz, spacing_mm, p, d_field_out, pl);
+    if (rc != DIR_OK) return rc;
+    return submit_plan(h, pl, p, poll);
 }
 
 // Fill one registration's statistics from its level states and history.
@@ -1709,21 +1737,30 @@ int collect_register(dir_handle *h, dir_stats *stats, int32_t *status = nullptr)
 {
     const InFlight f = h->inflight;
     h->inflight.active = false;
+    // the level states and histories of all registrations: two copies into
+    // the pinned stage, one wait
+    const size_t sbytes = f.state_stride * (size_t)(f.count - 1) + sizeof(LevelState) * (size_t)f.levels;
+    const size_t hoff = (sbytes + 255) & ~(size_t)255;
+    const size_t hbytes =
+        f.total_iters > 0 ? f.hist_stride * (size_t)(f.count - 1) + sizeof(double) * 4 * (size_t)f.total_iters : 0;
+    if (hoff + hbytes > h->stage_bytes) {
+        DIR_TRY(hipStreamSynchronize(h->stream));  // the old stage may still be a copy's target
+        if (h->stage) (void)hipHostFree(h->stage);
+        h->stage = nullptr;
+        h->stage_bytes = 0;
+        DIR_TRY(hipHostMalloc(&h->stage, hoff + hbytes));
+        h->stage_bytes = hoff + hbytes;
+    }
+    char *stage = static_cast<char *>(h->stage);
+    DIR_TRY(hipMemcpyAsync(stage, h->state.p, sbytes, hipMemcpyDeviceToHost, h->stream));
+    if (hbytes) DIR_TRY(hipMemcpyAsync(stage + hoff, h->history.p, hbytes, hipMemcpyDeviceToHost, h->stream));
     int rc = finish(h);
     if (rc != DIR_OK) return rc;
     bool finite = true;
-    std::vector<double> hh((size_t)4 * (size_t)(f.total_iters > 0 ? f.total_iters : 1));
     for (int r = 0; r < f.count; ++r) {
-        LevelState hs[DIR_MAX_LEVELS];
-        rc = copy_to_host(h, hs, static_cast<char *>(h->state.p) + f.state_stride * (size_t)r,
-                          sizeof(LevelState) * f.levels);
-        if (rc != DIR_OK) return rc;
-        if (f.total_iters > 0) {
-            rc = copy_to_host(h, hh.data(), static_cast<char *>(h->history.p) + f.hist_stride * (size_t)r,
-                              sizeof(double) * 4 * f.total_iters);
-            if (rc != DIR_OK) return rc;
-        }
-        const bool ok = fill_stats(f, hs, hh.data(), stats ? &stats[r] : nullptr);
+        const LevelState *hs = reinterpret_cast<const LevelState *>(stage + f.state_stride * (size_t)r);
+        const double *hh = reinterpret_cast<const double *>(stage + hoff + f.hist_stride * (size_t)r);
+        const bool ok = fill_stats(f, hs, hh, stats ? &stats[r] : nullptr);
         if (status) status[r] = ok ? DIR_OK : DIR_ENUMERIC;
         if (!ok) finite = false;
     }
@@ -1821,10 +1858,7 @@ int32_t dir_register_batch_async(dir_handle *h, int32_t count, const float *cons
     RegPlan pl;
     rc = plan_batch(h, count, d_static, d_moving, dims, spacing_mm, params, d_field_out, pl);
     if (rc != DIR_OK) return rc;
-    rc = enqueue_register(h, pl, false);
-    if (rc != DIR_OK) return rc;
-    note_inflight(h, pl);
-    return DIR_OK;
+    return submit_plan(h, pl, params, false);
 }
 
 int32_t dir_register_batch(dir_handle *h, int32_t count, const float *const *d_static,

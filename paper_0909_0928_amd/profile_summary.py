@@ -99,6 +99,24 @@ def trace_summary(d: str, command: str, out: str) -> None:
         for (k2, g), v2 in sorted(solo.items(), key=lambda kv: -kv[0][1]):
             if k2 == k:
                 lines.append(f"| `{k}` | {g} | {len(v2)} | {sum(v2) / len(v2):.2f} |")
+    # steps end with the inverse-consistent registration's composition
+    ends = [i for i, (_, _, r) in enumerate(recs) if "k_compose" in r["Kernel_Name"]]
+    if ends:
+        lines += ["", "## Device time per step (launches up to each composition; the step's first launches wait "
+                  "for the host)", "",
+                  "| step | launches | span ms | kernels ms | idle ms | idle, excluding the wait for the first "
+                  "launch and the copy-backs, ms |", "|---|---|---|---|---|---|"]
+        lo = 0
+        for n, hi in enumerate(ends):
+            seg = recs[lo:hi + 1]
+            span = (seg[-1][1] - seg[0][0]) / 1e6
+            busy = sum(t1 - t0 for t0, t1, _ in seg) / 1e6
+            idle_k = 0.0
+            for (a0, a1, _), (b0, b1, rb) in zip(seg, seg[1:]):
+                if "copyBuffer" not in rb["Kernel_Name"] and "copyBuffer" not in _["Kernel_Name"]:
+                    idle_k += max(b0 - a1, 0) / 1e6
+            lines.append(f"| {n} | {len(seg)} | {span:.2f} | {busy:.2f} | {span - busy:.2f} | {idle_k:.2f} |")
+            lo = hi + 1
     lines += ["", "## Per kernel and grid size (from the kernel trace)", "",
               "| kernel | grid threads | calls | average us | total ms |", "|---|---|---|---|---|"]
     for (k, g), v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:30]:

@@ -305,3 +305,45 @@ def test_autotuned_smoothing_depth_leaves_results_unchanged(B, h):
         _check_equal(_alone(B, h, pairs[:1], params[:1]), alone)
     finally:
         B.dir_autotune_clear()
+
+
+@pytest.mark.parametrize("storage,shapes,iters", [
+    ("f32", [(48, 40, 20)] * 6, [4, 3, 2]),               # every level in lockstep
+    ("f32", [(256, 256, 100)] * 2, [3, 2, 1]),            # finest level one registration at a time
+    ("f32", [(160, 160, 100)] * 3, [3, 2]),               # finest level on three lanes (side streams captured)
+    ("f16", [(256, 256, 100)] * 3 + [(200, 180, 90)], [2, 2, 1]),
+])
+def test_graph_captured_batch_replays_equal_eager(B, storage, shapes, iters):
+    """dir_set_graphs on: a batch (lockstep levels, and levels on side-stream
+    lanes) is captured on first use and replayed; every replay, with eager
+    work and synchronisations in between, gives each field and history bitwise
+    as the eager batch; a changed parameter is captured anew."""
+    pairs = []
+    for k, shape in enumerate(shapes):
+        pairs += _pairs(shape, 1, 300 + k)
+    names = [SIX[k % len(SIX)] for k in range(len(shapes))]
+    params = [B.make_params(v, iters, sigma=1.5, alpha=a, storage=storage) for v, a in names]
+    S = [p[0] for p in pairs]
+    M = [p[1] for p in pairs]
+    s = torch.cuda.Stream()
+    hg = B.dir_create(0, stream=s)
+    try:
+        eager = [(f.clone(), st) for f, st in B.dir_register_batch(hg, S, M, params)]
+        B.dir_set_graphs(hg, True)
+        outs = [torch.empty_like(f) for f, _ in eager]
+        for rep in range(3):
+            for o in outs:
+                o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            res = B.dir_register_batch(hg, S, M, params, field_outs=outs)
+            _check_equal(res, eager)
+            B.dir_warp(hg, S[0], outs[0])           # eager work on the handle's stream between replays
+            (S[0] * 2.0).sum().item()               # and on the default stream
+        changed = list(params)
+        changed[0] = B.make_params(names[0][0], iters, sigma=1.5, alpha=0.7, storage=storage)
+        res = B.dir_register_batch(hg, S, M, changed, field_outs=outs)
+        B.dir_set_graphs(hg, False)
+        ref = B.dir_register_batch(hg, S, M, changed)
+        _check_equal(res, ref)
+    finally:
+        B.dir_destroy(hg)
