@@ -125,13 +125,20 @@ __device__ __forceinline__ void force_point(const Geo &q, float alpha2, const Bu
     const float vx = St::load(b.v, lo.c, ro.c), vy = St::load(b.v, lo.c, ro.c + nbytes),
                 vz = St::load(b.v, lo.c, ro.c + 2u * nbytes);
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    // intensity difference: sampled in FP64 here (passive, evolved) or taken
-    // from the pre-warp kernel, which forms it the same way; rounded once
+    // intensity difference: sampled in FP64 here (passive, evolved; FP32 for
+    // 16-bit storage) or taken from the pre-warp kernel, which forms it the
+    // same way; rounded once
     double D64;
-    if (V == kPassive || V == kEvolved)
-        D64 = bsample64<St>(b.M, bcell_disp<ES>(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)St::load(b.S, lo.c, ro.c);
-    else
+    if constexpr (V == kPassive || V == kEvolved) {
+        if constexpr (ES == 4)
+            D64 = bsample64<St>(b.M, bcell_disp<ES>(x, y, z, vx, vy, vz, nx, ny, nz)) -
+                  (double)St::load(b.S, lo.c, ro.c);
+        else  // 16-bit storage: FP32 sample (see bsample32)
+            D64 = (double)(bsample32<St>(b.M, bcell32<ES>(x, y, z, vx, vy, vz, nx, ny, nz)) -
+                           St::load(b.S, lo.c, ro.c));
+    } else {
         D64 = (double)St::load(b.Dd, lo.c, ro.c);
+    }
     const float D = (float)D64;
     if (V == kInverseConsistent) {
         // Eq 6: g = grad Im + grad Is = grad P of the two deformed images.

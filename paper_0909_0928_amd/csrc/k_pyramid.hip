@@ -117,7 +117,8 @@ struct PrewarpArgs {
 };
 
 // Intensity difference for the active and double forces: D = M(x - v) - S(x),
-// sampled and subtracted in FP64, rounded once.  The force kernel takes D and
+// sampled and subtracted in FP64, rounded once (FP32 for 16-bit storage, see
+// bsample32).  The force kernel takes D and
 // its gradient from here (grad Im = grad D + grad S), so the gather happens
 // once per iteration.  Buffer addressing as in the force kernel; every volume
 // in format St.
@@ -131,15 +132,19 @@ __device__ __forceinline__ void warp_diff_at(const PrewarpArgs &a, int r, int x,
                                  rv = make_rsrc(a.v[r], 3u * nbytes), rD = make_rsrc(a.D[r], nbytes);
     const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
     const float vx = St::load(rv, o, 0), vy = St::load(rv, o, nbytes), vz = St::load(rv, o, 2u * nbytes);
-    const double d = bsample64<St>(rM, bcell_disp<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)St::load(rS, o, 0);
-    St::store(rD, (float)d, o, 0);
+    if constexpr (E == 4) {
+        const double d = bsample64<St>(rM, bcell_disp<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)St::load(rS, o, 0);
+        St::store(rD, (float)d, o, 0);
+    } else {  // 16-bit storage: FP32 sample (see bsample32)
+        St::store(rD, bsample32<St>(rM, bcell32<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - St::load(rS, o, 0), o, 0);
+    }
 }
 
 // Inverse-consistent pair (Sec 2.2, after Eq 6): Im = M(x - h), Is = S(x + h),
 // written as D = Im - Is and P = Im + Is (the force needs D and grad P).
-// Both formed in FP64 and rounded once: D to the storage format, P to FP32
-// (P is near twice the background intensity, where 16-bit spacing would
-// quantise the gradient the force divides by).
+// Both formed in FP64 and rounded once (FP32 for 16-bit storage): D to the
+// storage format, P to FP32 (P is near twice the background intensity, where
+// 16-bit spacing would quantise the gradient the force divides by).
 template <class St>
 __device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x, int y, int z)
 {
@@ -151,10 +156,17 @@ __device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x,
                                  rP = make_rsrc(a.P[r], (4u / E) * nbytes);
     const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
     const float hx = St::load(rh, o, 0), hy = St::load(rh, o, nbytes), hz = St::load(rh, o, 2u * nbytes);
-    const double im = bsample64<St>(rM, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz));
-    const double is = bsample64<St>(rS, bcell_disp<E>(x, y, z, -hx, -hy, -hz, nx, ny, nz));
-    St::store(rD, (float)(im - is), o, 0);
-    StF32::store(rP, (float)(im + is), (4u / E) * o, 0);
+    if constexpr (E == 4) {
+        const double im = bsample64<St>(rM, bcell_disp<E>(x, y, z, hx, hy, hz, nx, ny, nz));
+        const double is = bsample64<St>(rS, bcell_disp<E>(x, y, z, -hx, -hy, -hz, nx, ny, nz));
+        St::store(rD, (float)(im - is), o, 0);
+        StF32::store(rP, (float)(im + is), (4u / E) * o, 0);
+    } else {  // 16-bit storage: FP32 samples (see bsample32)
+        const float im = bsample32<St>(rM, bcell32<E>(x, y, z, hx, hy, hz, nx, ny, nz));
+        const float is = bsample32<St>(rS, bcell32<E>(x, y, z, -hx, -hy, -hz, nx, ny, nz));
+        St::store(rD, im - is, o, 0);
+        StF32::store(rP, im + is, (4u / E) * o, 0);
+    }
 }
 
 // Workgroup -> (registration, x tile, y tile, z plane); false past the volume
