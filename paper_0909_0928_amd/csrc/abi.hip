@@ -24,7 +24,12 @@ const char *const kKernelNames[K_COUNT] = {
     "restrict", "prolong", "gradient", "compose", "fill", "convert", "similarity", "warp_mixed",
 };
 
-// Device buffer that only grows.
+// Bytes allocated past every workspace buffer's size: 16-bit volumes are
+// gathered with 8-byte loads that may reach kPad16 bytes past a volume's end.
+constexpr size_t kSlackBytes = 256;
+static_assert(kSlackBytes >= kPad16, "slack covers the gathers' overreach");
+
+// Device buffer that only grows (`bytes` usable, kSlackBytes more allocated).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -36,7 +41,7 @@ struct DevBuf {
             p = nullptr;
             bytes = 0;
         }
-        hipError_t e = hipMalloc(&p, need);
+        hipError_t e = hipMalloc(&p, need + kSlackBytes);
         if (e == hipSuccess) bytes = need;
         return e;
     }

@@ -27,6 +27,12 @@ constexpr int kMaxBatch = 8;
 enum Storage { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2 };
 inline unsigned storage_bytes(int st) { return st == kStoreF32 ? 4u : 2u; }
 
+// Bytes a 16-bit volume's buffer reaches past the volume's end, so that the
+// 8-byte loads of a 16-bit gather (bpair16) stay in range: the workspace
+// allocates them, and the buffer resources of gathered 16-bit volumes
+// include them.
+constexpr unsigned kPad16 = 8;
+
 // Kernel ids for event timing; names in kKernelNames (abi.hip).
 enum KernelId {
     K_FORCE = 0,     // force + x pass of the smoothing + sums (+ last-workgroup reduction)

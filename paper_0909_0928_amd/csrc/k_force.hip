@@ -134,7 +134,7 @@ __device__ __forceinline__ void force_point(const Geo &q, float alpha2, const Bu
             D64 = bsample64<St>(b.M, bcell_disp<ES>(x, y, z, vx, vy, vz, nx, ny, nz)) -
                   (double)St::load(b.S, lo.c, ro.c);
         else  // 16-bit storage: FP32 sample (see bsample32)
-            D64 = (double)(bsample32<St>(b.M, bcell32<ES>(x, y, z, vx, vy, vz, nx, ny, nz)) -
+            D64 = (double)(bsample32<St, false>(b.M, bcell32<ES>(x, y, z, vx, vy, vz, nx, ny, nz)) -
                            St::load(b.S, lo.c, ro.c));
     } else {
         D64 = (double)St::load(b.Dd, lo.c, ro.c);

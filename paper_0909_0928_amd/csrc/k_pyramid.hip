@@ -128,7 +128,8 @@ __device__ __forceinline__ void warp_diff_at(const PrewarpArgs &a, int r, int x,
     const int nx = a.geo[r].nx, ny = a.geo[r].ny, nz = a.geo[r].nz;
     constexpr unsigned E = St::kBytes;
     const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
-    const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes), rS = make_rsrc(a.S[r], nbytes),
+    constexpr unsigned pad = E == 2 ? kPad16 : 0u;  // M is gathered (bsample32)
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes + pad), rS = make_rsrc(a.S[r], nbytes),
                                  rv = make_rsrc(a.v[r], 3u * nbytes), rD = make_rsrc(a.D[r], nbytes);
     const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
     const float vx = St::load(rv, o, 0), vy = St::load(rv, o, nbytes), vz = St::load(rv, o, 2u * nbytes);
@@ -136,7 +137,7 @@ __device__ __forceinline__ void warp_diff_at(const PrewarpArgs &a, int r, int x,
         const double d = bsample64<St>(rM, bcell_disp<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - (double)St::load(rS, o, 0);
         St::store(rD, (float)d, o, 0);
     } else {  // 16-bit storage: FP32 sample (see bsample32)
-        St::store(rD, bsample32<St>(rM, bcell32<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - St::load(rS, o, 0), o, 0);
+        St::store(rD, bsample32<St, true>(rM, bcell32<E>(x, y, z, vx, vy, vz, nx, ny, nz)) - St::load(rS, o, 0), o, 0);
     }
 }
 
@@ -151,7 +152,8 @@ __device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x,
     const int nx = a.geo[r].nx, ny = a.geo[r].ny, nz = a.geo[r].nz;
     constexpr unsigned E = St::kBytes;
     const unsigned nbytes = E * (unsigned)nx * (unsigned)ny * (unsigned)nz;
-    const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes), rS = make_rsrc(a.S[r], nbytes),
+    constexpr unsigned pad = E == 2 ? kPad16 : 0u;  // M and S are gathered (bsample32)
+    const __amdgpu_buffer_rsrc_t rM = make_rsrc(a.M[r], nbytes + pad), rS = make_rsrc(a.S[r], nbytes + pad),
                                  rh = make_rsrc(a.v[r], 3u * nbytes), rD = make_rsrc(a.D[r], nbytes),
                                  rP = make_rsrc(a.P[r], (4u / E) * nbytes);
     const unsigned o = E * (unsigned)(x + nx * (y + ny * z));
@@ -162,8 +164,8 @@ __device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x,
         St::store(rD, (float)(im - is), o, 0);
         StF32::store(rP, (float)(im + is), (4u / E) * o, 0);
     } else {  // 16-bit storage: FP32 samples (see bsample32)
-        const float im = bsample32<St>(rM, bcell32<E>(x, y, z, hx, hy, hz, nx, ny, nz));
-        const float is = bsample32<St>(rS, bcell32<E>(x, y, z, -hx, -hy, -hz, nx, ny, nz));
+        const float im = bsample32<St, true>(rM, bcell32<E>(x, y, z, hx, hy, hz, nx, ny, nz));
+        const float is = bsample32<St, true>(rS, bcell32<E>(x, y, z, -hx, -hy, -hz, nx, ny, nz));
         St::store(rD, im - is, o, 0);
         StF32::store(rP, im + is, (4u / E) * o, 0);
     }
