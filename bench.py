@@ -682,7 +682,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--latency-steps", type=int, default=10,
+    ap.add_argument("--latency-steps", type=int, default=20,
                     help="sequential steps for the latency and for the roofline pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gt", action="store_true", help="skip the ground-truth error pass (profiling runs)")
@@ -967,7 +967,7 @@ def main():
                    "smoothing_z_depths_finest_first": depths},
         "latency_ms": {"p50": float(np.percentile(lats, 50)) if compare else None,
                        "p99": float(np.percentile(lats, 99)) if compare else None,
-                       "per_setting_p50": per_var, "alone": True,
+                       "per_setting_p50": per_var, "alone": True, "samples": int(lats.size) if compare else 0,
                        "step_p50": float(np.percentile(step_ms, 50)), "step_p99": float(np.percentile(step_ms, 99))},
         "streams": streams_res,
         "batch_graphs": graphs_res,
