@@ -709,6 +709,8 @@ def main():
                     help="serve: registrations a pool slot may run as one lockstep batch (1: one by one)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain device copies of known size (counter calibration)")
+    ap.add_argument("--barrier-probe", action="store_true",
+                    help="only run the grid-barrier probe (the cost of the barrier a persistent kernel would need)")
     ap.add_argument("--profile-run", action="store_true",
                     help="batch steps and the roofline pass only (no stream or sequential comparison, no "
                          "ground truth, no CPU baseline), so a kernel trace holds the launches the roofline times")
@@ -717,6 +719,13 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only: independent registrations shard by pair, "
                                    "and a single volume is not split across GPUs; use --gpus 1"}))
         sys.exit(2)
+
+    if args.barrier_probe:
+        import subprocess
+        from paper_0909_0928_amd import build as hip_build
+        if not os.path.exists(hip_build.PROBE):
+            sys.exit(f"{hip_build.PROBE} missing; build it with python -m paper_0909_0928_amd.build")
+        sys.exit(subprocess.run([hip_build.PROBE]).returncode)
 
     import torch
     if args.study_storage:

@@ -14,6 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdemons.so")
+PROBE = os.path.join(PKG, "probe_grid_barrier")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["k_pyramid.hip", "k_force.hip", "k_smooth.hip", "abi.hip", "pool.hip"]
 ARCH = "gfx950"
@@ -45,8 +46,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the grid-barrier probe of bench.py --barrier-probe (a separate program)
+    cmd = [HIPCC, *FLAGS, "-o", PROBE, os.path.join(CSRC, "probe_grid_barrier.hip")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for probe_grid_barrier.hip:\n{r.stdout}\n{r.stderr}")
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PROBE}")
     return LIB
 
 
