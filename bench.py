@@ -127,11 +127,11 @@ def launch_units(kernel, shape, iters, n_ic, n_active_like, n_settings, level=No
     return None
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, record=None):
     """HBM bytes per launch of `kernel` from the committed counter record
-    (profiles/<kernel>_traffic.json), or None when the record is missing or
-    was taken on different kernel sources."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"{kernel}_traffic.json")
+    (profiles/<kernel>_traffic.json, or `record`), or None when the record is
+    missing or was taken on different kernel sources."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", record or f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None, None
     from paper_0909_0928_amd import profile_summary as PS
@@ -626,6 +626,8 @@ def serve(args):
 
 HBM_SHAPE = (512, 512, 160)
 HBM_ITERS = [100, 100, 50, 25]
+# counter record of the finest-level force launches at HBM_SHAPE
+HBM_TRAFFIC_RECORD = "force_traffic_512x512x160.json"
 
 
 def hbm_roofline(args):
@@ -669,8 +671,11 @@ def hbm_roofline(args):
         tot_ms += ms
     B.dir_destroy(h)
     achieved = tot_b / (tot_ms * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic("force", HBM_TRAFFIC_RECORD)
     return {"kernel": "force", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "algo_bytes_per_voxel": abpv, "per_variant": rows,
+            "traffic": traffic, "traffic_source": traffic_src,
+            "bytes_per_launch_algorithmic": abpv * n0,
             "workload": f"{HBM_SHAPE[0]}x{HBM_SHAPE[1]}x{HBM_SHAPE[2]} FP32 phantom pair (max displacement "
                         f"{STUDY_MAX_U:g} voxels), 4 levels {HBM_ITERS} coarse to fine, finest-level force launches "
                         f"of {reps} passive and {reps} inverse-consistent registrations; working set about 1.9 GB, "
@@ -709,6 +714,8 @@ def main():
                     help="serve: registrations a pool slot may run as one lockstep batch (1: one by one)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain device copies of known size (counter calibration)")
+    ap.add_argument("--hbm-roofline-only", action="store_true",
+                    help="only the 512x512x160 force-kernel roofline (for counter runs on that working set)")
     ap.add_argument("--barrier-probe", action="store_true",
                     help="only run the grid-barrier probe (the cost of the barrier a persistent kernel would need)")
     ap.add_argument("--profile-run", action="store_true",
@@ -728,6 +735,9 @@ def main():
         sys.exit(subprocess.run([hip_build.PROBE]).returncode)
 
     import torch
+    if args.hbm_roofline_only:
+        print(json.dumps(hbm_roofline(args)))
+        return
     if args.study_storage:
         storage_study(args)
         return

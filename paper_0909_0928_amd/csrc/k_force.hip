@@ -34,7 +34,8 @@ using namespace dev;
 struct Geo {
     int nx, ny, nz;
     int gxt;             // x tiles
-    int rows_per_block;  // row steps per workgroup
+    int gy;              // groups of W rows along y
+    int rows_per_block;  // row steps per workgroup: consecutive planes z of one y group
     int blocks;          // workgroups
 };
 
@@ -210,6 +211,7 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
     const Geo &q = a.geo[reg];
     const int x0 = (lid % q.gxt) * TX;
     const int rb = lid / q.gxt;
+    const int yb = rb % q.gy, zb = rb / q.gy;  // y group (fastest across workgroups), z chunk
     const int R = RC >= 0 ? RC : taps.radius;
     const int rows = q.ny * q.nz;
     const unsigned N = (unsigned)q.nx * (unsigned)rows;
@@ -226,11 +228,14 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
     double s1 = 0.0, s2 = 0.0, sse = 0.0;
 
     for (int it = 0; it < q.rows_per_block; ++it) {
-        // row index y + ny * z; the same for every lane of a wavefront
-        const int r = __builtin_amdgcn_readfirstlane((rb * q.rows_per_block + it) * W + wrow);
-        const bool row_ok = r < rows;
+        // row (y, z): the workgroup's row steps walk z, so a row's z +- 1
+        // stencil rows and the rows its gathers reach are those of its own
+        // neighbouring steps; the same for every lane of a wavefront
+        const int y = __builtin_amdgcn_readfirstlane(yb * W + wrow);
+        const int z = __builtin_amdgcn_readfirstlane(zb * q.rows_per_block + it);
+        const bool row_ok = y < q.ny && z < q.nz;
+        const int r = y + q.ny * z;
         if (row_ok) {
-            const int y = r % q.ny, z = r / q.ny;
             const unsigned rowb = ES * (unsigned)q.nx;  // bytes per row
             RowOffsets ro;
             ro.c = rowb * (unsigned)r;
@@ -350,7 +355,7 @@ __global__ void k_level_reset(LevelState *st)
 }
 
 struct ForceGrid {
-    int tx, gxt, rows_per_block;
+    int tx, gxt, gy, rows_per_block;
     int64_t blocks;
 };
 
@@ -372,12 +377,15 @@ ForceGrid force_grid(Dims d)
     g.tx = d.nx <= 64 ? 64 : (d.nx <= 128 ? 128 : (d.nx <= 256 ? 256 : 512));
     const int w = g.tx < 256 ? 256 / g.tx : 1;
     g.gxt = ceil_div(d.nx, g.tx);
-    const int64_t steps = ((int64_t)d.ny * d.nz + w - 1) / w;  // row steps of the whole volume
+    g.gy = ceil_div(d.ny, w);
+    const int64_t steps = (int64_t)g.gy * d.nz;  // row steps of the whole volume
     const int64_t target = target_force_blocks(steps * g.gxt);
     const int64_t per_tile = (target + g.gxt - 1) / g.gxt;
-    g.rows_per_block = (int)((steps + per_tile - 1) / per_tile);
+    // planes per workgroup so that the workgroups of one x tile number about per_tile
+    g.rows_per_block = (int)(((int64_t)d.nz * g.gy + per_tile - 1) / per_tile);
     if (g.rows_per_block < 1) g.rows_per_block = 1;
-    g.blocks = (int64_t)g.gxt * ((steps + g.rows_per_block - 1) / g.rows_per_block);
+    if (g.rows_per_block > d.nz) g.rows_per_block = d.nz;
+    g.blocks = (int64_t)g.gxt * g.gy * ceil_div(d.nz, g.rows_per_block);
     return g;
 }
 
@@ -442,7 +450,7 @@ hipError_t launch_force_group(Ctx &c, const ForceLaunch &f, const ForceGrid *g, 
         a.alpha2[q] = f.alpha2[r];
         a.variant[q] = f.variant == kMixedVariants ? f.variants[r] : f.variant;
         if (a.variant[q] != variant) variant = kMixedVariants;
-        a.geo[q] = Geo{f.d[r].nx, f.d[r].ny, f.d[r].nz, g[r].gxt, g[r].rows_per_block, (int)g[r].blocks};
+        a.geo[q] = Geo{f.d[r].nx, f.d[r].ny, f.d[r].nz, g[r].gxt, g[r].gy, g[r].rows_per_block, (int)g[r].blocks};
         a.first[q] = (int)total;
         total += g[r].blocks;
     }

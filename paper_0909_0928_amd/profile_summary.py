@@ -137,14 +137,20 @@ def _copy_factor(d: str, expected_kib: float) -> float:
 
 
 def traffic_summary(fetch: str, write: str, fetch_copy: str, write_copy: str, kernel: str, command: str,
-                    out: str) -> dict:
+                    out: str, largest_grid: bool = False) -> dict:
+    """largest_grid: count only the kernel's launches of the largest grid (the
+    finest level of the largest volume in the run)."""
     kib = COPY_BYTES / 1024.0
     ff = _copy_factor(fetch_copy, kib)
     wf = _copy_factor(write_copy, kib)
     sym = KERNEL_SYMBOL[kernel]
 
     def mean_kib(d):
-        v = [float(r["Counter_Value"]) for r in _counter_rows(d) if _short(r["Kernel_Name"]).startswith(sym)]
+        rows = [r for r in _counter_rows(d) if _short(r["Kernel_Name"]).startswith(sym)]
+        if largest_grid:
+            g = max(int(r["Grid_Size"]) for r in rows)
+            rows = [r for r in rows if int(r["Grid_Size"]) == g]
+        v = [float(r["Counter_Value"]) for r in rows]
         return sum(v) / len(v), len(v)
 
     fk, nf = mean_kib(fetch)
@@ -176,11 +182,12 @@ def main():
     c.add_argument("--kernel", default="force")
     c.add_argument("--command", required=True)
     c.add_argument("--out", required=True)
+    c.add_argument("--largest-grid", action="store_true", help="only the launches of the largest grid")
     a = ap.parse_args()
     if a.cmd == "trace":
         trace_summary(a.dir, a.command, a.out)
     else:
-        traffic_summary(a.fetch, a.write, a.fetch_copy, a.write_copy, a.kernel, a.command, a.out)
+        traffic_summary(a.fetch, a.write, a.fetch_copy, a.write_copy, a.kernel, a.command, a.out, a.largest_grid)
 
 
 if __name__ == "__main__":
