@@ -266,8 +266,9 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
                         const float *d_moving, const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma,
                         int32_t radius, float *d_field_out, double *sums);
 
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): dir_step
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc, code that must not allocate while other
+ * work is being captured into a HIP graph): dir_step
  * (same arguments, same kernels and launch shapes, so bitwise the same
  * d_field_out and sums, FP32 storage) with every intermediate (the
  * x-smoothed field, the pre-warped images, the per-workgroup sums, the
@@ -283,7 +284,9 @@ int32_t dir_step_stored(dir_handle *h, int32_t storage, int32_t variant, double 
  * work is enqueued.  Every call on one device shares that device's array and
  * it keeps the last call's contents (each call rewrites what it reads), so
  * calls that overlap on one device (several threads, or handles on
- * different streams) race and must be serialised by the caller.  Blocks. */
+ * different streams) race and must be serialised by the caller.  Blocks
+ * until the step is complete (it reads the sums back), so the call itself
+ * cannot be recorded into a graph. */
 #define DIR_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
 int32_t dir_step_noalloc(dir_handle *h, int32_t variant, double alpha, const float *d_static, const float *d_moving,
                          const float *d_field, int32_t nx, int32_t ny, int32_t nz, double sigma, int32_t radius,
