@@ -1635,12 +1635,6 @@ int capture_register(dir_handle *h, const RegPlan &pl, hipGraphExec_t *exec)
     return DIR_OK;
 }
 
-// Validate and enqueue one registration on the handle's stream and record it
-// as in flight.  Without a host wait inside the registration (no polled
-// stopping rule) and without kernel timing, the launches are captured once
-// into a HIP graph and the graph is replayed while the arguments and the
-// workspace stay the same; otherwise (or on the null stream, which cannot be
-// captured) they are enqueued one by one.
 // Record an enqueued plan as the handle's registration in flight.
 void note_inflight(dir_handle *h, const RegPlan &pl)
 {
@@ -1696,6 +1690,7 @@ int submit_plan(dir_handle *h, const RegPlan &pl, const dir_params *p, bool poll
     return DIR_OK;
 }
 
+// Validate one registration and submit it (submit_plan).
 int submit_register(dir_handle *h, const float *d_static, const float *d_moving, int32_t nx, int32_t ny,
                     int32_t nz, const double *spacing_mm, const dir_params *p, float *d_field_out, bool poll)
 {
