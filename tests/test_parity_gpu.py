@@ -4,7 +4,6 @@ Both sides get identical FP32-representable inputs (the oracle reads them as
 float64).  Per-step outputs must agree to a normwise relative error of 1e-5;
 whole registrations to an RMS field difference of 0.01 voxel.
 """
-import math
 import sys
 
 import numpy as np
