@@ -123,6 +123,27 @@ def test_mm_multilevel_end_to_end(B, h, pair, variant):
     assert np.allclose(hg[:3, :3], hist[:3, :3], rtol=1e-3, atol=1e-9)
 
 
+WIDE = [(100, 40, 8), (200, 36, 6), (300, 32, 6)]  # force tiles 128, 256 and 512 voxels wide
+
+
+@pytest.mark.parametrize("shape", WIDE)
+@pytest.mark.parametrize("variant", ["passive", "active", "inverse_consistent"])
+@pytest.mark.parametrize("units,sigma", [("mm", 1.5), ("voxels", 2.0)])
+def test_wide_rows_runtime_radius(B, h, variant, shape, units, sigma):
+    """The force kernels that take the smoothing radius at run time (every
+    physical-units registration; sigma 2 voxels, radius 6, in voxel units) on
+    rows wider than the other tests reach: tiles of 128, 256 and 512 voxels
+    (two per thread), three iterations against the oracle."""
+    ph = P.make_phantom(shape, seed=43, max_u=2.5, spacing_mm=SPACING)
+    S, M = f64(ph.static), f64(ph.moving)
+    got, hg, ref, hist = _both(B, h, S, M, variant, [3], sigma, units=units)
+    r = rel(got, ref)
+    _say(f"wide rows {shape} {variant} {units}: normwise {r:.2e}")
+    assert r < 3 * REL_TOL
+    assert float(np.abs(got - ref).max()) <= 30 * REL_TOL * float(np.abs(ref).max())
+    assert np.allclose(hg[:, :3], hist[:, :3], rtol=3 * REL_TOL, atol=0)
+
+
 def test_mm_unit_spacing_equals_voxel_units(B, h, pair):
     """With 1 mm voxels both units give the same registration (to rounding:
     the physical kernels take the metric as arguments)."""
