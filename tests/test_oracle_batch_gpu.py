@@ -88,13 +88,25 @@ def test_batch_against_oracle(B, cases):
 
 def test_batching_pool_against_oracle(B, cases):
     """A two-slot pool admitting up to four compatible requests per slot as a
-    lockstep batch, every request submitted before any is collected."""
+    lockstep batch.  Two long registrations (zero images, 256x256x96, 200
+    iterations: over ten milliseconds each) take both slots first, so the
+    seven cases, submitted right after them, queue and are admitted as
+    lockstep groups when the slots free."""
+    blocker = torch.zeros((96, 256, 256), dtype=torch.float32, device="cuda")
+    slow = B.make_params("passive", [100, 100], sigma=1.5)
+    args = [(_dev(c["S"]), _dev(c["M"]), _params(B, c)) for c in cases]
+    torch.cuda.synchronize()
     with B.Pool(slots=2, max_bytes=0, max_batch=4) as pool:
-        tickets = [pool.submit(_dev(c["S"]), _dev(c["M"]), _params(B, c)) for c in cases]
+        long_tickets = [pool.submit(blocker, blocker, slow) for _ in range(2)]
+        tickets = [pool.submit(*a) for a in args]
         for c, t in zip(cases, tickets):
             f, st = pool.wait(t)
             _check(c, f, st, "pool")
-        assert pool.stats()["peak_running"] >= 2
+        for t in long_tickets:
+            pool.wait(t)
+        stats = pool.stats()
+        print(f"pool peak running {stats['peak_running']}", flush=True)
+        assert stats["peak_running"] >= 4  # a group of four ran as one lockstep batch
 
 
 def test_concurrent_async_against_oracle(B, cases):
