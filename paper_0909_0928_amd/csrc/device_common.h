@@ -158,6 +158,64 @@ __device__ __forceinline__ int xcd_logical_id(int b, int nb)
     return x * per + min(x, rem) + i;
 }
 
+// Logical workgroup g of a launch over `count` registrations to (reg, lid)
+// (A: the launch's arguments, with first[] and chunk[]).  Registration r owns
+// b_r = first[r + 1] - first[r] workgroups, cut into kXCDs consecutive chunks
+// (chunk k: lids k b_r / kXCDs .. (k + 1) b_r / kXCDs - 1), and the logical
+// order runs chunk 0 of every registration, then chunk 1 of every
+// registration, and so on (chunk[k]: where chunk k starts, from the host).
+// Each XCD's contiguous range of logical ids then holds about an eighth of
+// every registration, so registrations of unequal cost (variants) spread
+// evenly over the XCDs, while a registration's neighbouring workgroups stay
+// together.  chunk[0] < 0 asks for registration-major order instead
+// (registration r from first[r]), which keeps more of a small registration
+// on one XCD.  Which rows a (reg, lid) covers, and so every result, does not
+// depend on the order.  Wave-uniform scalar work on values loaded once.
+template <class A>
+__device__ __forceinline__ void batch_slot(int g, const A &a, int &reg, int &lid)
+{
+    reg = 0;
+    lid = g;
+    if (a.count == 1) return;
+    if (a.chunk[0] < 0) {  // registration-major order: registration r at first[r]
+        int base = 0;
+#pragma unroll
+        for (int r = 1; r < kMaxBatch; ++r)
+            if (r < a.count && g >= a.first[r]) {
+                reg = r;
+                base = a.first[r];
+            }
+        lid = g - base;
+        return;
+    }
+    int b[kMaxBatch];
+#pragma unroll
+    for (int r = 0; r < kMaxBatch; ++r) b[r] = r < a.count ? a.first[r + 1] - a.first[r] : 0;
+    int k = 0, base = 0;
+#pragma unroll
+    for (int j = 1; j < kXCDs; ++j)
+        if (g >= a.chunk[j]) {
+            k = j;
+            base = a.chunk[j];
+        }
+    unsigned off = (unsigned)(g - base);
+    bool found = false;
+#pragma unroll
+    for (int r = 0; r < kMaxBatch; ++r) {
+        const unsigned lo = ((unsigned)k * (unsigned)b[r]) / kXCDs;
+        const unsigned n = ((unsigned)(k + 1) * (unsigned)b[r]) / kXCDs - lo;
+        if (!found) {
+            if (off < n) {
+                reg = r;
+                lid = (int)(lo + off);
+                found = true;
+            } else {
+                off -= n;
+            }
+        }
+    }
+}
+
 // Raw buffer access: the resource (base, size in bytes) lives in scalar
 // registers, a per-lane byte offset in one VGPR and a wave-uniform byte offset
 // in an SGPR, so addressing costs no 64-bit vector arithmetic.  Offsets past
@@ -600,6 +658,30 @@ __device__ __forceinline__ void reduce_sums(const double *__restrict__ partials,
 // host-side launch helpers
 // ---------------------------------------------------------------------------
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// chunk[] of batch_slot for a launch whose registration r owns
+// first[r + 1] - first[r] workgroups: the chunk starts of the interleaved
+// order when every registration has at least kInterleaveMinBlocks
+// workgroups, else registration-major order.  Measured in the six-setting
+// batch at 256x256x100: interleaving took the 128x128x50 force launches
+// from 47.3 to 45.6 us and the mixed pre-warp from 25.0 to 21.6 us (1,600
+// and 3,200 workgroups per registration), but the 64x64x25 force launch
+// from 13.0 to 14.8 us (400 per registration).
+constexpr int kInterleaveMinBlocks = 1024;
+
+inline void batch_chunks(const int *first, int count, int *chunk)
+{
+    for (int r = 0; r < count; ++r)
+        if (first[r + 1] - first[r] < kInterleaveMinBlocks) {
+            chunk[0] = -1;
+            return;
+        }
+    for (int k = 0; k < dev::kXCDs; ++k) {
+        unsigned s = 0;
+        for (int r = 0; r < count; ++r) s += ((unsigned)k * (unsigned)(first[r + 1] - first[r])) / dev::kXCDs;
+        chunk[k] = (int)s;
+    }
+}
 
 struct Grid2 {
     int gx, gy;

@@ -29,7 +29,8 @@ using namespace dev;
 // StBF16); the pointers are untyped.  One launch serves `count` registrations
 // (a lockstep batch; 1 outside batches), possibly of different sizes with the
 // same tile width TX: per-registration arguments are arrays indexed by
-// registration, and each registration has its own range of workgroups.
+// registration, and each registration has its own set of workgroups
+// (interleaved over the XCDs by batch_slot).
 // Volume size and workgroup layout of one registration of a launch.
 struct Geo {
     int nx, ny, nz;
@@ -48,7 +49,8 @@ struct ForceArgs {
     float alpha2[kMaxBatch];
     int variant[kMaxBatch];         // read by the mixed-variant instance only
     Geo geo[kMaxBatch];
-    int first[kMaxBatch + 1];       // logical workgroups of registration r: first[r] .. first[r + 1] - 1
+    int first[kMaxBatch + 1];       // registration r has first[r + 1] - first[r] workgroups (order: batch_slot)
+    int chunk[kXCDs];               // logical start of chunk k (batch_slot)
     int count;
     int n;                          // iteration index within the level
     Metric metric;                  // physical units (instances with MM = true only)
@@ -312,17 +314,15 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
 }
 
 // One workgroup of a force launch.  Logical workgroup ids (XCD-contiguous)
-// run registration by registration (first[]); V = kMixedVariants takes each
+// map to (registration, workgroup) by batch_slot; V = kMixedVariants takes each
 // registration's variant from the arguments (a uniform branch per workgroup).
 template <int V, int TX, int RC, class St, bool MM>
 __global__ __launch_bounds__(256) void k_force_x(ForceArgs a, GaussTaps taps)
 {
     __shared__ typename ForceTile<TX>::Rows ul;
     __shared__ float wl[2 * kMaxRadius + 1];  // taps, read as LDS broadcasts
-    const int g = xcd_logical_id(blockIdx.x, gridDim.x);
-    int reg = 0;  // wave-uniform
-    while (reg + 1 < a.count && g >= a.first[reg + 1]) ++reg;
-    const int lid = g - a.first[reg];
+    int reg, lid;  // wave-uniform
+    batch_slot(xcd_logical_id(blockIdx.x, gridDim.x), a, reg, lid);
     if (a.stop_at[reg] && *a.stop_at[reg] < a.n) return;
     if (threadIdx.x <= 2 * kMaxRadius) wl[threadIdx.x] = taps.w[threadIdx.x];  // ordered before use by the row barrier
     if constexpr (V != kMixedVariants) {
@@ -455,6 +455,7 @@ hipError_t launch_force_group(Ctx &c, const ForceLaunch &f, const ForceGrid *g, 
         total += g[r].blocks;
     }
     a.first[k] = (int)total;
+    batch_chunks(a.first, k, a.chunk);
     a.count = k;
     a.n = f.n;
     const bool mm = f.metric != nullptr;

@@ -103,15 +103,17 @@ struct PlaneGeo {
 
 // Pre-warp of one iteration for `count` registrations (a lockstep batch; 1
 // outside batches), possibly of different sizes: per-registration arguments
-// are arrays indexed by registration, and each registration has its own range
-// of 64 x 4 workgroups (one per x tile, y tile and z plane).
+// are arrays indexed by registration, and each registration has its own set
+// of 64 x 4 workgroups (one per x tile, y tile and z plane; interleaved over
+// the XCDs by batch_slot).
 struct PrewarpArgs {
     const void *M[kMaxBatch], *S[kMaxBatch], *v[kMaxBatch];
     void *D[kMaxBatch], *P[kMaxBatch];
     const int *stop_at[kMaxBatch];  // skip when *stop_at < n (NULL: never)
     int kind[kMaxBatch];            // read by the mixed instance only
     PlaneGeo geo[kMaxBatch];
-    int first[kMaxBatch + 1];       // logical workgroups of registration r: first[r] .. first[r + 1] - 1
+    int first[kMaxBatch + 1];       // registration r has first[r + 1] - first[r] workgroups (order: batch_slot)
+    int chunk[kXCDs];               // logical start of chunk k (batch_slot)
     int count;
     int n;
 };
@@ -175,10 +177,8 @@ __device__ __forceinline__ void warp_pair_at(const PrewarpArgs &a, int r, int x,
 // or once the registration's level has stopped.
 __device__ __forceinline__ bool prewarp_voxel(const PrewarpArgs &a, int &r, int &x, int &y, int &z)
 {
-    const int g = xcd_logical_id(blockIdx.x, gridDim.x);
-    r = 0;  // wave-uniform
-    while (r + 1 < a.count && g >= a.first[r + 1]) ++r;
-    const int lb = g - a.first[r];
+    int lb;  // wave-uniform
+    batch_slot(xcd_logical_id(blockIdx.x, gridDim.x), a, r, lb);
     if (a.stop_at[r] && *a.stop_at[r] < a.n) return false;
     const PlaneGeo &t = a.geo[r];
     const int q = lb / t.gx;
@@ -416,6 +416,7 @@ hipError_t launch_prewarp(Ctx &c, const PrewarpLaunch &w)
         a.kind[r] = w.kind == kPrewarpMixed ? w.kinds[r] : w.kind;
     }
     a.first[w.count] = (int)total;
+    batch_chunks(a.first, w.count, a.chunk);
     a.count = w.count;
     a.n = w.n;
     const dim3 grid((unsigned)total), block(kBlockX, kBlockY);
