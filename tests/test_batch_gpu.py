@@ -258,6 +258,20 @@ def test_batch_levels_on_concurrent_streams(B, h, storage, shapes, iters):
         _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
 
 
+def test_interleaved_lockstep_order_equals_alone(B, h):
+    """Four FP32 registrations of 256x256x100 with different force variants
+    and both pre-warp kinds: their 128x128x50 level runs in lockstep with at
+    least 1,024 force and pre-warp workgroups per registration, so those
+    launches take the order that interleaves the registrations over the XCDs;
+    fields and every FP64 sum stay bitwise those of each registration alone."""
+    pairs = _pairs((256, 256, 100), 2, 990)
+    pairs = pairs + pairs
+    names = [("passive", 1.0), ("inverse_consistent", 1.0), ("double", 0.4), ("active", 1.0)]
+    params = [B.make_params(v, [4, 3, 1], sigma=1.5, alpha=a) for v, a in names]
+    alone = _alone(B, h, pairs, params)
+    _check_equal(B.dir_register_batch(h, [S for S, _ in pairs], [M for _, M in pairs], params), alone)
+
+
 def test_batch_timing_counts_launches_per_tile_class_and_lane(B):
     # per-kernel timing on a batch: one force launch per tile class and
     # iteration on the lockstep level, one per registration and iteration on
