@@ -78,6 +78,36 @@ __device__ __forceinline__ void cdiff(__amdgpu_buffer_rsrc_t I, const LaneOffset
     gz = (MM ? m.gs[2] : 0.5f) * (St::load(I, lo.c, ro.zp) - St::load(I, lo.c, ro.zm));
 }
 
+// Values of one volume along a lane's column carried from a row step to the
+// next (row steps walk z): the centre and the z + 1 neighbour of the last
+// step are the z - 1 neighbour and the centre of this one.
+struct ZCarry {
+    float c, zp;
+};
+
+// cdiff that also yields the centre: with `carry` (the previous row step was
+// plane z - 1 of the same column) z - 1 and the centre come from zc, else
+// they are loaded; zc receives this step's centre and z + 1 value.  The
+// loaded values and the arithmetic are those of cdiff.
+template <class St, bool MM>
+__device__ __forceinline__ void cdiff_carry(__amdgpu_buffer_rsrc_t I, const LaneOffsets &lo, const RowOffsets &ro,
+                                            const Metric &m, bool carry, ZCarry &zc, float &gx, float &gy,
+                                            float &gz)
+{
+    float zm;
+    if (carry) {
+        zm = zc.c;
+        zc.c = zc.zp;
+    } else {
+        zm = St::load(I, lo.c, ro.zm);
+        zc.c = St::load(I, lo.c, ro.c);
+    }
+    gx = (MM ? m.gs[0] : 0.5f) * (St::load(I, lo.xp, ro.c) - St::load(I, lo.xm, ro.c));
+    gy = (MM ? m.gs[1] : 0.5f) * (St::load(I, lo.c, ro.yp) - St::load(I, lo.c, ro.ym));
+    zc.zp = St::load(I, lo.c, ro.zp);
+    gz = (MM ? m.gs[2] : 0.5f) * (zc.zp - zm);
+}
+
 // Hardware square root and reciprocal (about 1 ulp): the force's parity
 // tolerance is 1e-5 and the norms only feed FP64 sums.
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -190,6 +220,64 @@ __device__ __forceinline__ void force_point(const Geo &q, float alpha2, const Bu
     d2 = D64 * D64;
 }
 
+// force_point for the forces whose stencils are carried in z (active and
+// double: S and D; inverse-consistent: P): the same loaded values and the
+// same arithmetic, with cs (S) and cd (D, or P) holding the lane's column
+// from the previous row step when `carry`.
+template <int V, class St, bool MM>
+__device__ __forceinline__ void force_point_carry(const Geo &q, float alpha2, const Bufs &b, int x, const RowOffsets &ro,
+                                                  unsigned nbytes, const Metric &m, bool carry, ZCarry &cs,
+                                                  ZCarry &cd, float &u0, float &u1, float &u2, double &adr,
+                                                  double &av, double &d2)
+{
+    static_assert(V == kActive || V == kDouble || V == kInverseConsistent, "carried stencils");
+    constexpr unsigned ES = St::kBytes;
+    LaneOffsets lo;
+    lo.c = ES * (unsigned)x;
+    lo.xm = ES * (unsigned)max(x - 1, 0);
+    lo.xp = ES * (unsigned)min(x + 1, q.nx - 1);
+    const float vx = St::load(b.v, lo.c, ro.c), vy = St::load(b.v, lo.c, ro.c + nbytes),
+                vz = St::load(b.v, lo.c, ro.c + 2u * nbytes);
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    double D64;  // from the pre-warp kernel
+    if constexpr (V == kInverseConsistent) {
+        D64 = (double)St::load(b.Dd, lo.c, ro.c);
+        constexpr unsigned K4 = 4u / ES;  // P is FP32 in every format
+        const LaneOffsets l4{K4 * lo.c, K4 * lo.xm, K4 * lo.xp};
+        const RowOffsets r4{K4 * ro.c, K4 * ro.ym, K4 * ro.yp, K4 * ro.zm, K4 * ro.zp};
+        float gx, gy, gz;
+        cdiff_carry<StF32, MM>(b.P, l4, r4, m, carry, cd, gx, gy, gz);
+        dterm((float)D64, gx, gy, gz, alpha2, fx, fy, fz);  // Eq 6
+    } else {
+        float sx, sy, sz, dx, dy, dz, bx, by, bz;
+        cdiff_carry<St, MM>(b.S, lo, ro, m, carry, cs, sx, sy, sz);
+        cdiff_carry<St, MM>(b.Dd, lo, ro, m, carry, cd, dx, dy, dz);
+        D64 = (double)cd.c;
+        const float D = (float)D64;
+        if (V == kDouble) dterm(D, sx, sy, sz, alpha2, fx, fy, fz);  // Eq 1
+        dterm(D, dx + sx, dy + sy, dz + sz, alpha2, bx, by, bz);    // Eq 3: grad Im = grad (Im - S) + grad S
+        fx += bx;
+        fy += by;
+        fz += bz;
+    }
+    if (MM) {
+        fx *= m.os[0];
+        fy *= m.os[1];
+        fz *= m.os[2];
+    }
+    u0 = vx + fx;
+    u1 = vy + fy;
+    u2 = vz + fz;
+    if (MM) {
+        adr = (double)fast_sqrt(fmaf(m.nw[0] * fx, fx, fmaf(m.nw[1] * fy, fy, m.nw[2] * fz * fz)));
+        av = (double)fast_sqrt(fmaf(m.nw[0] * vx, vx, fmaf(m.nw[1] * vy, vy, m.nw[2] * vz * vz)));
+    } else {
+        adr = (double)fast_sqrt(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+        av = (double)fast_sqrt(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    }
+    d2 = D64 * D64;
+}
+
 // Rows in flight per workgroup and the LDS row buffer of a TX-wide tile.
 template <int TX>
 struct ForceTile {
@@ -228,6 +316,17 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
     b.P = make_rsrc(a.P[reg], 4u * N);  // FP32 in every format
     b.out = make_rsrc(a.out[reg], 3u * nbytes);
     double s1 = 0.0, s2 = 0.0, sse = 0.0;
+    // The first TX / LANES points of a lane in each row step (all of them
+    // unless a row spans several tiles, whose inner halos add up to 2R
+    // points) carry their columns' values in z to the next row step: with
+    // FP32 storage, for the forces that read two stencils (active, double)
+    // or the FP32 sum P (inverse-consistent).  Measured at 512x512x160, the
+    // carry took active and double from 314 to 296 us and IC from 279 to
+    // 273 us; it left passive unchanged, and for 16-bit storage its registers
+    // cost occupancy (passive F16 276 -> 290 us, IC F16 188 -> 203 us).
+    constexpr bool CARRY = ES == 4 && (V == kActive || V == kDouble || V == kInverseConsistent);
+    constexpr int SLOTS = TX / LANES;
+    ZCarry cs[SLOTS], cd[SLOTS];
 
     for (int it = 0; it < q.rows_per_block; ++it) {
         // row (y, z): the workgroup's row steps walk z, so a row's z +- 1
@@ -249,11 +348,7 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
             // the row: a halo slot beyond a row end holds the end voxel's u
             // (clamped index), so the end lanes copy theirs there instead.
             const int p_lo = max(R - x0, 0), p_hi = min(TX + 2 * R, q.nx - x0 + R);
-            for (int p = p_lo + lane; p < p_hi; p += LANES) {
-                const int xx = x0 - R + p;  // in [0, nx)
-                float u0, u1, u2;
-                double adr, av, d2;
-                force_point<V, St, MM>(q, alpha2, b, xx, y, z, ro, nbytes, a.metric, u0, u1, u2, adr, av, d2);
+            auto emit = [&](int p, int xx, float u0, float u1, float u2, double adr, double av, double d2) {
                 ul[0][wrow][p] = u0;
                 ul[1][wrow][p] = u1;
                 ul[2][wrow][p] = u2;
@@ -275,6 +370,36 @@ __device__ __forceinline__ void force_rows(const ForceArgs &a, const GaussTaps &
                     s1 += adr;
                     s2 += av;
                     sse += d2;
+                }
+            };
+            if constexpr (CARRY) {
+#pragma unroll
+                for (int j = 0; j < SLOTS; ++j) {
+                    const int p = p_lo + lane + j * LANES;
+                    if (p >= p_hi) break;
+                    const int xx = x0 - R + p;  // in [0, nx)
+                    float u0, u1, u2;
+                    double adr, av, d2;
+                    force_point_carry<V, St, MM>(q, alpha2, b, xx, ro, nbytes, a.metric, it > 0, cs[j], cd[j], u0, u1,
+                                                 u2, adr, av, d2);
+                    emit(p, xx, u0, u1, u2, adr, av, d2);
+                }
+                for (int p = p_lo + lane + SLOTS * LANES; p < p_hi; p += LANES) {  // inner-halo points
+                    const int xx = x0 - R + p;
+                    float u0, u1, u2;
+                    double adr, av, d2;
+                    ZCarry ns, nd;
+                    force_point_carry<V, St, MM>(q, alpha2, b, xx, ro, nbytes, a.metric, false, ns, nd, u0, u1, u2,
+                                                 adr, av, d2);
+                    emit(p, xx, u0, u1, u2, adr, av, d2);
+                }
+            } else {
+                for (int p = p_lo + lane; p < p_hi; p += LANES) {
+                    const int xx = x0 - R + p;  // in [0, nx)
+                    float u0, u1, u2;
+                    double adr, av, d2;
+                    force_point<V, St, MM>(q, alpha2, b, xx, y, z, ro, nbytes, a.metric, u0, u1, u2, adr, av, d2);
+                    emit(p, xx, u0, u1, u2, adr, av, d2);
                 }
             }
         }
