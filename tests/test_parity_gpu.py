@@ -237,6 +237,29 @@ def test_step(B, h, shape3, variant, sigma, radius):
         assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
 
 
+# (nz, ny, nx): force workgroups of two row steps (the stencil values carried
+# from one step to the next) with a one-plane last z chunk, on 512-, 256- and
+# three 512-voxel tiles (inner-halo points, which carry nothing)
+CARRY_SHAPES = [(37, 200, 300), (61, 160, 130), (23, 64, 1030)]
+
+
+@pytest.mark.parametrize("shape3", CARRY_SHAPES)
+@pytest.mark.parametrize("variant,alpha", [("active", 1.0), ("double", 0.4), ("inverse_consistent", 1.0)])
+def test_step_carried_stencils(B, h, shape3, variant, alpha):
+    """One iteration of the forces whose z-stencil values a lane carries
+    between row steps, against the oracle (field and sums)."""
+    S, M, v = _pair(shape3, 15)
+    out, sums_gpu = B.dir_step(h, variant, alpha, dev(S), dev(M), dev(v), 1.5, 5)
+    u_ref, sums_ref = O.force(O.VARIANTS[variant], S, M, v, alpha=alpha)
+    ref = O.smooth(u_ref, 1.5, 5)
+    extra = None
+    if variant == "inverse_consistent":
+        extra = O.smooth(ic_force_rounding_bound(S, M, v, alpha), 1.5, 5)
+    assert_close(host(out) - v, ref - v, extra=extra)
+    for k in range(3):
+        assert abs(sums_gpu[k] - sums_ref[k]) <= REL_TOL * abs(sums_ref[k]) + 1e-12
+
+
 @pytest.mark.parametrize("shape3", [(3, 4, 5), (2, 3, 40), (1, 2, 257)])
 @pytest.mark.parametrize("variant", ["passive", "inverse_consistent"])
 def test_step_widest_radius(B, h, shape3, variant):
