@@ -484,15 +484,17 @@ struct ForceGrid {
     int64_t blocks;
 };
 
-// Workgroups per launch to aim for: half the row steps, within [1024, 8192].
+// Workgroups per launch to aim for: half the row steps, within [256, 8192].
 // Measured at 256x256x100 (and its pyramid): 25,600 row steps run best as
 // 6,400 workgroups of 4 steps and 3,200 as 1,600 of 2 (10% faster than one
-// step each); small levels keep one step per workgroup.  The bound also
-// caps the number of sum slots.
+// step each).  Since a lane carries its z-stencil values from step to step,
+// the 400 row steps of a 64x64x25 level also run faster as 200 workgroups of
+// 2 than as 400 of 1 (the six-setting batch's launch: 13.2-13.8 -> 11.9-12.1
+// us).  The bound also caps the number of sum slots.
 int64_t target_force_blocks(int64_t steps)
 {
     const int64_t t = steps / 2;
-    return t < 1024 ? 1024 : (t > 8192 ? 8192 : t);
+    return t < 256 ? 256 : (t > 8192 ? 8192 : t);
 }
 
 ForceGrid force_grid(Dims d)
