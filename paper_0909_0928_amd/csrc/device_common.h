@@ -664,10 +664,11 @@ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // order when every registration has at least kInterleaveMinBlocks
 // workgroups, else registration-major order.  Measured in the six-setting
 // batch at 256x256x100: interleaving took the 128x128x50 force launches
-// from 47.3 to 45.6 us and the mixed pre-warp from 25.0 to 21.6 us (1,600
-// and 3,200 workgroups per registration), but the 64x64x25 force launch
-// from 13.0 to 14.8 us (400 per registration).
-constexpr int kInterleaveMinBlocks = 1024;
+// from 47.3 to 45.6 us with 1,600 workgroups per registration (and from
+// 42.5 to 39.5 us with 800 of 4 row steps) and the mixed pre-warp from 25.0
+// to 21.6 us (3,200), but the 64x64x25 force launch from 13.0 to 14.8 us
+// (400 per registration).
+constexpr int kInterleaveMinBlocks = 512;
 
 inline void batch_chunks(const int *first, int count, int *chunk)
 {

@@ -484,16 +484,19 @@ struct ForceGrid {
     int64_t blocks;
 };
 
-// Workgroups per launch to aim for: half the row steps, within [256, 8192].
-// Measured at 256x256x100 (and its pyramid): 25,600 row steps run best as
-// 6,400 workgroups of 4 steps and 3,200 as 1,600 of 2 (10% faster than one
-// step each).  Since a lane carries its z-stencil values from step to step,
-// the 400 row steps of a 64x64x25 level also run faster as 200 workgroups of
-// 2 than as 400 of 1 (the six-setting batch's launch: 13.2-13.8 -> 11.9-12.1
-// us).  The bound also caps the number of sum slots.
+// Workgroups per launch to aim for: a quarter of the row steps, within
+// [256, 8192].  Measured at 256x256x100 (and its pyramid): 25,600 row steps
+// run best as 6,400 workgroups of 4 steps (10% faster than one step each).
+// Since a lane carries its z-stencil values from step to step, the smaller
+// levels gain from longer walks too: in the six-setting batch the 64x64x25
+// force launch (400 row steps per registration) went from 13.2-13.8 to
+// 11.9-12.1 us with 2 steps per workgroup, and the 128x128x50 one (3,200)
+// from 42.5 to 39.5 us with 4 steps (as 800 workgroups per registration,
+// in the interleaved order of batch_slot).  The bound also caps the number
+// of sum slots.
 int64_t target_force_blocks(int64_t steps)
 {
-    const int64_t t = steps / 2;
+    const int64_t t = steps / 4;
     return t < 256 ? 256 : (t > 8192 ? 8192 : t);
 }
 
