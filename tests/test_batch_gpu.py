@@ -261,7 +261,7 @@ def test_batch_levels_on_concurrent_streams(B, h, storage, shapes, iters):
 def test_interleaved_lockstep_order_equals_alone(B, h):
     """Four FP32 registrations of 256x256x100 with different force variants
     and both pre-warp kinds: their 128x128x50 level runs in lockstep with at
-    least 1,024 force and pre-warp workgroups per registration, so those
+    least 512 force and pre-warp workgroups per registration, so those
     launches take the order that interleaves the registrations over the XCDs;
     fields and every FP64 sum stay bitwise those of each registration alone."""
     pairs = _pairs((256, 256, 100), 2, 990)
